@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Throughput of exact frequent-k-mer counting on one MI355X.
+
+One step = one whole counting call (pack, Bloom screen, collect, radix sort,
+run-length compaction) over one synthetic read library already resident in
+HBM, through the C ABI entry point tk_count_device with a preallocated
+workspace.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload large|small|long_k]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "frequent k-mers/sec counted (exact) + % HBM peak; p50/p99 job latency served"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOAD_INFO = {
+    "small": dict(genome_bp=1_000_000, coverage=10, read_len=100, sub_rate=0.01, n_rate=0.0, repeats=None),
+    "large": dict(genome_bp=50_000_000, coverage=30, read_len=100, sub_rate=0.01, n_rate=0.0,
+                  repeats="20% as 5 kbp copies, 2-10 per family, 2% divergence"),
+    "long_k": dict(genome_bp=20_000_000, coverage=40, read_len=150, sub_rate=0.005, n_rate=0.001, repeats=None),
+}
+
+
+def algorithmic_bytes(n_bases: int, n_windows: int, n_collected: int, n_out: int, key_bytes: int,
+                      passes: int, screen: bool) -> dict:
+    """Bytes each stage must move (structures in HBM, one 64-byte filter
+    block per window per Bloom pass):
+      pack    : 1 B/base read + 0.375 B/base written (2-bit codes + validity bit)
+      screen  : 0.375 B/base read + 64 B read + 64 B written per window
+      collect : 0.375 B/base read + 64 B read per window + key bytes per survivor
+      sort    : 2 x key bytes per survivor per radix pass
+      compact : key bytes per survivor + (key bytes + 4) per output record
+    """
+    pack = 1.375 * n_bases
+    scr = (0.375 * n_bases + 128.0 * n_windows) if screen else 0.0
+    col = 0.375 * n_bases + (64.0 * n_windows if screen else 0.0) + key_bytes * n_collected
+    srt = 2.0 * key_bytes * passes * n_collected
+    cmp_ = key_bytes * n_collected + (key_bytes + 4) * n_out
+    return dict(pack=pack, screen=scr, collect=col, sort=srt, compact=cmp_)
+
+
+def cpu_baseline(lib, target_s: float = 12.0) -> dict:
+    """The oracle, as it stands, on a bounded prefix of the same library."""
+    import numpy as np
+    import oracle
+    n_reads = lib.n_reads
+    read_len = int(lib.offsets[1] - lib.offsets[0]) if n_reads else 1
+    # calibrate on a small prefix, then size the timed sample to ~target_s
+    probe = min(n_reads, 20_000)
+    t0 = time.perf_counter()
+    oracle.kmer_count(lib.bases[:probe * read_len], lib.offsets[:probe + 1], lib.k, lib.c)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    sample = int(min(n_reads, max(probe, probe * target_s / dt)))
+    b = lib.bases[:int(lib.offsets[sample])]
+    o = np.ascontiguousarray(lib.offsets[:sample + 1])
+    t0 = time.perf_counter()
+    res = oracle.kmer_count(b, o, lib.k, lib.c)
+    dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": res.n_windows / dt, "unit": "k-mer windows/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample} of {n_reads} reads ({res.n_windows} windows, {dt:.1f} s), "
+                      f"single-threaded on 1 of {os.cpu_count()} host cores ({cpu})"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOAD_INFO))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with measured HBM bytes per launch of the dominant kernel")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "this build has no multi-GPU path.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1305_1861_amd as tk
+    import readsim
+
+    tk.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.perf_counter()
+    lib = readsim.WORKLOADS[args.workload]()
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] generated {lib.name}: {lib.n_bases} bases, {lib.n_reads} reads in {gen_s:.1f} s",
+          file=sys.stderr, flush=True)
+    bases = torch.from_numpy(lib.bases).to(dev)
+    offsets = torch.from_numpy(lib.offsets.view(np.int64)).to(dev)
+    opts = tk.tk_default_options()
+    opts.flags = tk.TK_FLAG_TIMING
+    need = tk.tk_workspace_size(lib.n_bases, lib.n_reads, lib.k, lib.c, opts)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        tk.tk_count_device(bases, offsets, lib.k, lib.c, opts, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    stage_sum = {s: 0.0 for s in tk.STAGES}
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        r = tk.tk_count_device(bases, offsets, lib.k, lib.c, opts, workspace=ws, stream=stream)
+        lat.append(time.perf_counter() - ts)
+        for s in tk.STAGES:
+            stage_sum[s] += r.stage_ms[s]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+    stage_ms = {s: stage_sum[s] / args.steps for s in tk.STAGES}
+
+    key_bytes = 8 * r.key_words
+    model = algorithmic_bytes(lib.n_bases, r.n_windows, r.n_collected, r.n, key_bytes, r.sort_passes,
+                              lib.c >= 2)
+    dominant = max(stage_ms, key=lambda s: stage_ms[s])
+    achieved = model[dominant] / (stage_ms[dominant] * 1e-3) / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            tr = json.load(f)
+        if tr.get("stage") == dominant:
+            traffic = tr.get("bytes")
+    path_bytes = sum(model.values())
+    step_s = ms_per_step * 1e-3
+    out = {
+        "metric": METRIC,
+        "value": r.n_windows / step_s,
+        "unit": "k-mer windows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64" if r.key_words == 1 else "u128",
+        "data": "synthetic",
+        "config": {
+            "workload": lib.name,
+            **WORKLOAD_INFO[args.workload],
+            "n_reads": lib.n_reads, "n_bases": lib.n_bases, "k": lib.k, "c": lib.c,
+            "bloom_blocks": r.bloom_blocks,
+        },
+        "result": {
+            "n_windows": r.n_windows, "n_frequent": r.n, "n_collected": r.n_collected,
+            "n_distinct_collected": r.n_distinct, "n_false_pos": r.n_singletons,
+            "false_pos_rate_of_distinct": (r.n_singletons / r.n_distinct) if r.n_distinct else 0.0,
+            "sort_passes": r.sort_passes,
+        },
+        "frequent_kmers_per_s": r.n / step_s,
+        "hbm_frac_path": path_bytes / step_s / (HBM_PEAK_GBS * 1e9),
+        "model_bytes": {k: int(v) for k, v in model.items()},
+        "stage_ms": stage_ms,
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
+        "roofline": {
+            "bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(lib)
+    out["host"] = platform.node()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

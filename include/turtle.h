@@ -1,0 +1,242 @@
+/*
+ * turtle.h -- exact frequent-k-mer counting on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libturtle.so.  Every entry point returns a tk_status; errors are
+ * returned, never thrown or aborted, and outputs are left untouched on
+ * error.  A thread-local message with details is available from
+ * tk_last_error().  Calls are reentrant; calls that share a workspace or a
+ * stream are ordered by that stream.
+ *
+ * The method is the exact-count path of Roy, Bhattacharya & Schliep, "Turtle:
+ * identifying frequent k-mers with cache-efficient algorithms" (arXiv
+ * 1305.1861), §2.1:
+ *   1. k-mers are extracted from the reads, 2 bits per base, cut at every
+ *      byte that is not A/C/G/T (upper or lower case), never across reads;
+ *      a k-mer and its reverse complement are one object represented by the
+ *      numerically smaller encoding ("k-mer extraction and bit-encoding");
+ *   2. a pattern-blocked Bloom filter screens out k-mers seen only once
+ *      ("Identification of frequent k-mers with Pattern-blocked Bloom
+ *      Filter");
+ *   3. the surviving occurrences are counted by sorting and run-length
+ *      compaction instead of a hash table ("Counting frequencies with sorting
+ *      and compaction", Fig. 1, Algorithm 1).
+ *
+ * Result contract (bit-exact): every canonical k-mer whose TRUE number of
+ * occurrences is >= c, in ascending key order, with that number.  Keys:
+ *   - base codes A=0, C=1, G=2, T=3, first base most significant, so the
+ *     numeric order of keys is the lexicographic order of the k-mers;
+ *   - k in [1, 31]: one 64-bit word per key (key_words = 1);
+ *   - k in [32, 63]: two 64-bit words per key stored {hi, lo} (key_words =
+ *     2), ordered by (hi, lo).
+ * Counts are exact even for keys the Bloom screen let through by mistake:
+ * every occurrence of a candidate key is collected, so a false positive shows
+ * up with its true count 1 and is dropped (and counted in n_singletons).
+ * This replaces the paper's "+1" correction of §2.1, which assumes a key's
+ * first sighting was never a false positive.
+ *
+ * Bloom screen (used when c >= 2; c = 1 counts every window directly):
+ *   - n_blocks blocks of 64 bytes: words 0..3 are the first plane S (256
+ *     bits), words 4..7 the second plane T;
+ *   - h = fmix64(key) for one-word keys, fmix64(lo ^ fmix64(hi)) for
+ *     two-word keys (fmix64: the 64-bit finaliser of MurmurHash3);
+ *   - block = floor(h * n_blocks / 2^64);
+ *   - word w (0..3) of the block gets pattern table entry
+ *     (h >> (w * table_bits)) mod 2^table_bits, a 64-bit mask with
+ *     `bloom_bits` set bits; the table is precomputed with SplitMix64 seeded
+ *     with `bloom_seed`, entries filled in order, each drawing outputs and
+ *     taking the top six bits as a bit position, skipping repeats;
+ *   - screen pass: for each window and each word, old = atomicOr(S[w], m);
+ *     atomicOr(T[w], old & m).  A T bit therefore holds iff its position was
+ *     touched at least twice, whatever the order of the windows, so the set
+ *     of candidates is deterministic;
+ *   - collect pass: a window is collected iff all its pattern bits hold in T.
+ *     Every key seen at least twice is collected (no false negatives);
+ *   - default size: W = max(n_bases - n_reads * (k - 1), 1) estimated
+ *     windows, n_blocks = max(1, ceil(bloom_beta * W / 256)).
+ */
+#ifndef TURTLE_H
+#define TURTLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define TK_API __attribute__((visibility("default")))
+#else
+#define TK_API
+#endif
+
+typedef enum {
+    TK_OK = 0,
+    TK_EINVAL = -1,    /* bad argument: k outside [1, 63], c = 0, null
+                          pointer, decreasing offsets, workspace too small,
+                          misaligned device pointer, bad option value */
+    TK_ENOMEM = -2,    /* host or device allocation failed */
+    TK_EDEVICE = -3,   /* a HIP call failed (message in tk_last_error) */
+    TK_EOVERFLOW = -4  /* input too large: n_bases must be < 2^32 so that
+                          positions and counts fit 32 bits */
+} tk_status;
+
+/* Stages whose device time is reported when TK_FLAG_TIMING is set. */
+enum {
+    TK_STAGE_PACK = 0,     /* 2-bit packing and window validity        */
+    TK_STAGE_SCREEN = 1,   /* Bloom screen pass (atomic test-and-set)  */
+    TK_STAGE_COLLECT = 2,  /* Bloom collect pass (append survivors)    */
+    TK_STAGE_SORT = 3,     /* LSD radix sort of the survivors          */
+    TK_STAGE_COMPACT = 4,  /* run-length compaction and threshold      */
+    TK_STAGE_COUNT = 5
+};
+
+#define TK_FLAG_TIMING 1u  /* record HIP events around each stage */
+
+typedef struct {
+    uint32_t bloom_beta;        /* first-plane bits per estimated window (4) */
+    uint32_t bloom_table_bits;  /* log2 of pattern table entries, 1..12 (10) */
+    uint32_t bloom_bits;        /* set bits per table entry, 1..16 (2)       */
+    uint32_t flags;             /* TK_FLAG_* */
+    uint64_t bloom_blocks;      /* explicit filter size in blocks; 0 = rule  */
+    uint64_t bloom_seed;        /* SplitMix64 seed of the table (1305)       */
+} tk_options;
+
+typedef struct {
+    uint64_t n;             /* records in keys/counts (count >= c)           */
+    uint32_t k;
+    uint32_t key_words;     /* 1 for k <= 31, 2 for k >= 32                  */
+    uint64_t *keys;         /* n * key_words words, ascending                */
+    uint32_t *counts;       /* n counts                                      */
+    uint64_t n_windows;     /* valid k-mer windows in the input              */
+    uint64_t n_collected;   /* occurrences passed to the sort                */
+    uint64_t n_distinct;    /* distinct keys among the collected             */
+    uint64_t n_singletons;  /* collected keys seen once (screen false
+                               positives when c >= 2)                        */
+    uint64_t n_below_c;     /* collected keys with 2 <= count < c            */
+    uint64_t bloom_blocks;  /* filter blocks used; 0 when c = 1              */
+    uint32_t sort_passes;   /* radix passes run                              */
+    uint32_t reserved;
+    double stage_ms[TK_STAGE_COUNT]; /* device time per stage when timed     */
+} tk_result;
+
+/* Fill *opts with the defaults listed in tk_options. */
+TK_API tk_status tk_default_options(tk_options *opts);
+
+/* Short text for a status code (static storage). */
+TK_API const char *tk_strerror(tk_status st);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+TK_API const char *tk_last_error(void);
+
+/*
+ * Count the k-mers of a read library held in HOST memory.
+ *   bases   : n_bases ASCII bytes, all reads concatenated (read-only);
+ *   offsets : n_reads + 1 non-decreasing values, offsets[0] = 0 and
+ *             offsets[n_reads] = n_bases; read r is bases[offsets[r] ..
+ *             offsets[r+1]) (read-only);
+ *   k       : 1..63;  c : threshold >= 1;  opts : NULL for defaults.
+ * On success *out receives a library-allocated result whose keys/counts are
+ * host arrays; release it with tk_result_free.  Device memory is allocated
+ * and freed inside the call on the current HIP device.
+ */
+TK_API tk_status tk_count(const uint8_t *bases, const uint64_t *offsets,
+                   uint64_t n_reads, int k, uint32_t c,
+                   const tk_options *opts, tk_result **out);
+
+/* Release a result returned by tk_count (NULL is ignored). */
+TK_API void tk_result_free(tk_result *res);
+
+/*
+ * Device workspace needed by tk_count_device for a library of n_bases bases
+ * and n_reads reads at this k, c and options.  The size is an upper bound
+ * that does not depend on the read contents.
+ */
+TK_API tk_status tk_workspace_size(uint64_t n_bases, uint64_t n_reads, int k,
+                            uint32_t c, const tk_options *opts,
+                            size_t *bytes);
+
+/*
+ * Count the k-mers of a read library held in DEVICE memory.
+ *   d_bases      : device pointer, n_bases bytes (16-byte alignment takes
+ *                  the vector-load path; any alignment is accepted);
+ *   d_offsets    : device pointer, n_reads + 1 uint64 as in tk_count (the
+ *                  values are trusted: offsets[n_reads] must equal n_bases
+ *                  and they must not decrease);
+ *   d_workspace  : device buffer of ws_bytes >= tk_workspace_size(...),
+ *                  256-byte aligned, owned by the caller;
+ *   stream       : hipStream_t to launch on (NULL = the null stream).
+ * On success *out is filled in: out->keys and out->counts are DEVICE
+ * pointers into the workspace (valid until the workspace is reused), the
+ * other fields are host values.  The call blocks until the result is
+ * complete on the device.  The workspace may be reused by the next call
+ * once this one has returned.
+ */
+TK_API tk_status tk_count_device(const uint8_t *d_bases, const uint64_t *d_offsets,
+                          uint64_t n_bases, uint64_t n_reads, int k,
+                          uint32_t c, const tk_options *opts,
+                          void *d_workspace, size_t ws_bytes, void *stream,
+                          tk_result *out);
+
+/*
+ * The pattern table the screen uses for these options: 2^bloom_table_bits
+ * 64-bit masks written to host array `masks` of `capacity` entries.
+ */
+TK_API tk_status tk_pattern_table(const tk_options *opts, uint64_t *masks,
+                           uint64_t capacity);
+
+/* Filter size in 64-byte blocks for a library at these options. */
+TK_API tk_status tk_bloom_blocks(uint64_t n_bases, uint64_t n_reads, int k,
+                          const tk_options *opts, uint64_t *n_blocks);
+
+/* ---------------------------------------------------------------------
+ * Stage entry points (device memory, caller's stream), used to check each
+ * kernel on its own.  All pointers are device pointers.
+ * --------------------------------------------------------------------- */
+
+/*
+ * 2-bit packing (§2.1 extraction).  packed[w] holds bases 32w..32w+31, base
+ * 32w+t in bits (63-2t, 62-2t) (first base most significant; a non-base
+ * byte packs as 0).  valid[w] bit t is set iff the k bases ending at base
+ * 32w+t lie in one read and are all A/C/G/T.  n_words = ceil(n_bases/32);
+ * packed and valid hold n_words entries; *n_windows (device, uint64)
+ * receives the number of valid windows.  d_scratch holds n_words uint32.
+ */
+TK_API tk_status tk_pack_device(const uint8_t *d_bases, const uint64_t *d_offsets,
+                         uint64_t n_bases, uint64_t n_reads, int k,
+                         uint64_t *d_packed, uint32_t *d_valid,
+                         uint32_t *d_scratch, uint64_t *d_n_windows,
+                         void *stream);
+
+/*
+ * Stable LSD radix sort of n keys of key_words 64-bit words ({hi, lo} when
+ * 2), on the low `key_bits` bits (bits above must be zero).  d_keys holds
+ * the input; d_alt is a buffer of the same size; d_scratch holds
+ * tk_sort_scratch_size(n) bytes.  *d_sorted_out (host) receives whichever
+ * of d_keys / d_alt holds the sorted keys.
+ */
+TK_API tk_status tk_sort_scratch_size(uint64_t n, int key_words, size_t *bytes);
+TK_API tk_status tk_sort_keys_device(uint64_t *d_keys, uint64_t *d_alt, uint64_t n,
+                              int key_words, int key_bits, void *d_scratch,
+                              size_t scratch_bytes, void *stream,
+                              uint64_t **d_sorted_out);
+
+/*
+ * Run-length compaction and threshold of n sorted keys (§2.1 sorting and
+ * compaction): writes the distinct keys with count >= c to d_out_keys and
+ * their counts to d_out_counts (both sized for n entries), and to *stats
+ * (host) n_out, n_distinct, n_singletons, n_below_c in that order.
+ * d_scratch holds tk_compact_scratch_size(n) bytes.
+ */
+TK_API tk_status tk_compact_scratch_size(uint64_t n, size_t *bytes);
+TK_API tk_status tk_compact_device(const uint64_t *d_keys, uint64_t n, int key_words,
+                            uint32_t c, uint64_t *d_out_keys,
+                            uint32_t *d_out_counts, void *d_scratch,
+                            size_t scratch_bytes, void *stream,
+                            uint64_t stats[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TURTLE_H */

@@ -1,0 +1,624 @@
+// C ABI of libturtle: argument checks, workspace planning and the launch
+// order of the counting path on one HIP stream.
+//
+//   pack (K1) -> screen (K2) -> collect (K3) -> [read n_collected]
+//             -> radix sort (K4) -> compact (K5) -> [read counters]
+//
+// The only host synchronisations are the two small counter reads.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "internal.hpp"
+#include "turtle.h"
+
+namespace tk {
+namespace {
+
+thread_local char g_err[512];
+
+tk_status fail(tk_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define TK_HIP(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(TK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));            \
+    } while (0)
+
+constexpr uint32_t DEF_BETA = 4, DEF_TABLE_BITS = 10, DEF_BITS = 2;
+constexpr uint64_t DEF_SEED = 1305;
+constexpr int BLOCKS_PER_CU = 16;
+
+struct Opts {
+    uint32_t beta, table_bits, bits, flags;
+    uint64_t blocks, seed;
+};
+
+tk_status resolve(const tk_options *o, Opts *r) {
+    r->beta = DEF_BETA;
+    r->table_bits = DEF_TABLE_BITS;
+    r->bits = DEF_BITS;
+    r->flags = 0;
+    r->blocks = 0;
+    r->seed = DEF_SEED;
+    if (o) {
+        if (o->bloom_beta)
+            r->beta = o->bloom_beta;
+        if (o->bloom_table_bits)
+            r->table_bits = o->bloom_table_bits;
+        if (o->bloom_bits)
+            r->bits = o->bloom_bits;
+        r->flags = o->flags;
+        r->blocks = o->bloom_blocks;
+        r->seed = o->bloom_seed ? o->bloom_seed : DEF_SEED;
+    }
+    if (r->beta > 1024)
+        return fail(TK_EINVAL, "bloom_beta %u out of range [1, 1024]", r->beta);
+    if (r->table_bits < 1 || r->table_bits > 12)
+        return fail(TK_EINVAL, "bloom_table_bits %u out of range [1, 12]", r->table_bits);
+    if (r->bits < 1 || r->bits > 16)
+        return fail(TK_EINVAL, "bloom_bits %u out of range [1, 16]", r->bits);
+    return TK_OK;
+}
+
+uint64_t splitmix64_next(uint64_t &state) {
+    uint64_t z = (state += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Pattern table: SplitMix64(seed); each entry takes the top six bits of
+// successive outputs as bit positions, skipping repeats, until it has `bits`
+// distinct positions.  Cached for the life of the process (its storage is the
+// source of asynchronous uploads).
+const std::vector<uint64_t> &pattern_table(uint64_t seed, uint32_t table_bits, uint32_t bits) {
+    static std::mutex mu;
+    static std::map<std::tuple<uint64_t, uint32_t, uint32_t>, std::vector<uint64_t>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_tuple(seed, table_bits, bits);
+    auto it = cache.find(key);
+    if (it != cache.end())
+        return it->second;
+    std::vector<uint64_t> t(size_t(1) << table_bits, 0);
+    uint64_t state = seed;
+    for (auto &m : t) {
+        uint32_t have = 0;
+        while (have < bits) {
+            const uint64_t bit = 1ull << (splitmix64_next(state) >> 58);
+            if (!(m & bit)) {
+                m |= bit;
+                ++have;
+            }
+        }
+    }
+    return cache.emplace(key, std::move(t)).first->second;
+}
+
+uint64_t bloom_blocks_for(uint64_t n_bases, uint64_t n_reads, int k, const Opts &o) {
+    if (o.blocks)
+        return o.blocks;
+    const uint64_t cut = n_reads * (uint64_t)(k - 1);
+    const uint64_t w = n_bases > cut ? n_bases - cut : 0;
+    const uint64_t est = w ? w : 1;
+    const uint64_t b = ceil_div((uint64_t)o.beta * est, 256);
+    return b ? b : 1;
+}
+
+struct Plan {
+    int k, key_words;
+    uint32_t c;
+    bool screen;
+    Opts opts;
+    uint64_t n_bases, n_reads, n_words, cap, n_blocks;
+    size_t key_bytes;
+    size_t off_ctr, off_table, off_packed, off_valid, off_starts, off_filter;
+    size_t off_keys_a, off_keys_b, off_counts, off_sort, off_compact, total;
+    size_t sort_bytes, compact_bytes;
+};
+
+tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const tk_options *o, Plan *p) {
+    if (k < 1 || k > 63)
+        return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
+    if (c == 0)
+        return fail(TK_EINVAL, "threshold c must be >= 1");
+    if (n_bases >= (1ull << 32))
+        return fail(TK_EOVERFLOW, "n_bases = %llu must be below 2^32", (unsigned long long)n_bases);
+    if (n_reads >= (1ull << 40))
+        return fail(TK_EOVERFLOW, "n_reads = %llu too large", (unsigned long long)n_reads);
+    tk_status st = resolve(o, &p->opts);
+    if (st != TK_OK)
+        return st;
+    p->k = k;
+    p->c = c;
+    p->key_words = k <= 31 ? 1 : 2;
+    p->key_bytes = 8 * (size_t)p->key_words;
+    p->screen = c >= 2;
+    p->n_bases = n_bases;
+    p->n_reads = n_reads;
+    p->n_words = ceil_div(n_bases, 32);
+    p->cap = n_bases;  // windows <= bases
+    p->n_blocks = p->screen ? bloom_blocks_for(n_bases, n_reads, k, p->opts) : 0;
+    if (p->n_blocks > (1ull << 40))
+        return fail(TK_EINVAL, "filter of %llu blocks is too large", (unsigned long long)p->n_blocks);
+    p->sort_bytes = radix_scratch_bytes(p->cap, p->key_words);
+    p->compact_bytes = compact_scratch_bytes(p->cap);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = off;
+        off = align_up(off + bytes, 256);
+        return r;
+    };
+    p->off_ctr = take(sizeof(DevCounters));
+    p->off_table = take(sizeof(uint64_t) << p->opts.table_bits);
+    p->off_packed = take(p->n_words * sizeof(uint64_t));
+    p->off_valid = take(p->n_words * sizeof(uint32_t));
+    p->off_starts = take(p->n_words * sizeof(uint32_t));
+    p->off_filter = take(p->n_blocks * 64);
+    p->off_keys_a = take(p->cap * p->key_bytes);
+    p->off_keys_b = take(p->cap * p->key_bytes);
+    p->off_counts = take(p->cap * sizeof(uint32_t));
+    p->off_sort = take(p->sort_bytes);
+    p->off_compact = take(p->compact_bytes);
+    p->total = off;
+    return TK_OK;
+}
+
+__global__ void zero_vec(uint4 *__restrict__ p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void zero_u32(uint32_t *__restrict__ p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = 0;
+}
+
+// Clears n bytes (n a multiple of 4, p 4-byte aligned) with kernels rather
+// than memset nodes, so the sequence stays safe under stream capture.
+hipError_t zero_bytes(void *p, size_t n, hipStream_t s) {
+    if (n < 4)
+        return hipSuccess;
+    uint64_t words = n / 4;
+    uint32_t *q = static_cast<uint32_t *>(p);
+    if (((uintptr_t)q & 15u) == 0 && words >= 4) {
+        const uint64_t vec = words / 4;
+        const uint64_t g = std::min<uint64_t>(ceil_div(vec, 256), 65536);
+        zero_vec<<<dim3((unsigned)g), dim3(256), 0, s>>>(reinterpret_cast<uint4 *>(q), vec);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        q += vec * 4;
+        words -= vec * 4;
+    }
+    if (!words)
+        return hipSuccess;
+    const uint64_t g = std::min<uint64_t>(ceil_div(words, 256), 65536);
+    zero_u32<<<dim3((unsigned)g), dim3(256), 0, s>>>(q, words);
+    return hipGetLastError();
+}
+
+int g_cu_cache[64];
+
+}  // namespace
+
+int device_cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+        dev = 0;
+    int *slot = dev < 64 ? &g_cu_cache[dev] : nullptr;
+    if (slot && *slot)
+        return *slot;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+        cu = 256;
+    if (slot)
+        *slot = cu;
+    return cu;
+}
+
+namespace {
+
+struct Timer {
+    bool on = false;
+    hipEvent_t ev[TK_STAGE_COUNT + 1] = {};
+    ~Timer() {
+        for (auto &e : ev)
+            if (e)
+                (void)hipEventDestroy(e);
+    }
+    tk_status init(bool enable) {
+        on = enable;
+        if (!on)
+            return TK_OK;
+        for (auto &e : ev)
+            TK_HIP(hipEventCreate(&e));
+        return TK_OK;
+    }
+    tk_status mark(int i, hipStream_t s) {
+        if (on)
+            TK_HIP(hipEventRecord(ev[i], s));
+        return TK_OK;
+    }
+    void read(double *ms) {
+        for (int i = 0; i < TK_STAGE_COUNT; i++) {
+            float t = 0.f;
+            ms[i] = (on && hipEventElapsedTime(&t, ev[i], ev[i + 1]) == hipSuccess) ? (double)t : 0.0;
+        }
+    }
+};
+
+int persistent_grid(uint64_t n_pos) {
+    const uint64_t want = ceil_div(n_pos ? n_pos : 1, 256);
+    const uint64_t cap = (uint64_t)device_cu_count() * BLOCKS_PER_CU;
+    return (int)std::min(want, cap);
+}
+
+tk_status run_count(const uint8_t *d_bases, const uint64_t *d_offsets, const Plan &p, char *ws, hipStream_t s,
+                    tk_result *out) {
+    DevCounters *ctr = reinterpret_cast<DevCounters *>(ws + p.off_ctr);
+    uint64_t *table = reinterpret_cast<uint64_t *>(ws + p.off_table);
+    uint64_t *packed = reinterpret_cast<uint64_t *>(ws + p.off_packed);
+    uint32_t *valid = reinterpret_cast<uint32_t *>(ws + p.off_valid);
+    uint32_t *starts = reinterpret_cast<uint32_t *>(ws + p.off_starts);
+    uint64_t *filter = reinterpret_cast<uint64_t *>(ws + p.off_filter);
+    uint64_t *keys_a = reinterpret_cast<uint64_t *>(ws + p.off_keys_a);
+    uint64_t *keys_b = reinterpret_cast<uint64_t *>(ws + p.off_keys_b);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(ws + p.off_counts);
+
+    Timer tm;
+    tk_status st = tm.init(p.opts.flags & TK_FLAG_TIMING);
+    if (st != TK_OK)
+        return st;
+
+    TK_HIP(zero_bytes(ctr, sizeof(DevCounters), s));
+    TK_HIP(zero_bytes(starts, p.n_words * sizeof(uint32_t), s));
+    if (p.screen) {
+        TK_HIP(zero_bytes(filter, p.n_blocks * 64, s));
+        const auto &tab = pattern_table(p.opts.seed, p.opts.table_bits, p.opts.bits);
+        TK_HIP(hipMemcpyAsync(table, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    }
+
+    if ((st = tm.mark(TK_STAGE_PACK, s)) != TK_OK)
+        return st;
+    TK_HIP(launch_pack(d_bases, d_offsets, p.n_bases, p.n_reads, p.k, packed, valid, starts, &ctr->n_windows, s));
+    if ((st = tm.mark(TK_STAGE_SCREEN, s)) != TK_OK)
+        return st;
+    BloomArgs a{packed, valid, p.n_words, p.k, table, p.opts.table_bits, p.n_blocks, filter};
+    const int grid = persistent_grid(p.n_words * 32);
+    if (p.screen)
+        TK_HIP(launch_screen(a, grid, s));
+    if ((st = tm.mark(TK_STAGE_COLLECT, s)) != TK_OK)
+        return st;
+    TK_HIP(launch_collect(a, p.screen, keys_a, p.cap, &ctr->n_collected, grid, s));
+
+    DevCounters h{};
+    TK_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
+    TK_HIP(hipStreamSynchronize(s));
+    const uint64_t n = h.n_collected;
+    if (n > p.cap)
+        return fail(TK_EDEVICE, "collected %llu keys into a buffer of %llu", (unsigned long long)n,
+                    (unsigned long long)p.cap);
+
+    if ((st = tm.mark(TK_STAGE_SORT, s)) != TK_OK)
+        return st;
+    uint64_t *sorted = nullptr;
+    int passes = 0;
+    TK_HIP(radix_sort(keys_a, keys_b, n, p.key_words, 2 * p.k, ws + p.off_sort, p.sort_bytes, s, &sorted, &passes));
+    uint64_t *out_keys = sorted == keys_a ? keys_b : keys_a;
+    if ((st = tm.mark(TK_STAGE_COMPACT, s)) != TK_OK)
+        return st;
+    TK_HIP(compact(sorted, n, p.key_words, p.c, out_keys, counts, ws + p.off_compact, p.compact_bytes, ctr, s));
+    if ((st = tm.mark(TK_STAGE_COUNT, s)) != TK_OK)
+        return st;
+    TK_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
+    TK_HIP(hipStreamSynchronize(s));
+
+    memset(out, 0, sizeof *out);
+    out->n = h.n_out;
+    out->k = (uint32_t)p.k;
+    out->key_words = (uint32_t)p.key_words;
+    out->keys = out_keys;
+    out->counts = counts;
+    out->n_windows = h.n_windows;
+    out->n_collected = h.n_collected;
+    out->n_distinct = h.n_runs;
+    out->n_singletons = h.n_single;
+    out->n_below_c = h.n_below;
+    out->bloom_blocks = p.n_blocks;
+    out->sort_passes = (uint32_t)passes;
+    tm.read(out->stage_ms);
+    return TK_OK;
+}
+
+}  // namespace
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" {
+
+tk_status tk_default_options(tk_options *opts) {
+    if (!opts)
+        return fail(TK_EINVAL, "opts is NULL");
+    memset(opts, 0, sizeof *opts);
+    opts->bloom_beta = DEF_BETA;
+    opts->bloom_table_bits = DEF_TABLE_BITS;
+    opts->bloom_bits = DEF_BITS;
+    opts->bloom_seed = DEF_SEED;
+    return TK_OK;
+}
+
+const char *tk_strerror(tk_status st) {
+    switch (st) {
+    case TK_OK: return "ok";
+    case TK_EINVAL: return "invalid argument";
+    case TK_ENOMEM: return "out of memory";
+    case TK_EDEVICE: return "device error";
+    case TK_EOVERFLOW: return "input too large";
+    }
+    return "unknown status";
+}
+
+const char *tk_last_error(void) { return g_err; }
+
+tk_status tk_workspace_size(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const tk_options *opts,
+                            size_t *bytes) {
+    if (!bytes)
+        return fail(TK_EINVAL, "bytes is NULL");
+    Plan p;
+    tk_status st = make_plan(n_bases, n_reads, k, c, opts, &p);
+    if (st != TK_OK)
+        return st;
+    *bytes = p.total;
+    return TK_OK;
+}
+
+tk_status tk_bloom_blocks(uint64_t n_bases, uint64_t n_reads, int k, const tk_options *opts, uint64_t *n_blocks) {
+    if (!n_blocks)
+        return fail(TK_EINVAL, "n_blocks is NULL");
+    if (k < 1 || k > 63)
+        return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
+    Opts o;
+    tk_status st = resolve(opts, &o);
+    if (st != TK_OK)
+        return st;
+    *n_blocks = bloom_blocks_for(n_bases, n_reads, k, o);
+    return TK_OK;
+}
+
+tk_status tk_pattern_table(const tk_options *opts, uint64_t *masks, uint64_t capacity) {
+    Opts o;
+    tk_status st = resolve(opts, &o);
+    if (st != TK_OK)
+        return st;
+    const auto &t = pattern_table(o.seed, o.table_bits, o.bits);
+    if (!masks || capacity < t.size())
+        return fail(TK_EINVAL, "pattern table needs %zu entries", t.size());
+    memcpy(masks, t.data(), t.size() * sizeof(uint64_t));
+    return TK_OK;
+}
+
+tk_status tk_count_device(const uint8_t *d_bases, const uint64_t *d_offsets, uint64_t n_bases, uint64_t n_reads,
+                          int k, uint32_t c, const tk_options *opts, void *d_workspace, size_t ws_bytes,
+                          void *stream, tk_result *out) {
+    if (!out)
+        return fail(TK_EINVAL, "out is NULL");
+    if (!d_offsets)
+        return fail(TK_EINVAL, "offsets is NULL");
+    if (n_bases && !d_bases)
+        return fail(TK_EINVAL, "bases is NULL");
+    if (!d_workspace)
+        return fail(TK_EINVAL, "workspace is NULL");
+    if ((uintptr_t)d_workspace & 255u)
+        return fail(TK_EINVAL, "workspace must be 256-byte aligned");
+    Plan p;
+    tk_status st = make_plan(n_bases, n_reads, k, c, opts, &p);
+    if (st != TK_OK)
+        return st;
+    if (ws_bytes < p.total)
+        return fail(TK_EINVAL, "workspace of %zu bytes is below the %zu needed", ws_bytes, p.total);
+    return run_count(d_bases, d_offsets, p, static_cast<char *>(d_workspace), static_cast<hipStream_t>(stream),
+                     out);
+}
+
+tk_status tk_count(const uint8_t *bases, const uint64_t *offsets, uint64_t n_reads, int k, uint32_t c,
+                   const tk_options *opts, tk_result **out) {
+    if (!out)
+        return fail(TK_EINVAL, "out is NULL");
+    if (!offsets)
+        return fail(TK_EINVAL, "offsets is NULL");
+    if (offsets[0] != 0)
+        return fail(TK_EINVAL, "offsets[0] must be 0");
+    for (uint64_t r = 0; r < n_reads; r++)
+        if (offsets[r + 1] < offsets[r])
+            return fail(TK_EINVAL, "offsets decrease at read %llu", (unsigned long long)r);
+    const uint64_t n_bases = offsets[n_reads];
+    if (n_bases && !bases)
+        return fail(TK_EINVAL, "bases is NULL");
+    Plan p;
+    tk_status st = make_plan(n_bases, n_reads, k, c, opts, &p);
+    if (st != TK_OK)
+        return st;
+
+    uint8_t *d_bases = nullptr;
+    uint64_t *d_offsets = nullptr;
+    void *d_ws = nullptr;
+    tk_result *res = nullptr;
+    hipStream_t s = nullptr;
+    auto cleanup = [&]() {
+        if (d_bases) (void)hipFree(d_bases);
+        if (d_offsets) (void)hipFree(d_offsets);
+        if (d_ws) (void)hipFree(d_ws);
+        if (s) (void)hipStreamDestroy(s);
+    };
+    auto dev_fail = [&](const char *what, hipError_t e) {
+        cleanup();
+        if (res) {
+            free(res->keys);
+            free(res->counts);
+            free(res);
+        }
+        if (e == hipErrorOutOfMemory)
+            return fail(TK_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+        return fail(TK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+        return dev_fail("hipStreamCreate", e);
+    if ((e = hipMalloc(&d_bases, n_bases ? n_bases : 1)) != hipSuccess)
+        return dev_fail("hipMalloc(bases)", e);
+    if ((e = hipMalloc(&d_offsets, (n_reads + 1) * sizeof(uint64_t))) != hipSuccess)
+        return dev_fail("hipMalloc(offsets)", e);
+    if ((e = hipMalloc(&d_ws, p.total ? p.total : 256)) != hipSuccess)
+        return dev_fail("hipMalloc(workspace)", e);
+    if (n_bases && (e = hipMemcpyAsync(d_bases, bases, n_bases, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return dev_fail("hipMemcpy(bases)", e);
+    if ((e = hipMemcpyAsync(d_offsets, offsets, (n_reads + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        return dev_fail("hipMemcpy(offsets)", e);
+
+    tk_result dev{};
+    st = run_count(d_bases, d_offsets, p, static_cast<char *>(d_ws), s, &dev);
+    if (st != TK_OK) {
+        cleanup();
+        return st;
+    }
+    res = static_cast<tk_result *>(calloc(1, sizeof(tk_result)));
+    if (!res) {
+        cleanup();
+        return fail(TK_ENOMEM, "result allocation failed");
+    }
+    *res = dev;
+    res->keys = static_cast<uint64_t *>(malloc((dev.n ? dev.n : 1) * dev.key_words * sizeof(uint64_t)));
+    res->counts = static_cast<uint32_t *>(malloc((dev.n ? dev.n : 1) * sizeof(uint32_t)));
+    if (!res->keys || !res->counts) {
+        cleanup();
+        free(res->keys);
+        free(res->counts);
+        free(res);
+        return fail(TK_ENOMEM, "result allocation failed");
+    }
+    if (dev.n) {
+        if ((e = hipMemcpyAsync(res->keys, dev.keys, dev.n * dev.key_words * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                s)) != hipSuccess)
+            return dev_fail("hipMemcpy(keys)", e);
+        if ((e = hipMemcpyAsync(res->counts, dev.counts, dev.n * sizeof(uint32_t), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess)
+            return dev_fail("hipMemcpy(counts)", e);
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return dev_fail("hipStreamSynchronize", e);
+    cleanup();
+    *out = res;
+    return TK_OK;
+}
+
+void tk_result_free(tk_result *res) {
+    if (!res)
+        return;
+    free(res->keys);
+    free(res->counts);
+    free(res);
+}
+
+tk_status tk_pack_device(const uint8_t *d_bases, const uint64_t *d_offsets, uint64_t n_bases, uint64_t n_reads,
+                         int k, uint64_t *d_packed, uint32_t *d_valid, uint32_t *d_scratch,
+                         uint64_t *d_n_windows, void *stream) {
+    if (k < 1 || k > 63)
+        return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
+    if (n_bases >= (1ull << 32))
+        return fail(TK_EOVERFLOW, "n_bases must be below 2^32");
+    if (!d_offsets || !d_n_windows || (n_bases && (!d_bases || !d_packed || !d_valid || !d_scratch)))
+        return fail(TK_EINVAL, "NULL device pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t n_words = ceil_div(n_bases, 32);
+    TK_HIP(zero_bytes(d_n_windows, 8, s));
+    if ((uintptr_t)d_n_windows & 7u || (uintptr_t)d_scratch & 3u)
+        return fail(TK_EINVAL, "misaligned device pointer");
+    TK_HIP(zero_bytes(d_scratch, n_words * 4, s));
+    TK_HIP(launch_pack(d_bases, d_offsets, n_bases, n_reads, k, d_packed, d_valid, d_scratch,
+                       reinterpret_cast<unsigned long long *>(d_n_windows), s));
+    return TK_OK;
+}
+
+tk_status tk_sort_scratch_size(uint64_t n, int key_words, size_t *bytes) {
+    if (!bytes || (key_words != 1 && key_words != 2))
+        return fail(TK_EINVAL, "bad arguments");
+    *bytes = radix_scratch_bytes(n, key_words);
+    return TK_OK;
+}
+
+tk_status tk_sort_keys_device(uint64_t *d_keys, uint64_t *d_alt, uint64_t n, int key_words, int key_bits,
+                              void *d_scratch, size_t scratch_bytes, void *stream, uint64_t **d_sorted_out) {
+    if (key_words != 1 && key_words != 2)
+        return fail(TK_EINVAL, "key_words must be 1 or 2");
+    if (key_bits < 0 || key_bits > 64 * key_words)
+        return fail(TK_EINVAL, "key_bits out of range");
+    if (!d_sorted_out || (n && (!d_keys || !d_alt || !d_scratch)))
+        return fail(TK_EINVAL, "NULL pointer");
+    if (n >= (1ull << 32))
+        return fail(TK_EOVERFLOW, "at most 2^32 - 1 keys");
+    if (scratch_bytes < radix_scratch_bytes(n, key_words))
+        return fail(TK_EINVAL, "scratch too small");
+    int passes = 0;
+    TK_HIP(radix_sort(d_keys, d_alt, n, key_words, key_bits, d_scratch, scratch_bytes,
+                      static_cast<hipStream_t>(stream), d_sorted_out, &passes));
+    return TK_OK;
+}
+
+tk_status tk_compact_scratch_size(uint64_t n, size_t *bytes) {
+    if (!bytes)
+        return fail(TK_EINVAL, "bytes is NULL");
+    *bytes = align_up(sizeof(DevCounters), 256) + compact_scratch_bytes(n);
+    return TK_OK;
+}
+
+tk_status tk_compact_device(const uint64_t *d_keys, uint64_t n, int key_words, uint32_t c, uint64_t *d_out_keys,
+                            uint32_t *d_out_counts, void *d_scratch, size_t scratch_bytes, void *stream,
+                            uint64_t stats[4]) {
+    if (key_words != 1 && key_words != 2)
+        return fail(TK_EINVAL, "key_words must be 1 or 2");
+    if (c == 0)
+        return fail(TK_EINVAL, "threshold c must be >= 1");
+    if (!stats || !d_scratch || (n && (!d_keys || !d_out_keys || !d_out_counts)))
+        return fail(TK_EINVAL, "NULL pointer");
+    if ((uintptr_t)d_scratch & 255u)
+        return fail(TK_EINVAL, "scratch must be 256-byte aligned");
+    if (n >= (1ull << 32))
+        return fail(TK_EOVERFLOW, "at most 2^32 - 1 keys");
+    const size_t head = align_up(sizeof(DevCounters), 256);
+    if (scratch_bytes < head + compact_scratch_bytes(n))
+        return fail(TK_EINVAL, "scratch too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevCounters *ctr = static_cast<DevCounters *>(d_scratch);
+    TK_HIP(zero_bytes(ctr, sizeof(DevCounters), s));
+    TK_HIP(compact(d_keys, n, key_words, c, d_out_keys, d_out_counts, static_cast<char *>(d_scratch) + head,
+                   scratch_bytes - head, ctr, s));
+    DevCounters h{};
+    TK_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
+    TK_HIP(hipStreamSynchronize(s));
+    stats[0] = h.n_out;
+    stats[1] = h.n_runs;
+    stats[2] = h.n_single;
+    stats[3] = h.n_below;
+    return TK_OK;
+}
+
+}  // extern "C"

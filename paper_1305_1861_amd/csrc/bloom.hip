@@ -1,0 +1,222 @@
+// K2 screen and K3 collect: fused canonical k-mer extraction and the
+// two-plane pattern-blocked Bloom filter.
+//
+// Paper §2.1 (Identification of frequent k-mers with Pattern-blocked Bloom
+// Filter; Algorithm 1): a key selects one block of the filter by a hash and
+// sets a precomputed pattern of bits inside it, so each test/update touches a
+// single cache line.  Paper §2.1 (k-mer extraction): the key of a window is
+// the smaller of its forward and reverse-complement encodings.
+//
+// Filter block (64 bytes, 8 words): words 0..3 = first plane S, words 4..7 =
+// second plane T.  The pattern is multiplexed from one table: word w of the
+// block gets entry (h >> (w * table_bits)) mod 2^table_bits.
+//
+// screen : for every valid window, old = atomicOr(S[w], m_w) and, for the
+//          bits that were already set, atomicOr(T[w], old & m_w).  A T bit
+//          is set iff its position was touched at least twice, in any order.
+// collect: a window is a candidate iff all its pattern bits are set in T.
+//          Candidates are appended with one atomicAdd per wave (ballot +
+//          popcount for the lane offsets).  Every key seen at least twice is
+//          a candidate.
+//
+// Threads map one-to-one onto base positions: position p = 32w + t is the
+// last base of the window handled by that lane.  A persistent grid strides
+// over the positions so the pattern table is loaded into LDS once per block.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace tk {
+namespace {
+
+constexpr int BLOOM_THREADS = 256;
+
+// Forward/reverse-complement extraction of the window ending at base p.
+// k <= 31: one-word key.
+__device__ __forceinline__ uint64_t window_key1(const uint64_t *__restrict__ packed, uint64_t w, uint32_t t, int k) {
+    const uint64_t w0 = packed[w];
+    const uint64_t w1 = w ? packed[w - 1] : 0;
+    const uint32_t s = 62 - 2 * t;  // bit of the window's last base in w0
+    const uint64_t cat = s ? (w0 >> s) | (w1 << (64 - s)) : w0;
+    const uint64_t fwd = cat & ((1ull << (2 * k)) - 1);
+    const uint64_t rc = ~group_reverse(fwd) >> (64 - 2 * k);
+    return fwd < rc ? fwd : rc;
+}
+
+// 32 <= k <= 63: two-word key {hi, lo}.
+__device__ __forceinline__ Key2 window_key2(const uint64_t *__restrict__ packed, uint64_t w, uint32_t t, int k) {
+    const uint64_t w0 = packed[w];
+    const uint64_t w1 = w ? packed[w - 1] : 0;
+    const uint64_t w2 = w > 1 ? packed[w - 2] : 0;
+    const uint32_t s = 62 - 2 * t;
+    uint64_t lo, hi;
+    if (s) {
+        lo = (w0 >> s) | (w1 << (64 - s));
+        hi = (w1 >> s) | (w2 << (64 - s));
+    } else {
+        lo = w0;
+        hi = w1;
+    }
+    const int hb = 2 * k - 64;  // bits of the key in hi, 0..62
+    hi &= (1ull << hb) - 1;
+    // reverse complement of the 2k-bit value: reverse the 64 groups of the
+    // 128-bit word, complement, shift right by 128 - 2k
+    const uint64_t a_hi = ~group_reverse(lo);
+    const uint64_t a_lo = ~group_reverse(hi);
+    const int sh = 128 - 2 * k;  // 2..64
+    uint64_t rlo, rhi;
+    if (sh == 64) {
+        rlo = a_hi;
+        rhi = 0;
+    } else {
+        rlo = (a_lo >> sh) | (a_hi << (64 - sh));
+        rhi = a_hi >> sh;
+    }
+    const bool fwd_smaller = hi < rhi || (hi == rhi && lo <= rlo);
+    return fwd_smaller ? Key2{hi, lo} : Key2{rhi, rlo};
+}
+
+template <bool TWO>
+struct KeyOf;
+template <>
+struct KeyOf<false> {
+    using type = uint64_t;
+    __device__ static uint64_t get(const uint64_t *packed, uint64_t w, uint32_t t, int k) {
+        return window_key1(packed, w, t, k);
+    }
+};
+template <>
+struct KeyOf<true> {
+    using type = Key2;
+    __device__ static Key2 get(const uint64_t *packed, uint64_t w, uint32_t t, int k) {
+        return window_key2(packed, w, t, k);
+    }
+};
+
+__device__ __forceinline__ void load_table(const uint64_t *__restrict__ table, uint32_t n, uint64_t *s_table) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+        s_table[i] = table[i];
+    __syncthreads();
+}
+
+template <bool TWO>
+__global__ __launch_bounds__(BLOOM_THREADS) void screen_kernel(BloomArgs a) {
+    extern __shared__ uint64_t s_table[];
+    const uint32_t n_tab = 1u << a.table_bits;
+    load_table(a.table, n_tab, s_table);
+    const uint64_t n_pos = a.n_words * 32;
+    const uint64_t stride = (uint64_t)gridDim.x * BLOOM_THREADS;
+    for (uint64_t p = (uint64_t)blockIdx.x * BLOOM_THREADS + threadIdx.x; p < n_pos; p += stride) {
+        const uint64_t w = p >> 5;
+        const uint32_t t = (uint32_t)p & 31u;
+        if (!((a.valid[w] >> t) & 1u))
+            continue;
+        const auto key = KeyOf<TWO>::get(a.packed, w, t, a.k);
+        const uint64_t h = key_hash(key);
+        const uint64_t blk = __umul64hi(h, a.n_blocks);
+        uint64_t *b = a.filter + blk * 8;
+        uint64_t m[4], old[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            m[i] = s_table[(h >> (i * a.table_bits)) & (n_tab - 1)];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            old[i] = __hip_atomic_fetch_or(b + i, m[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint64_t again = old[i] & m[i];
+            if (again)
+                __hip_atomic_fetch_or(b + 4 + i, again, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <bool TWO, bool SCREEN>
+__global__ __launch_bounds__(BLOOM_THREADS) void collect_kernel(BloomArgs a, typename KeyOf<TWO>::type *__restrict__ out,
+                                                                uint64_t capacity,
+                                                                unsigned long long *__restrict__ n_out) {
+    using K = typename KeyOf<TWO>::type;
+    extern __shared__ uint64_t s_table[];
+    const uint32_t n_tab = 1u << a.table_bits;
+    if (SCREEN)
+        load_table(a.table, n_tab, s_table);
+    const uint64_t n_pos = a.n_words * 32;
+    const uint64_t stride = (uint64_t)gridDim.x * BLOOM_THREADS;
+    // every lane of a block runs the same number of iterations, so the wave
+    // ballot below always sees all 64 lanes
+    const uint64_t first = (uint64_t)blockIdx.x * BLOOM_THREADS;
+    for (uint64_t base = first; base < n_pos; base += stride) {
+        const uint64_t p = base + threadIdx.x;
+        bool cand = false;
+        K key{};
+        if (p < n_pos) {
+            const uint64_t w = p >> 5;
+            const uint32_t t = (uint32_t)p & 31u;
+            if ((a.valid[w] >> t) & 1u) {
+                key = KeyOf<TWO>::get(a.packed, w, t, a.k);
+                if (SCREEN) {
+                    const uint64_t h = key_hash(key);
+                    const uint64_t blk = __umul64hi(h, a.n_blocks);
+                    const ulonglong2 *tp = reinterpret_cast<const ulonglong2 *>(a.filter + blk * 8 + 4);
+                    const ulonglong2 t01 = tp[0];
+                    const ulonglong2 t23 = tp[1];
+                    const uint64_t m0 = s_table[h & (n_tab - 1)];
+                    const uint64_t m1 = s_table[(h >> a.table_bits) & (n_tab - 1)];
+                    const uint64_t m2 = s_table[(h >> (2 * a.table_bits)) & (n_tab - 1)];
+                    const uint64_t m3 = s_table[(h >> (3 * a.table_bits)) & (n_tab - 1)];
+                    cand = ((t01.x & m0) == m0) & ((t01.y & m1) == m1) & ((t23.x & m2) == m2) &
+                           ((t23.y & m3) == m3);
+                } else {
+                    cand = true;
+                }
+            }
+        }
+        const uint64_t ball = __ballot(cand);
+        if (ball) {
+            uint64_t at = 0;
+            if (lane_id() == 0)
+                at = atomicAdd(n_out, (unsigned long long)__popcll(ball));
+            at = read_lane64(at, 0);
+            const uint64_t idx = at + __popcll(ball & lanemask_lt());
+            if (cand && idx < capacity)
+                out[idx] = key;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_screen(const BloomArgs &a, int grid, hipStream_t stream) {
+    if (a.n_words == 0)
+        return hipSuccess;
+    const size_t lds = sizeof(uint64_t) << a.table_bits;
+    if (a.k <= 31)
+        screen_kernel<false><<<dim3(grid), dim3(BLOOM_THREADS), lds, stream>>>(a);
+    else
+        screen_kernel<true><<<dim3(grid), dim3(BLOOM_THREADS), lds, stream>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_collect(const BloomArgs &a, bool screen, void *keys, uint64_t capacity,
+                          unsigned long long *n_collected, int grid, hipStream_t stream) {
+    if (a.n_words == 0)
+        return hipSuccess;
+    const size_t lds = screen ? sizeof(uint64_t) << a.table_bits : 0;
+    if (a.k <= 31) {
+        if (screen)
+            collect_kernel<false, true><<<dim3(grid), dim3(BLOOM_THREADS), lds, stream>>>(
+                a, static_cast<uint64_t *>(keys), capacity, n_collected);
+        else
+            collect_kernel<false, false><<<dim3(grid), dim3(BLOOM_THREADS), lds, stream>>>(
+                a, static_cast<uint64_t *>(keys), capacity, n_collected);
+    } else {
+        if (screen)
+            collect_kernel<true, true><<<dim3(grid), dim3(BLOOM_THREADS), lds, stream>>>(
+                a, static_cast<Key2 *>(keys), capacity, n_collected);
+        else
+            collect_kernel<true, false><<<dim3(grid), dim3(BLOOM_THREADS), lds, stream>>>(
+                a, static_cast<Key2 *>(keys), capacity, n_collected);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tk

@@ -1,0 +1,73 @@
+// Host-side launchers shared between the translation units of libturtle.
+// Every launcher enqueues work on `stream` and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tk {
+
+// Device counters of one counting call (zeroed before the call).
+struct DevCounters {
+    unsigned long long n_windows;
+    unsigned long long n_collected;
+    unsigned long long n_runs;
+    unsigned long long n_out;
+    unsigned long long n_single;
+    unsigned long long n_below;
+    unsigned long long pad[2];
+};
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---- pack.hip -------------------------------------------------------------
+// starts: n_words uint32, must be zero on entry.
+hipError_t launch_pack(const uint8_t *bases, const uint64_t *offsets, uint64_t n_bases,
+                       uint64_t n_reads, int k, uint64_t *packed, uint32_t *valid,
+                       uint32_t *starts, unsigned long long *n_windows, hipStream_t stream);
+
+// ---- bloom.hip ------------------------------------------------------------
+struct BloomArgs {
+    const uint64_t *packed;
+    const uint32_t *valid;
+    uint64_t n_words;
+    int k;
+    const uint64_t *table;  // 2^table_bits masks in device memory
+    uint32_t table_bits;
+    uint64_t n_blocks;
+    uint64_t *filter;       // n_blocks * 8 words
+};
+hipError_t launch_screen(const BloomArgs &a, int grid, hipStream_t stream);
+// screen = false collects every valid window (c = 1).
+hipError_t launch_collect(const BloomArgs &a, bool screen, void *keys, uint64_t capacity,
+                          unsigned long long *n_collected, int grid, hipStream_t stream);
+
+// ---- scan.hip -------------------------------------------------------------
+// Exclusive prefix sum of n uint32 values (in may equal out).  *total (device)
+// receives the sum.  scratch holds scan_scratch_words(n) uint32.
+uint64_t scan_scratch_words(uint64_t n);
+hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *scratch,
+                                 uint32_t *total, hipStream_t stream);
+
+// ---- radix.hip ------------------------------------------------------------
+size_t radix_scratch_bytes(uint64_t n, int key_words);
+// Sorts n keys on bits [0, key_bits); returns in *sorted which buffer holds
+// the result and in *passes the number of passes run.
+hipError_t radix_sort(uint64_t *keys, uint64_t *alt, uint64_t n, int key_words, int key_bits,
+                      void *scratch, size_t scratch_bytes, hipStream_t stream, uint64_t **sorted,
+                      int *passes);
+
+// ---- compact.hip ----------------------------------------------------------
+size_t compact_scratch_bytes(uint64_t n);
+// Run-length compaction of n sorted keys with threshold c.  Writes
+// n_runs, n_out, n_single and n_below into *ctr (device).
+hipError_t compact(const uint64_t *keys, uint64_t n, int key_words, uint32_t c, uint64_t *out_keys,
+                   uint32_t *out_counts, void *scratch, size_t scratch_bytes, DevCounters *ctr,
+                   hipStream_t stream);
+
+// Number of compute units of the current device (cached).
+int device_cu_count();
+
+}  // namespace tk

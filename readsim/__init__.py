@@ -225,6 +225,30 @@ def random_reads(seed: int, n_reads: int, min_len: int = 0, max_len: int = 120,
     return bases, offsets
 
 
+def de_bruijn(alphabet: str, n: int) -> str:
+    """Linear de Bruijn sequence B(|alphabet|, n): every length-n word over the
+    alphabet occurs exactly once (Fredricksen-Kessler-Maiorana construction,
+    plus the n - 1 wrap-around symbols)."""
+    kk = len(alphabet)
+    a = [0] * kk * n
+    seq = []
+
+    def db(t, p):
+        if t > n:
+            if n % p == 0:
+                seq.extend(a[1:p + 1])
+        else:
+            a[t] = a[t - p]
+            db(t + 1, p)
+            for j in range(a[t - p] + 1, kk):
+                a[t] = j
+                db(t + 1, t)
+
+    db(1, 1)
+    cyc = "".join(alphabet[i] for i in seq)
+    return cyc + cyc[:n - 1]
+
+
 def from_strings(reads) -> tuple[np.ndarray, np.ndarray]:
     """Pack a list of ``str``/``bytes`` reads into the (bases, offsets) layout."""
     raw = [r.encode("latin-1") if isinstance(r, str) else bytes(r) for r in reads]

@@ -1,0 +1,120 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol declared in include/turtle.h, and its host logic (options, filter size
+rule, pattern table, argument checks) agrees with the oracle's independent
+implementation of the same documented rules."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1305_1861_amd as tk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "turtle.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(tk.LIB_PATH):
+        from paper_1305_1861_amd import build
+        build.build()
+    return tk.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"TK_API\s+[\w\s\*]*?\b(tk_\w+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for want in ("tk_count", "tk_count_device", "tk_workspace_size", "tk_result_free", "tk_strerror"):
+        assert want in names
+    assert sorted(tk.exported_symbols()) == names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    raw = ctypes.CDLL(tk.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(raw, name), name
+
+
+def test_default_options(lib):
+    o = tk.tk_default_options()
+    assert (o.bloom_beta, o.bloom_table_bits, o.bloom_bits, o.bloom_seed, o.bloom_blocks) == (4, 10, 2, 1305, 0)
+
+
+def test_strerror(lib):
+    assert tk.tk_strerror(0) == "ok"
+    assert "invalid" in tk.tk_strerror(-1)
+    assert tk.tk_strerror(-4)
+
+
+def test_pattern_table_matches_oracle(oracle_lib, lib):
+    for bits, table_bits, seed in [(2, 10, 1305), (1, 4, 7), (3, 12, 99), (16, 6, 5)]:
+        got = tk.tk_pattern_table(dict(bloom_bits=bits, bloom_table_bits=table_bits, bloom_seed=seed))
+        want = oracle_lib.pattern_masks(1 << table_bits, bits, seed)
+        assert (got == want).all()
+
+
+@pytest.mark.parametrize("n_bases,n_reads,k", [(0, 0, 31), (10_000_000, 100_000, 31), (99, 1, 63),
+                                               (5, 5, 21), (1_500_000_000, 15_000_000, 31)])
+def test_bloom_size_rule_matches_oracle(oracle_lib, lib, n_bases, n_reads, k):
+    for beta in (1, 4, 7):
+        assert tk.tk_bloom_blocks(n_bases, n_reads, k, dict(bloom_beta=beta)) == \
+            oracle_lib.default_blocks(n_bases, n_reads, k, beta)
+    assert tk.tk_bloom_blocks(n_bases, n_reads, k, dict(bloom_blocks=12345)) == 12345
+
+
+def test_workspace_size_grows(lib):
+    a = tk.tk_workspace_size(1000, 10, 31, 2)
+    b = tk.tk_workspace_size(100_000, 1000, 31, 2)
+    c = tk.tk_workspace_size(100_000, 1000, 63, 2)
+    assert 0 < a < b < c
+    # c = 1 needs no filter
+    assert tk.tk_workspace_size(100_000, 1000, 31, 1) < b
+    assert tk.tk_workspace_size(0, 0, 5, 2) > 0
+
+
+@pytest.mark.parametrize("k,c", [(0, 2), (64, 2), (-3, 2), (31, 0)])
+def test_bad_arguments_rejected(lib, k, c):
+    with pytest.raises(tk.TurtleError) as e:
+        tk.tk_workspace_size(100, 1, k, c)
+    assert e.value.status == tk.TK_EINVAL
+    # the host entry point checks before touching any device
+    b = np.frombuffer(b"ACGTACGT", np.uint8).copy()
+    o = np.array([0, 8], np.uint64)
+    with pytest.raises(tk.TurtleError) as e:
+        tk.tk_count(b, o, k, c)
+    assert e.value.status == tk.TK_EINVAL
+
+
+def test_bad_offsets_rejected(lib):
+    b = np.frombuffer(b"ACGTACGT", np.uint8).copy()
+    with pytest.raises(tk.TurtleError) as e:
+        tk.tk_count(b, np.array([0, 6, 3, 8], np.uint64), 3, 2)
+    assert e.value.status == tk.TK_EINVAL and "decrease" in str(e.value)
+    with pytest.raises(tk.TurtleError) as e:
+        tk.tk_count(b, np.array([1, 8], np.uint64), 3, 2)
+    assert e.value.status == tk.TK_EINVAL
+
+
+def test_overflow_rejected(lib):
+    with pytest.raises(tk.TurtleError) as e:
+        tk.tk_workspace_size(1 << 32, 10, 31, 2)
+    assert e.value.status == tk.TK_EOVERFLOW
+
+
+def test_bad_options_rejected(lib):
+    for bad in (dict(bloom_table_bits=13), dict(bloom_bits=17), dict(bloom_beta=5000)):
+        with pytest.raises(tk.TurtleError) as e:
+            tk.tk_workspace_size(1000, 10, 31, 2, bad)
+        assert e.value.status == tk.TK_EINVAL
+
+
+def test_last_error_message(lib):
+    with pytest.raises(tk.TurtleError):
+        tk.tk_workspace_size(100, 1, 99, 2)
+    assert "k = 99" in tk.tk_last_error()

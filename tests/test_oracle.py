@@ -72,31 +72,9 @@ def test_all_a_read(oracle_lib):
             assert res.count.tolist() == [L - k + 1]
 
 
-def de_bruijn(alphabet: str, n: int) -> str:
-    """Linear de Bruijn sequence B(|alphabet|, n) (Fredricksen-Kessler-Maiorana)."""
-    kk = len(alphabet)
-    a = [0] * kk * n
-    seq = []
-
-    def db(t, p):
-        if t > n:
-            if n % p == 0:
-                seq.extend(a[1:p + 1])
-        else:
-            a[t] = a[t - p]
-            db(t + 1, p)
-            for j in range(a[t - p] + 1, kk):
-                a[t] = j
-                db(t + 1, t)
-
-    db(1, 1)
-    cyc = "".join(alphabet[i] for i in seq)
-    return cyc + cyc[:n - 1]
-
-
 @pytest.mark.parametrize("k", [2, 3, 4, 5, 6, 7])
 def test_de_bruijn_closed_form(oracle_lib, k):
-    s = de_bruijn("ACGT", k)
+    s = readsim.de_bruijn("ACGT", k)
     assert len(s) == 4 ** k + k - 1
     b, o = readsim.from_strings([s])
     res = oracle_lib.kmer_count(b, o, k, 1)
