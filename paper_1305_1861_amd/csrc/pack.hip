@@ -29,6 +29,7 @@ __device__ __forceinline__ void classify4(uint32_t x, uint32_t &codes, uint32_t 
     auto zero_bytes = [](uint32_t v) { return ~(((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v | 0x7F7F7F7Fu); };
     const uint32_t ok = zero_bytes(u ^ 0x41414141u) | zero_bytes(u ^ 0x43434343u) |
                         zero_bytes(u ^ 0x47474747u) | zero_bytes(u ^ 0x54545454u);
+    codes &= (ok >> 7) * 3u;  // a non-base byte packs as code 0
     const uint32_t nb = ~ok & 0x80808080u;
     bad4 = ((nb >> 7) & 1u) | ((nb >> 14) & 2u) | ((nb >> 21) & 4u) | ((nb >> 28) & 8u);
 }
