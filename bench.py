@@ -33,21 +33,33 @@ WORKLOAD_INFO = {
 
 
 def algorithmic_bytes(n_bases: int, n_windows: int, n_collected: int, n_out: int, key_bytes: int,
-                      passes: int, screen: bool) -> dict:
-    """Bytes each stage must move (structures in HBM, one 64-byte filter
-    block per window per Bloom pass):
+                      passes: int, screen: bool, part_bits: int) -> dict:
+    """Bytes each stage must move (the least traffic its structures need).
+
+    Global-filter path (one 64-byte filter block per window per Bloom pass):
       pack    : 1 B/base read + 0.375 B/base written (2-bit codes + validity bit)
       screen  : 0.375 B/base read + 64 B read + 64 B written per window
       collect : 0.375 B/base read + 64 B read per window + key bytes per survivor
       sort    : 2 x key bytes per survivor per radix pass
       compact : key bytes per survivor + (key bytes + 4) per output record
+    Partitioned path (filters, sort and compaction of a bucket live in LDS):
+      pack      : as above
+      partition : 0.375 B/base read + key bytes per window written, plus one
+                  read and one write of every key for the second pass (D > 10)
+      bucket    : key bytes per window read + (key bytes + 4) per record written
+      gather    : (key bytes + 4) per record read and written
     """
     pack = 1.375 * n_bases
-    scr = (0.375 * n_bases + 128.0 * n_windows) if screen else 0.0
-    col = 0.375 * n_bases + (64.0 * n_windows if screen else 0.0) + key_bytes * n_collected
-    srt = 2.0 * key_bytes * passes * n_collected
-    cmp_ = key_bytes * n_collected + (key_bytes + 4) * n_out
-    return dict(pack=pack, screen=scr, collect=col, sort=srt, compact=cmp_)
+    if part_bits < 0:
+        scr = (0.375 * n_bases + 128.0 * n_windows) if screen else 0.0
+        col = 0.375 * n_bases + (64.0 * n_windows if screen else 0.0) + key_bytes * n_collected
+        srt = 2.0 * key_bytes * passes * n_collected
+        cmp_ = key_bytes * n_collected + (key_bytes + 4) * n_out
+        return dict(pack=pack, screen=scr, collect=col, sort=srt, compact=cmp_)
+    part = 0.375 * n_bases + key_bytes * n_windows + (2.0 * key_bytes * n_windows if part_bits > 10 else 0.0)
+    bucket = key_bytes * n_windows + (key_bytes + 4) * n_out
+    gather = 2.0 * (key_bytes + 4) * n_out
+    return dict(pack=pack, partition=part, bucket=bucket, gather=gather)
 
 
 def cpu_baseline(lib, target_s: float = 12.0) -> dict:
@@ -88,6 +100,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOAD_INFO))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--global-filter", action="store_true",
+                    help="one Bloom filter in HBM for the whole library (device-scope atomics)")
     ap.add_argument("--traffic", default=None,
                     help="JSON file with measured HBM bytes per launch of the dominant kernel")
     args = ap.parse_args()
@@ -116,7 +130,7 @@ def main() -> int:
     bases = torch.from_numpy(lib.bases).to(dev)
     offsets = torch.from_numpy(lib.offsets.view(np.int64)).to(dev)
     opts = tk.tk_default_options()
-    opts.flags = tk.TK_FLAG_TIMING
+    opts.flags = tk.TK_FLAG_TIMING | (tk.TK_FLAG_GLOBAL_FILTER if args.global_filter else 0)
     need = tk.tk_workspace_size(lib.n_bases, lib.n_reads, lib.k, lib.c, opts)
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
@@ -143,8 +157,8 @@ def main() -> int:
 
     key_bytes = 8 * r.key_words
     model = algorithmic_bytes(lib.n_bases, r.n_windows, r.n_collected, r.n, key_bytes, r.sort_passes,
-                              lib.c >= 2)
-    dominant = max(stage_ms, key=lambda s: stage_ms[s])
+                              lib.c >= 2, r.part_bits)
+    dominant = max(model, key=lambda s: stage_ms.get(s, 0.0))
     achieved = model[dominant] / (stage_ms[dominant] * 1e-3) / 1e9
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
@@ -171,18 +185,19 @@ def main() -> int:
             "workload": lib.name,
             **WORKLOAD_INFO[args.workload],
             "n_reads": lib.n_reads, "n_bases": lib.n_bases, "k": lib.k, "c": lib.c,
-            "bloom_blocks": r.bloom_blocks,
+            "filter": "global" if args.global_filter else "per-bucket",
+            "bloom_blocks": r.bloom_blocks, "part_bits": r.part_bits,
         },
         "result": {
             "n_windows": r.n_windows, "n_frequent": r.n, "n_collected": r.n_collected,
             "n_distinct_collected": r.n_distinct, "n_false_pos": r.n_singletons,
             "false_pos_rate_of_distinct": (r.n_singletons / r.n_distinct) if r.n_distinct else 0.0,
-            "sort_passes": r.sort_passes,
+            "sort_passes": r.sort_passes, "n_fallback_buckets": r.n_fallback,
         },
         "frequent_kmers_per_s": r.n / step_s,
         "hbm_frac_path": path_bytes / step_s / (HBM_PEAK_GBS * 1e9),
         "model_bytes": {k: int(v) for k, v in model.items()},
-        "stage_ms": stage_ms,
+        "stage_ms": {k: v for k, v in stage_ms.items() if k in model},
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
         "roofline": {
             "bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

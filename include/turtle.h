@@ -35,6 +35,14 @@
  * first sighting was never a false positive.
  *
  * Bloom screen (used when c >= 2; c = 1 counts every window directly):
+ *   - buckets (default, partitioned path): the windows are grouped by the top
+ *     D bits of their key (2k-bit value) and every bucket has a filter of its
+ *     own, sized from its own number of windows n_s:
+ *     n_blocks = max(1, ceil(bloom_beta * n_s / 256)).  D follows the size
+ *     rule: W = max(n_bases - n_reads * (k - 1), 1), L = ceil(log2 W),
+ *     D = L - 11 for one-word keys and L - 10 for two-word keys, clamped to
+ *     [0, min(20, 2k)] (or D = part_bits when set).  With TK_FLAG_GLOBAL_FILTER
+ *     one filter covers the whole library (size rule below);
  *   - n_blocks blocks of 64 bytes: words 0..3 are the first plane S (256
  *     bits), words 4..7 the second plane T;
  *   - h = fmix64(key) for one-word keys, fmix64(lo ^ fmix64(hi)) for
@@ -51,7 +59,7 @@
  *     of candidates is deterministic;
  *   - collect pass: a window is collected iff all its pattern bits hold in T.
  *     Every key seen at least twice is collected (no false negatives);
- *   - default size: W = max(n_bases - n_reads * (k - 1), 1) estimated
+ *   - global filter size: W = max(n_bases - n_reads * (k - 1), 1) estimated
  *     windows, n_blocks = max(1, ceil(bloom_beta * W / 256)).
  */
 #ifndef TURTLE_H
@@ -81,25 +89,39 @@ typedef enum {
                           positions and counts fit 32 bits */
 } tk_status;
 
-/* Stages whose device time is reported when TK_FLAG_TIMING is set. */
+/* Stages whose device time is reported when TK_FLAG_TIMING is set.  The
+ * partitioned path (default) runs PACK, PARTITION, BUCKET, FALLBACK and
+ * GATHER; the global-filter path runs PACK, SCREEN, COLLECT, SORT, COMPACT. */
 enum {
-    TK_STAGE_PACK = 0,     /* 2-bit packing and window validity        */
-    TK_STAGE_SCREEN = 1,   /* Bloom screen pass (atomic test-and-set)  */
-    TK_STAGE_COLLECT = 2,  /* Bloom collect pass (append survivors)    */
-    TK_STAGE_SORT = 3,     /* LSD radix sort of the survivors          */
-    TK_STAGE_COMPACT = 4,  /* run-length compaction and threshold      */
-    TK_STAGE_COUNT = 5
+    TK_STAGE_PACK = 0,       /* 2-bit packing and window validity           */
+    TK_STAGE_SCREEN = 1,     /* global filter: screen pass (atomicOr)       */
+    TK_STAGE_COLLECT = 2,    /* global filter: collect pass (append)        */
+    TK_STAGE_SORT = 3,       /* global filter: LSD radix sort               */
+    TK_STAGE_COMPACT = 4,    /* global filter: run-length compaction        */
+    TK_STAGE_PARTITION = 5,  /* partitioned: radix passes on the top bits   */
+    TK_STAGE_BUCKET = 6,     /* partitioned: per-bucket screen, sort, RLE   */
+    TK_STAGE_FALLBACK = 7,   /* partitioned: buckets too large for LDS      */
+    TK_STAGE_GATHER = 8,     /* partitioned: records into final order       */
+    TK_STAGE_COUNT = 9
 };
 
-#define TK_FLAG_TIMING 1u  /* record HIP events around each stage */
+#define TK_FLAG_TIMING 1u         /* record HIP events around each stage     */
+#define TK_FLAG_GLOBAL_FILTER 2u  /* one filter for the whole library in HBM
+                                     (device-scope atomics) instead of one
+                                     filter per bucket                       */
 
 typedef struct {
-    uint32_t bloom_beta;        /* first-plane bits per estimated window (4) */
-    uint32_t bloom_table_bits;  /* log2 of pattern table entries, 1..12 (10) */
+    uint32_t bloom_beta;        /* first-plane bits per window (4); the
+                                   partitioned path accepts 1..32          */
+    uint32_t bloom_table_bits;  /* log2 of pattern table entries, 1..10 (10) */
     uint32_t bloom_bits;        /* set bits per table entry, 1..16 (2)       */
     uint32_t flags;             /* TK_FLAG_* */
-    uint64_t bloom_blocks;      /* explicit filter size in blocks; 0 = rule  */
+    uint64_t bloom_blocks;      /* global filter only: explicit size in
+                                   blocks; 0 = size rule                    */
     uint64_t bloom_seed;        /* SplitMix64 seed of the table (1305)       */
+    int32_t part_bits;          /* partitioned path: bucket bits D, 0..20;
+                                   -1 (default) = size rule                 */
+    uint32_t reserved;
 } tk_options;
 
 typedef struct {
@@ -114,9 +136,11 @@ typedef struct {
     uint64_t n_singletons;  /* collected keys seen once (screen false
                                positives when c >= 2)                        */
     uint64_t n_below_c;     /* collected keys with 2 <= count < c            */
-    uint64_t bloom_blocks;  /* filter blocks used; 0 when c = 1              */
-    uint32_t sort_passes;   /* radix passes run                              */
-    uint32_t reserved;
+    uint64_t bloom_blocks;  /* global filter: blocks used (0 when c = 1 or
+                               partitioned)                                  */
+    uint32_t sort_passes;   /* global filter: radix passes run               */
+    int32_t part_bits;      /* partitioned: bucket bits D used; -1 global    */
+    uint64_t n_fallback;    /* partitioned: buckets too large for LDS        */
     double stage_ms[TK_STAGE_COUNT]; /* device time per stage when timed     */
 } tk_result;
 
@@ -185,9 +209,13 @@ TK_API tk_status tk_count_device(const uint8_t *d_bases, const uint64_t *d_offse
 TK_API tk_status tk_pattern_table(const tk_options *opts, uint64_t *masks,
                            uint64_t capacity);
 
-/* Filter size in 64-byte blocks for a library at these options. */
+/* Global-filter size in 64-byte blocks for a library at these options. */
 TK_API tk_status tk_bloom_blocks(uint64_t n_bases, uint64_t n_reads, int k,
                           const tk_options *opts, uint64_t *n_blocks);
+
+/* Bucket bits D the partitioned path uses for a library at these options. */
+TK_API tk_status tk_part_bits(uint64_t n_bases, uint64_t n_reads, int k,
+                              const tk_options *opts, int *part_bits);
 
 /* ---------------------------------------------------------------------
  * Stage entry points (device memory, caller's stream), used to check each

@@ -74,6 +74,16 @@ def _load():
                                                 ctypes.c_uint64, ctypes.c_uint32,
                                                 ctypes.c_uint32, ctypes.c_uint64,
                                                 _u64p, _u64p, _u64p, _u8p]
+        lib.oracle_bloom_model_buckets_keys.restype = ctypes.c_int
+        lib.oracle_bloom_model_buckets_keys.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_int,
+                                                        ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32,
+                                                        ctypes.c_uint32, ctypes.c_uint64,
+                                                        _u64p, _u64p, _u64p]
+        lib.oracle_bloom_model_buckets.restype = ctypes.c_int
+        lib.oracle_bloom_model_buckets.argtypes = [_u8p, _u64p, ctypes.c_uint64, ctypes.c_int,
+                                                   ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32,
+                                                   ctypes.c_uint32, ctypes.c_uint64,
+                                                   _u64p, _u64p, _u64p]
         lib.oracle_bloom_model.restype = ctypes.c_int
         lib.oracle_bloom_model.argtypes = [_u8p, _u64p, ctypes.c_uint64, ctypes.c_int,
                                            ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
@@ -256,6 +266,52 @@ def bloom_model(bases, offsets, k: int, n_blocks: int, n_patterns: int = BLOOM_P
                                    ctypes.byref(c))
     if r != 0:
         raise ValueError(f"oracle_bloom_model: status {r}")
+    return BloomStats(int(a.value), int(bb.value), int(c.value))
+
+
+def partition_bits(n_bases: int, n_reads: int, k: int, part_bits: int = -1) -> int:
+    """Bucket bits D of the per-bucket filters (rule of the counting interface).
+
+    W = max(n_bases - n_reads * (k - 1), 1), L = ceil(log2 W); D = L - 11 for
+    one-word keys (k <= 31) and L - 10 for two-word keys, clamped to
+    [0, min(20, 2k)]; an explicit ``part_bits`` >= 0 is clamped the same way.
+    """
+    cap = min(20, 2 * k)
+    if part_bits >= 0:
+        return min(part_bits, cap)
+    w = max(n_bases - n_reads * (k - 1), 1)
+    lg = (w - 1).bit_length()
+    return max(0, min(lg - (11 if k <= 31 else 10), cap))
+
+
+def bloom_model_buckets_keys(hi, lo, k: int, D: int, beta: int = BLOOM_BETA,
+                             n_patterns: int = BLOOM_PATTERNS, n_bits: int = BLOOM_BITS,
+                             seed: int = BLOOM_SEED) -> BloomStats:
+    hi = np.ascontiguousarray(hi, dtype=np.uint64)
+    lo = np.ascontiguousarray(lo, dtype=np.uint64)
+    n = int(hi.size)
+    ih = hi if n else np.zeros(1, np.uint64)
+    il = lo if n else np.zeros(1, np.uint64)
+    a, b, c = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_uint64(0)
+    r = _load().oracle_bloom_model_buckets_keys(_p(ih, _u64p), _p(il, _u64p), n, k, D, beta,
+                                                n_patterns, n_bits, seed, ctypes.byref(a),
+                                                ctypes.byref(b), ctypes.byref(c))
+    if r != 0:
+        raise ValueError(f"oracle_bloom_model_buckets_keys: status {r}")
+    return BloomStats(int(a.value), int(b.value), int(c.value))
+
+
+def bloom_model_buckets(bases, offsets, k: int, D: int, beta: int = BLOOM_BETA,
+                        n_patterns: int = BLOOM_PATTERNS, n_bits: int = BLOOM_BITS,
+                        seed: int = BLOOM_SEED) -> BloomStats:
+    """Per-bucket Bloom model over the windows of a library."""
+    b, o, n = _reads(bases, offsets)
+    a, bb, c = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_uint64(0)
+    r = _load().oracle_bloom_model_buckets(_p(b, _u8p), _p(o, _u64p), n, k, D, beta, n_patterns,
+                                           n_bits, seed, ctypes.byref(a), ctypes.byref(bb),
+                                           ctypes.byref(c))
+    if r != 0:
+        raise ValueError(f"oracle_bloom_model_buckets: status {r}")
     return BloomStats(int(a.value), int(bb.value), int(c.value))
 
 

@@ -529,3 +529,98 @@ int oracle_bloom_model(const uint8_t *bases, const uint64_t *offsets,
     free(keys); free(hi); free(lo);
     return st;
 }
+
+/*
+ * Bloom model with one filter per bucket: a key's bucket is the top D bits of
+ * its 2k-bit value; bucket s with n_s occurrences has its own two-plane filter
+ * of max(1, ceil(beta * n_s / 256)) blocks, used only by the keys of s.  The
+ * result is the sum over buckets of oracle_bloom_model_keys.
+ */
+int oracle_bloom_model_buckets_keys(const uint64_t *hi, const uint64_t *lo,
+                                    uint64_t n, int k, int D, uint32_t beta,
+                                    uint32_t n_patterns, uint32_t n_bits,
+                                    uint64_t seed, uint64_t *n_cand_occ,
+                                    uint64_t *n_cand, uint64_t *n_cand_single)
+{
+    if (k < 1 || k > 63 || D < 0 || D > 2 * k || D > 24 || beta == 0)
+        return OR_EINVAL;
+    uint64_t n_buckets = (uint64_t)1 << D;
+    uint64_t *count = (uint64_t *)calloc(n_buckets + 1, sizeof(uint64_t));
+    uint32_t *bucket = n ? (uint32_t *)malloc(n * sizeof(uint32_t)) : NULL;
+    uint64_t *order = n ? (uint64_t *)malloc(n * sizeof(uint64_t)) : NULL;
+    uint64_t *ghi = n ? (uint64_t *)malloc(n * sizeof(uint64_t)) : NULL;
+    uint64_t *glo = n ? (uint64_t *)malloc(n * sizeof(uint64_t)) : NULL;
+    if (!count || (n && (!bucket || !order || !ghi || !glo))) {
+        free(count); free(bucket); free(order); free(ghi); free(glo);
+        return OR_ENOMEM;
+    }
+    for (uint64_t i = 0; i < n; i++) {
+        u128 key = ((u128)hi[i] << 64) | lo[i];
+        bucket[i] = D ? (uint32_t)(key >> (2 * k - D)) : 0;
+        count[bucket[i] + 1] += 1;
+    }
+    /* counting sort of the occurrences by bucket */
+    for (uint64_t b = 0; b < n_buckets; b++)
+        count[b + 1] += count[b];
+    for (uint64_t i = 0; i < n; i++)
+        order[count[bucket[i]]++] = i;
+    uint64_t start = 0;
+    *n_cand_occ = *n_cand = *n_cand_single = 0;
+    for (uint64_t b = 0; b < n_buckets; b++) {
+        uint64_t end = count[b]; /* after the placement loop count[b] = end of b */
+        uint64_t ns = end - start;
+        if (ns) {
+            for (uint64_t j = 0; j < ns; j++) {
+                ghi[j] = hi[order[start + j]];
+                glo[j] = lo[order[start + j]];
+            }
+            uint64_t blocks = ((uint64_t)beta * ns + 255) / 256;
+            if (blocks == 0)
+                blocks = 1;
+            uint64_t a = 0, c = 0, d = 0;
+            int st = oracle_bloom_model_keys(ghi, glo, ns, k > 31, blocks, n_patterns,
+                                             n_bits, seed, &a, &c, &d, NULL);
+            if (st != OR_OK) {
+                free(count); free(bucket); free(order); free(ghi); free(glo);
+                return st;
+            }
+            *n_cand_occ += a;
+            *n_cand += c;
+            *n_cand_single += d;
+        }
+        start = end;
+    }
+    free(count); free(bucket); free(order); free(ghi); free(glo);
+    return OR_OK;
+}
+
+/* The per-bucket Bloom model over the windows of a read library. */
+int oracle_bloom_model_buckets(const uint8_t *bases, const uint64_t *offsets,
+                               uint64_t n_reads, int k, int D, uint32_t beta,
+                               uint32_t n_patterns, uint32_t n_bits,
+                               uint64_t seed, uint64_t *n_cand_occ,
+                               uint64_t *n_cand, uint64_t *n_cand_single)
+{
+    int st = check_args(offsets, n_reads, k);
+    if (st != OR_OK)
+        return st;
+    u128 *keys = NULL;
+    uint64_t n = 0;
+    st = enumerate_keys(bases, offsets, n_reads, k, &keys, &n);
+    if (st != OR_OK)
+        return st;
+    uint64_t *hi = n ? (uint64_t *)malloc(n * sizeof(uint64_t)) : NULL;
+    uint64_t *lo = n ? (uint64_t *)malloc(n * sizeof(uint64_t)) : NULL;
+    if (n && (!hi || !lo)) {
+        free(keys); free(hi); free(lo);
+        return OR_ENOMEM;
+    }
+    for (uint64_t i = 0; i < n; i++) {
+        hi[i] = (uint64_t)(keys[i] >> 64);
+        lo[i] = (uint64_t)keys[i];
+    }
+    st = oracle_bloom_model_buckets_keys(hi, lo, n, k, D, beta, n_patterns, n_bits,
+                                         seed, n_cand_occ, n_cand, n_cand_single);
+    free(keys); free(hi); free(lo);
+    return st;
+}

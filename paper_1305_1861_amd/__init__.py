@@ -26,7 +26,8 @@ LIB_PATH = os.path.join(_HERE, "libturtle.so")
 
 TK_OK, TK_EINVAL, TK_ENOMEM, TK_EDEVICE, TK_EOVERFLOW = 0, -1, -2, -3, -4
 TK_FLAG_TIMING = 1
-STAGES = ("pack", "screen", "collect", "sort", "compact")
+TK_FLAG_GLOBAL_FILTER = 2
+STAGES = ("pack", "screen", "collect", "sort", "compact", "partition", "bucket", "fallback", "gather")
 
 _u64 = ctypes.c_uint64
 _u32 = ctypes.c_uint32
@@ -35,7 +36,8 @@ _vp = ctypes.c_void_p
 
 class tk_options(ctypes.Structure):
     _fields_ = [("bloom_beta", _u32), ("bloom_table_bits", _u32), ("bloom_bits", _u32),
-                ("flags", _u32), ("bloom_blocks", _u64), ("bloom_seed", _u64)]
+                ("flags", _u32), ("bloom_blocks", _u64), ("bloom_seed", _u64),
+                ("part_bits", ctypes.c_int32), ("reserved", _u32)]
 
 
 class tk_result(ctypes.Structure):
@@ -43,7 +45,7 @@ class tk_result(ctypes.Structure):
                 ("keys", ctypes.POINTER(_u64)), ("counts", ctypes.POINTER(_u32)),
                 ("n_windows", _u64), ("n_collected", _u64), ("n_distinct", _u64),
                 ("n_singletons", _u64), ("n_below_c", _u64), ("bloom_blocks", _u64),
-                ("sort_passes", _u32), ("reserved", _u32),
+                ("sort_passes", _u32), ("part_bits", ctypes.c_int32), ("n_fallback", _u64),
                 ("stage_ms", ctypes.c_double * len(STAGES))]
 
 
@@ -80,6 +82,7 @@ def load_library():
                                            P(tk_result)]),
         "tk_pattern_table": (ctypes.c_int, [P(tk_options), _vp, _u64]),
         "tk_bloom_blocks": (ctypes.c_int, [_u64, _u64, ctypes.c_int, P(tk_options), P(_u64)]),
+        "tk_part_bits": (ctypes.c_int, [_u64, _u64, ctypes.c_int, P(tk_options), P(ctypes.c_int)]),
         "tk_pack_device": (ctypes.c_int, [_vp, _vp, _u64, _u64, ctypes.c_int, _vp, _vp, _vp,
                                           _vp, _vp]),
         "tk_sort_scratch_size": (ctypes.c_int, [_u64, ctypes.c_int, P(ctypes.c_size_t)]),
@@ -100,7 +103,7 @@ def load_library():
 def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["tk_default_options", "tk_strerror", "tk_last_error", "tk_count", "tk_result_free",
-            "tk_workspace_size", "tk_count_device", "tk_pattern_table", "tk_bloom_blocks",
+            "tk_workspace_size", "tk_count_device", "tk_pattern_table", "tk_bloom_blocks", "tk_part_bits",
             "tk_pack_device", "tk_sort_scratch_size", "tk_sort_keys_device",
             "tk_compact_scratch_size", "tk_compact_device"]
 
@@ -157,6 +160,13 @@ def tk_bloom_blocks(n_bases: int, n_reads: int, k: int, opts=None) -> int:
     return int(out.value)
 
 
+def tk_part_bits(n_bases: int, n_reads: int, k: int, opts=None) -> int:
+    o = _opts(opts)
+    out = ctypes.c_int(0)
+    _check(load_library().tk_part_bits(n_bases, n_reads, k, _optp(o), ctypes.byref(out)), "tk_part_bits")
+    return int(out.value)
+
+
 def tk_pattern_table(opts=None) -> np.ndarray:
     o = _opts(opts)
     bits = o.bloom_table_bits if o is not None and o.bloom_table_bits else 10
@@ -182,6 +192,8 @@ class Counts:
     n_below_c: int
     bloom_blocks: int
     sort_passes: int
+    part_bits: int
+    n_fallback: int
     stage_ms: dict = field(default_factory=dict)
 
     @property
@@ -194,6 +206,7 @@ def _stats(r: tk_result) -> dict:
                 n_collected=int(r.n_collected), n_distinct=int(r.n_distinct),
                 n_singletons=int(r.n_singletons), n_below_c=int(r.n_below_c),
                 bloom_blocks=int(r.bloom_blocks), sort_passes=int(r.sort_passes),
+                part_bits=int(r.part_bits), n_fallback=int(r.n_fallback),
                 stage_ms={s: float(r.stage_ms[i]) for i, s in enumerate(STAGES)})
 
 

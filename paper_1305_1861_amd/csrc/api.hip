@@ -46,6 +46,7 @@ constexpr int BLOCKS_PER_CU = 16;
 struct Opts {
     uint32_t beta, table_bits, bits, flags;
     uint64_t blocks, seed;
+    int part_bits;
 };
 
 tk_status resolve(const tk_options *o, Opts *r) {
@@ -55,6 +56,7 @@ tk_status resolve(const tk_options *o, Opts *r) {
     r->flags = 0;
     r->blocks = 0;
     r->seed = DEF_SEED;
+    r->part_bits = -1;
     if (o) {
         if (o->bloom_beta)
             r->beta = o->bloom_beta;
@@ -65,11 +67,15 @@ tk_status resolve(const tk_options *o, Opts *r) {
         r->flags = o->flags;
         r->blocks = o->bloom_blocks;
         r->seed = o->bloom_seed ? o->bloom_seed : DEF_SEED;
+        r->part_bits = o->part_bits;
     }
-    if (r->beta > 1024)
-        return fail(TK_EINVAL, "bloom_beta %u out of range [1, 1024]", r->beta);
-    if (r->table_bits < 1 || r->table_bits > 12)
-        return fail(TK_EINVAL, "bloom_table_bits %u out of range [1, 12]", r->table_bits);
+    const bool global = r->flags & TK_FLAG_GLOBAL_FILTER;
+    if (r->beta > (global ? 1024u : 32u))
+        return fail(TK_EINVAL, "bloom_beta %u out of range [1, %u]", r->beta, global ? 1024u : 32u);
+    if (r->table_bits < 1 || r->table_bits > 10)
+        return fail(TK_EINVAL, "bloom_table_bits %u out of range [1, 10]", r->table_bits);
+    if (r->part_bits < -1 || r->part_bits > 20)
+        return fail(TK_EINVAL, "part_bits %d out of range [-1, 20]", r->part_bits);
     if (r->bits < 1 || r->bits > 16)
         return fail(TK_EINVAL, "bloom_bits %u out of range [1, 16]", r->bits);
     return TK_OK;
@@ -119,16 +125,47 @@ uint64_t bloom_blocks_for(uint64_t n_bases, uint64_t n_reads, int k, const Opts 
     return b ? b : 1;
 }
 
+// Bucket bits of the partitioned path (size rule documented in turtle.h).
+int part_bits_for(uint64_t n_bases, uint64_t n_reads, int k, const Opts &o) {
+    const int cap = std::min(20, 2 * k);
+    if (o.part_bits >= 0)
+        return std::min(o.part_bits, cap);
+    const uint64_t cut = n_reads * (uint64_t)(k - 1);
+    const uint64_t w = n_bases > cut ? n_bases - cut : 1;
+    int lg = 0;
+    while ((1ull << lg) < w)
+        ++lg;
+    const int d = lg - (k <= 31 ? 11 : 10);
+    return std::max(0, std::min(d, cap));
+}
+
+constexpr uint64_t MAX_BUCKET_GRID = 4096;
+
 struct Plan {
     int k, key_words;
     uint32_t c;
-    bool screen;
+    bool screen, global;
     Opts opts;
     uint64_t n_bases, n_reads, n_words, cap, n_blocks;
     size_t key_bytes;
+    // partitioned path
+    int D, shift1, bits1, shift2, bits2;  // bits2 == 0: one pass
+    uint64_t n_buckets, fb_cap, fb_nb_max;
+    size_t part_words;
+    // workspace offsets
     size_t off_ctr, off_table, off_packed, off_valid, off_starts, off_filter;
-    size_t off_keys_a, off_keys_b, off_counts, off_sort, off_compact, total;
+    size_t off_keys_a, off_keys_b, off_counts, off_sort, off_compact;
+    size_t off_gapc, off_f, off_part, off_rec_start, off_rec_nout, off_rec_off, off_rec_scan;
+    size_t off_wg, off_fb_list, off_misc, total;
     size_t sort_bytes, compact_bytes;
+};
+
+// small device values of the partitioned path
+struct Misc {
+    uint32_t fb_count;
+    uint32_t totals[3];  // [0] windows, [1] records out, [2] keys after pass 2
+    unsigned long long fb_stats[4];
+    DevCounters fb_ctr;
 };
 
 tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const tk_options *o, Plan *p) {
@@ -148,13 +185,33 @@ tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const
     p->key_words = k <= 31 ? 1 : 2;
     p->key_bytes = 8 * (size_t)p->key_words;
     p->screen = c >= 2;
+    p->global = p->opts.flags & TK_FLAG_GLOBAL_FILTER;
     p->n_bases = n_bases;
     p->n_reads = n_reads;
     p->n_words = ceil_div(n_bases, 32);
     p->cap = n_bases;  // windows <= bases
-    p->n_blocks = p->screen ? bloom_blocks_for(n_bases, n_reads, k, p->opts) : 0;
+    p->n_blocks = (p->screen && p->global) ? bloom_blocks_for(n_bases, n_reads, k, p->opts) : 0;
     if (p->n_blocks > (1ull << 40))
         return fail(TK_EINVAL, "filter of %llu blocks is too large", (unsigned long long)p->n_blocks);
+    p->D = p->global ? -1 : part_bits_for(n_bases, n_reads, k, p->opts);
+    p->bits2 = 0;
+    p->shift2 = 0;
+    if (!p->global) {
+        const int D = p->D;
+        if (D <= 10) {
+            p->bits1 = D;
+            p->shift1 = 2 * k - D;
+        } else {
+            p->bits1 = D / 2;
+            p->shift1 = 2 * k - D;
+            p->bits2 = D - p->bits1;
+            p->shift2 = 2 * k - p->bits2;
+        }
+        p->n_buckets = 1ull << D;
+        p->fb_cap = p->cap / ((uint64_t)bucket_capacity(p->key_words) + 1) + 1;
+        p->fb_nb_max = p->screen ? ceil_div((uint64_t)p->opts.beta * std::max<uint64_t>(p->cap, 1), 256) : 0;
+        p->part_words = partition_scratch_words(std::max<uint64_t>(p->n_words * 32, 1), p->key_words);
+    }
     p->sort_bytes = radix_scratch_bytes(p->cap, p->key_words);
     p->compact_bytes = compact_scratch_bytes(p->cap);
     size_t off = 0;
@@ -168,12 +225,26 @@ tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const
     p->off_packed = take(p->n_words * sizeof(uint64_t));
     p->off_valid = take(p->n_words * sizeof(uint32_t));
     p->off_starts = take(p->n_words * sizeof(uint32_t));
-    p->off_filter = take(p->n_blocks * 64);
     p->off_keys_a = take(p->cap * p->key_bytes);
     p->off_keys_b = take(p->cap * p->key_bytes);
-    p->off_counts = take(p->cap * sizeof(uint32_t));
     p->off_sort = take(p->sort_bytes);
     p->off_compact = take(p->compact_bytes);
+    if (p->global) {
+        p->off_filter = take(p->n_blocks * 64);
+        p->off_counts = take(p->cap * sizeof(uint32_t));
+    } else {
+        p->off_filter = take(p->fb_nb_max * 64);
+        p->off_gapc = take(p->cap * sizeof(uint32_t));
+        p->off_f = take(p->cap * p->key_bytes);
+        p->off_part = take(p->part_words * sizeof(uint32_t));
+        p->off_rec_start = take(p->n_buckets * sizeof(uint32_t));
+        p->off_rec_nout = take(p->n_buckets * sizeof(uint32_t));
+        p->off_rec_off = take(p->n_buckets * sizeof(uint32_t));
+        p->off_rec_scan = take(scan_scratch_words(p->n_buckets) * sizeof(uint32_t));
+        p->off_wg = take(MAX_BUCKET_GRID * 4 * sizeof(unsigned long long));
+        p->off_fb_list = take(p->fb_cap * 3 * sizeof(uint32_t));
+        p->off_misc = take(sizeof(Misc));
+    }
     p->total = off;
     return TK_OK;
 }
@@ -237,7 +308,8 @@ namespace {
 
 struct Timer {
     bool on = false;
-    hipEvent_t ev[TK_STAGE_COUNT + 1] = {};
+    hipEvent_t ev[2 * TK_STAGE_COUNT] = {};
+    bool used[TK_STAGE_COUNT] = {};
     ~Timer() {
         for (auto &e : ev)
             if (e)
@@ -252,14 +324,22 @@ struct Timer {
         return TK_OK;
     }
     tk_status mark(int i, hipStream_t s) {
+        if (on) {
+            TK_HIP(hipEventRecord(ev[2 * i], s));
+            used[i] = true;
+        }
+        return TK_OK;
+    }
+    tk_status end(int i, hipStream_t s) {
         if (on)
-            TK_HIP(hipEventRecord(ev[i], s));
+            TK_HIP(hipEventRecord(ev[2 * i + 1], s));
         return TK_OK;
     }
     void read(double *ms) {
         for (int i = 0; i < TK_STAGE_COUNT; i++) {
             float t = 0.f;
-            ms[i] = (on && hipEventElapsedTime(&t, ev[i], ev[i + 1]) == hipSuccess) ? (double)t : 0.0;
+            ms[i] = (on && used[i] && hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) ? (double)t
+                                                                                                       : 0.0;
         }
     }
 };
@@ -270,8 +350,8 @@ int persistent_grid(uint64_t n_pos) {
     return (int)std::min(want, cap);
 }
 
-tk_status run_count(const uint8_t *d_bases, const uint64_t *d_offsets, const Plan &p, char *ws, hipStream_t s,
-                    tk_result *out) {
+tk_status run_global(const uint8_t *d_bases, const uint64_t *d_offsets, const Plan &p, char *ws, hipStream_t s,
+                     tk_result *out) {
     DevCounters *ctr = reinterpret_cast<DevCounters *>(ws + p.off_ctr);
     uint64_t *table = reinterpret_cast<uint64_t *>(ws + p.off_table);
     uint64_t *packed = reinterpret_cast<uint64_t *>(ws + p.off_packed);
@@ -298,15 +378,17 @@ tk_status run_count(const uint8_t *d_bases, const uint64_t *d_offsets, const Pla
     if ((st = tm.mark(TK_STAGE_PACK, s)) != TK_OK)
         return st;
     TK_HIP(launch_pack(d_bases, d_offsets, p.n_bases, p.n_reads, p.k, packed, valid, starts, &ctr->n_windows, s));
-    if ((st = tm.mark(TK_STAGE_SCREEN, s)) != TK_OK)
+    if ((st = tm.end(TK_STAGE_PACK, s)) != TK_OK || (st = tm.mark(TK_STAGE_SCREEN, s)) != TK_OK)
         return st;
     BloomArgs a{packed, valid, p.n_words, p.k, table, p.opts.table_bits, p.n_blocks, filter};
     const int grid = persistent_grid(p.n_words * 32);
     if (p.screen)
         TK_HIP(launch_screen(a, grid, s));
-    if ((st = tm.mark(TK_STAGE_COLLECT, s)) != TK_OK)
+    if ((st = tm.end(TK_STAGE_SCREEN, s)) != TK_OK || (st = tm.mark(TK_STAGE_COLLECT, s)) != TK_OK)
         return st;
     TK_HIP(launch_collect(a, p.screen, keys_a, p.cap, &ctr->n_collected, grid, s));
+    if ((st = tm.end(TK_STAGE_COLLECT, s)) != TK_OK)
+        return st;
 
     DevCounters h{};
     TK_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
@@ -322,10 +404,10 @@ tk_status run_count(const uint8_t *d_bases, const uint64_t *d_offsets, const Pla
     int passes = 0;
     TK_HIP(radix_sort(keys_a, keys_b, n, p.key_words, 2 * p.k, ws + p.off_sort, p.sort_bytes, s, &sorted, &passes));
     uint64_t *out_keys = sorted == keys_a ? keys_b : keys_a;
-    if ((st = tm.mark(TK_STAGE_COMPACT, s)) != TK_OK)
+    if ((st = tm.end(TK_STAGE_SORT, s)) != TK_OK || (st = tm.mark(TK_STAGE_COMPACT, s)) != TK_OK)
         return st;
     TK_HIP(compact(sorted, n, p.key_words, p.c, out_keys, counts, ws + p.off_compact, p.compact_bytes, ctr, s));
-    if ((st = tm.mark(TK_STAGE_COUNT, s)) != TK_OK)
+    if ((st = tm.end(TK_STAGE_COMPACT, s)) != TK_OK)
         return st;
     TK_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
     TK_HIP(hipStreamSynchronize(s));
@@ -343,8 +425,168 @@ tk_status run_count(const uint8_t *d_bases, const uint64_t *d_offsets, const Pla
     out->n_below_c = h.n_below;
     out->bloom_blocks = p.n_blocks;
     out->sort_passes = (uint32_t)passes;
+    out->part_bits = -1;
     tm.read(out->stage_ms);
     return TK_OK;
+}
+
+tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, const Plan &p, char *ws,
+                          hipStream_t s, tk_result *out) {
+    DevCounters *ctr = reinterpret_cast<DevCounters *>(ws + p.off_ctr);
+    uint64_t *table = reinterpret_cast<uint64_t *>(ws + p.off_table);
+    uint64_t *packed = reinterpret_cast<uint64_t *>(ws + p.off_packed);
+    uint32_t *valid = reinterpret_cast<uint32_t *>(ws + p.off_valid);
+    uint32_t *starts = reinterpret_cast<uint32_t *>(ws + p.off_starts);
+    uint64_t *filter = reinterpret_cast<uint64_t *>(ws + p.off_filter);
+    uint64_t *keys_a = reinterpret_cast<uint64_t *>(ws + p.off_keys_a);
+    uint64_t *keys_b = reinterpret_cast<uint64_t *>(ws + p.off_keys_b);
+    uint32_t *gap_counts = reinterpret_cast<uint32_t *>(ws + p.off_gapc);
+    uint64_t *fbuf = reinterpret_cast<uint64_t *>(ws + p.off_f);
+    uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
+    uint32_t *rec_start = reinterpret_cast<uint32_t *>(ws + p.off_rec_start);
+    uint32_t *rec_nout = reinterpret_cast<uint32_t *>(ws + p.off_rec_nout);
+    uint32_t *rec_off = reinterpret_cast<uint32_t *>(ws + p.off_rec_off);
+    uint32_t *rec_scan = reinterpret_cast<uint32_t *>(ws + p.off_rec_scan);
+    unsigned long long *wg = reinterpret_cast<unsigned long long *>(ws + p.off_wg);
+    uint32_t *fb_list = reinterpret_cast<uint32_t *>(ws + p.off_fb_list);
+    Misc *misc = reinterpret_cast<Misc *>(ws + p.off_misc);
+    const int kw = p.key_words;
+
+    Timer tm;
+    tk_status st = tm.init(p.opts.flags & TK_FLAG_TIMING);
+    if (st != TK_OK)
+        return st;
+
+    TK_HIP(zero_bytes(ctr, sizeof(DevCounters), s));
+    TK_HIP(zero_bytes(misc, sizeof(Misc), s));
+    TK_HIP(zero_bytes(starts, p.n_words * sizeof(uint32_t), s));
+    TK_HIP(zero_bytes(rec_nout, p.n_buckets * sizeof(uint32_t), s));
+    if (p.screen) {
+        const auto &tab = pattern_table(p.opts.seed, p.opts.table_bits, p.opts.bits);
+        TK_HIP(hipMemcpyAsync(table, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    }
+
+    if ((st = tm.mark(TK_STAGE_PACK, s)) != TK_OK)
+        return st;
+    TK_HIP(launch_pack(d_bases, d_offsets, p.n_bases, p.n_reads, p.k, packed, valid, starts, nullptr, s));
+    if ((st = tm.end(TK_STAGE_PACK, s)) != TK_OK || (st = tm.mark(TK_STAGE_PARTITION, s)) != TK_OK)
+        return st;
+
+    // keys ordered by bucket: windows -> A (-> B)
+    PartArgs pa{packed, valid, nullptr, p.n_words * 32, p.k, p.shift1, p.bits1, 0, nullptr};
+    TK_HIP(partition_pass(pa, true, keys_a, part, p.part_words, &misc->totals[0], s));
+    uint64_t *sorted = keys_a, *other = keys_b;
+    if (p.bits2) {
+        PartArgs pb{nullptr, nullptr, keys_a, p.cap, p.k, p.shift2, p.bits2, 0, &misc->totals[0]};
+        TK_HIP(partition_pass(pb, false, keys_b, part, p.part_words, &misc->totals[2], s));
+        sorted = keys_b;
+        other = keys_a;
+    }
+    if ((st = tm.end(TK_STAGE_PARTITION, s)) != TK_OK || (st = tm.mark(TK_STAGE_BUCKET, s)) != TK_OK)
+        return st;
+
+    const int grid = (int)std::min<uint64_t>((uint64_t)bucket_grid(), MAX_BUCKET_GRID);
+    BucketArgs ba{};
+    ba.keys = sorted;
+    ba.n_dev = &misc->totals[0];
+    ba.k = p.k;
+    ba.D = p.D;
+    ba.c = p.c;
+    ba.screen = p.screen;
+    ba.beta = p.opts.beta;
+    ba.table = table;
+    ba.table_bits = p.opts.table_bits;
+    ba.gap_keys = other;
+    ba.gap_counts = gap_counts;
+    ba.rec_start = rec_start;
+    ba.rec_nout = rec_nout;
+    ba.wg_stats = wg;
+    ba.fb_list = fb_list;
+    ba.fb_count = &misc->fb_count;
+    ba.fb_cap = (uint32_t)p.fb_cap;
+    TK_HIP(launch_bucket(ba, kw, grid, s));
+    if ((st = tm.end(TK_STAGE_BUCKET, s)) != TK_OK)
+        return st;
+
+    Misc hm{};
+    TK_HIP(hipMemcpyAsync(&hm, misc, sizeof hm, hipMemcpyDeviceToHost, s));
+    TK_HIP(hipStreamSynchronize(s));
+    if (hm.fb_count > p.fb_cap)
+        return fail(TK_EDEVICE, "%u oversized buckets exceed the list of %llu", hm.fb_count,
+                    (unsigned long long)p.fb_cap);
+
+    // buckets too large for LDS: global-memory kernels, same filter rule
+    if ((st = tm.mark(TK_STAGE_FALLBACK, s)) != TK_OK)
+        return st;
+    if (hm.fb_count) {
+        std::vector<uint32_t> list(3 * (size_t)hm.fb_count);
+        TK_HIP(hipMemcpyAsync(list.data(), fb_list, list.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+        const int SB = 2 * p.k - p.D;
+        for (uint32_t i = 0; i < hm.fb_count; i++) {
+            const uint32_t b = list[3 * i], start = list[3 * i + 1], ns = list[3 * i + 2];
+            const uint64_t *kb = sorted + (size_t)start * kw;
+            uint64_t *gap = other + (size_t)start * kw;
+            const uint64_t nb = std::max<uint64_t>(1, ceil_div((uint64_t)p.opts.beta * ns, 256));
+            if (p.screen) {
+                TK_HIP(zero_bytes(filter, nb * 64, s));
+                TK_HIP(launch_fb_screen(kb, ns, kw, table, p.opts.table_bits, filter, nb, s));
+            }
+            TK_HIP(zero_bytes(&misc->fb_ctr, sizeof(DevCounters), s));
+            TK_HIP(launch_fb_collect(kb, ns, kw, table, p.opts.table_bits, filter, nb, p.screen, fbuf,
+                                     &misc->fb_ctr.n_collected, s));
+            unsigned long long n_surv = 0;
+            TK_HIP(hipMemcpyAsync(&n_surv, &misc->fb_ctr.n_collected, sizeof n_surv, hipMemcpyDeviceToHost, s));
+            TK_HIP(hipStreamSynchronize(s));
+            uint64_t *srt = nullptr;
+            int passes = 0;
+            TK_HIP(radix_sort(fbuf, gap, n_surv, kw, SB, ws + p.off_sort, p.sort_bytes, s, &srt, &passes));
+            uint64_t *dst = srt == fbuf ? gap : fbuf;
+            TK_HIP(compact(srt, n_surv, kw, p.c, dst, gap_counts + start, ws + p.off_compact, p.compact_bytes,
+                           &misc->fb_ctr, s));
+            if (dst != gap && n_surv)
+                TK_HIP(hipMemcpyAsync(gap, dst, n_surv * p.key_bytes, hipMemcpyDeviceToDevice, s));
+            TK_HIP(launch_fb_fold(&misc->fb_ctr, b, rec_nout, misc->fb_stats, s));
+        }
+    }
+    if ((st = tm.end(TK_STAGE_FALLBACK, s)) != TK_OK || (st = tm.mark(TK_STAGE_GATHER, s)) != TK_OK)
+        return st;
+
+    // records of every bucket in bucket order: final keys in `sorted`,
+    // final counts in F
+    uint32_t *out_counts = reinterpret_cast<uint32_t *>(fbuf);
+    TK_HIP(launch_exclusive_scan(rec_nout, rec_off, p.n_buckets, rec_scan, &misc->totals[1], s));
+    TK_HIP(launch_gather(rec_start, rec_nout, rec_off, p.n_buckets, other, gap_counts, kw, sorted, out_counts, s));
+    TK_HIP(launch_stats(wg, (uint64_t)grid, misc->fb_stats, misc->totals, ctr, s));
+    if ((st = tm.end(TK_STAGE_GATHER, s)) != TK_OK)
+        return st;
+    DevCounters h{};
+    TK_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
+    TK_HIP(hipStreamSynchronize(s));
+
+    memset(out, 0, sizeof *out);
+    out->n = h.n_out;
+    out->k = (uint32_t)p.k;
+    out->key_words = (uint32_t)kw;
+    out->keys = sorted;
+    out->counts = out_counts;
+    out->n_windows = h.n_windows;
+    out->n_collected = h.n_collected;
+    out->n_distinct = h.n_runs;
+    out->n_singletons = h.n_single;
+    out->n_below_c = h.n_below;
+    out->bloom_blocks = 0;
+    out->sort_passes = 0;
+    out->part_bits = p.D;
+    out->n_fallback = hm.fb_count;
+    tm.read(out->stage_ms);
+    return TK_OK;
+}
+
+tk_status run_count(const uint8_t *d_bases, const uint64_t *d_offsets, const Plan &p, char *ws, hipStream_t s,
+                    tk_result *out) {
+    return p.global ? run_global(d_bases, d_offsets, p, ws, s, out)
+                    : run_partitioned(d_bases, d_offsets, p, ws, s, out);
 }
 
 }  // namespace
@@ -362,6 +604,7 @@ tk_status tk_default_options(tk_options *opts) {
     opts->bloom_table_bits = DEF_TABLE_BITS;
     opts->bloom_bits = DEF_BITS;
     opts->bloom_seed = DEF_SEED;
+    opts->part_bits = -1;
     return TK_OK;
 }
 
@@ -400,6 +643,19 @@ tk_status tk_bloom_blocks(uint64_t n_bases, uint64_t n_reads, int k, const tk_op
     if (st != TK_OK)
         return st;
     *n_blocks = bloom_blocks_for(n_bases, n_reads, k, o);
+    return TK_OK;
+}
+
+tk_status tk_part_bits(uint64_t n_bases, uint64_t n_reads, int k, const tk_options *opts, int *part_bits) {
+    if (!part_bits)
+        return fail(TK_EINVAL, "part_bits is NULL");
+    if (k < 1 || k > 63)
+        return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
+    Opts o;
+    tk_status st = resolve(opts, &o);
+    if (st != TK_OK)
+        return st;
+    *part_bits = part_bits_for(n_bases, n_reads, k, o);
     return TK_OK;
 }
 

@@ -30,68 +30,6 @@ namespace {
 
 constexpr int BLOOM_THREADS = 256;
 
-// Forward/reverse-complement extraction of the window ending at base p.
-// k <= 31: one-word key.
-__device__ __forceinline__ uint64_t window_key1(const uint64_t *__restrict__ packed, uint64_t w, uint32_t t, int k) {
-    const uint64_t w0 = packed[w];
-    const uint64_t w1 = w ? packed[w - 1] : 0;
-    const uint32_t s = 62 - 2 * t;  // bit of the window's last base in w0
-    const uint64_t cat = s ? (w0 >> s) | (w1 << (64 - s)) : w0;
-    const uint64_t fwd = cat & ((1ull << (2 * k)) - 1);
-    const uint64_t rc = ~group_reverse(fwd) >> (64 - 2 * k);
-    return fwd < rc ? fwd : rc;
-}
-
-// 32 <= k <= 63: two-word key {hi, lo}.
-__device__ __forceinline__ Key2 window_key2(const uint64_t *__restrict__ packed, uint64_t w, uint32_t t, int k) {
-    const uint64_t w0 = packed[w];
-    const uint64_t w1 = w ? packed[w - 1] : 0;
-    const uint64_t w2 = w > 1 ? packed[w - 2] : 0;
-    const uint32_t s = 62 - 2 * t;
-    uint64_t lo, hi;
-    if (s) {
-        lo = (w0 >> s) | (w1 << (64 - s));
-        hi = (w1 >> s) | (w2 << (64 - s));
-    } else {
-        lo = w0;
-        hi = w1;
-    }
-    const int hb = 2 * k - 64;  // bits of the key in hi, 0..62
-    hi &= (1ull << hb) - 1;
-    // reverse complement of the 2k-bit value: reverse the 64 groups of the
-    // 128-bit word, complement, shift right by 128 - 2k
-    const uint64_t a_hi = ~group_reverse(lo);
-    const uint64_t a_lo = ~group_reverse(hi);
-    const int sh = 128 - 2 * k;  // 2..64
-    uint64_t rlo, rhi;
-    if (sh == 64) {
-        rlo = a_hi;
-        rhi = 0;
-    } else {
-        rlo = (a_lo >> sh) | (a_hi << (64 - sh));
-        rhi = a_hi >> sh;
-    }
-    const bool fwd_smaller = hi < rhi || (hi == rhi && lo <= rlo);
-    return fwd_smaller ? Key2{hi, lo} : Key2{rhi, rlo};
-}
-
-template <bool TWO>
-struct KeyOf;
-template <>
-struct KeyOf<false> {
-    using type = uint64_t;
-    __device__ static uint64_t get(const uint64_t *packed, uint64_t w, uint32_t t, int k) {
-        return window_key1(packed, w, t, k);
-    }
-};
-template <>
-struct KeyOf<true> {
-    using type = Key2;
-    __device__ static Key2 get(const uint64_t *packed, uint64_t w, uint32_t t, int k) {
-        return window_key2(packed, w, t, k);
-    }
-};
-
 __device__ __forceinline__ void load_table(const uint64_t *__restrict__ table, uint32_t n, uint64_t *s_table) {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
         s_table[i] = table[i];

@@ -1,0 +1,582 @@
+// Per-bucket screen, sort and compaction in LDS.
+//
+// The keys arrive ordered by bucket (top D bits).  Every bucket owns a
+// pattern-blocked Bloom filter sized from its own number of windows, so the
+// filter of one bucket fits in LDS and is touched by one workgroup only -- the
+// GPU counterpart of the paper's per-consumer filters (§2.1, parallelization:
+// a k-mer always meets the same filter because it is routed by a function of
+// its value).  Within a bucket (§2.1 PBF, sorting and compaction, Algorithm 1):
+//   screen : for each window, old = atomicOr(S[w], m_w); atomicOr(T[w], old & m_w)
+//   collect: a window survives iff all its pattern bits hold in T
+//   sort   : LSD radix sort of the survivors on the bits below the bucket
+//            digit (keys in registers, LDS as exchange buffer)
+//   compact: run-length compaction, threshold c, (key, count) records written
+//            at the bucket's start index (gathered into place afterwards).
+//
+// A persistent workgroup streams through a contiguous range of buckets.  A
+// bucket with more windows than fit in registers is recorded for the
+// fallback path (global-memory kernels with the same filter semantics).
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace tk {
+namespace {
+
+constexpr int BK_THREADS = 512;
+constexpr int BK_WAVES = BK_THREADS / WAVE;
+constexpr int BK_SORT_BITS = 9;
+constexpr int BK_BINS = 1 << BK_SORT_BITS;  // == BK_THREADS: one bin per thread
+constexpr int BK_TABLE = 1024;              // pattern table entries held in LDS (max)
+
+template <typename K>
+struct BkItems;
+template <>
+struct BkItems<uint64_t> {
+    static constexpr int value = 15;  // 7680 windows per bucket in LDS
+};
+template <>
+struct BkItems<Key2> {
+    static constexpr int value = 7;  // 3584 windows per bucket in LDS
+};
+
+template <typename K>
+__device__ __forceinline__ uint32_t bucket_of(const K &key, int k, int D) {
+    return digit_of(key, 2 * k - D, (1u << D) - 1u);
+}
+
+// First index in [p, n) whose bucket is greater than the bucket of key p-1
+// (p itself when p == 0, n when p >= n).  Buckets are non-decreasing.
+template <typename K>
+__device__ uint64_t next_bucket_start(const K *__restrict__ keys, uint64_t n, uint64_t p, int k, int D) {
+    if (p == 0 || p >= n)
+        return p >= n ? n : 0;
+    const uint32_t d = bucket_of(keys[p - 1], k, D);
+    uint64_t lo = p, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (bucket_of(keys[mid], k, D) > d)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// End of bucket d starting at p: first index in [p, n) with bucket > d.
+template <typename K>
+__device__ uint64_t bucket_end(const K *__restrict__ keys, uint64_t n, uint64_t p, uint32_t d, int k, int D) {
+    uint64_t lo = p, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (bucket_of(keys[mid], k, D) > d)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+template <typename K>
+__device__ __forceinline__ K sentinel();
+template <>
+__device__ __forceinline__ uint64_t sentinel<uint64_t>() { return ~0ull; }
+template <>
+__device__ __forceinline__ Key2 sentinel<Key2>() { return Key2{~0ull, ~0ull}; }
+
+// Number of lanes whose flag is set in a ballot.
+__device__ __forceinline__ uint32_t wave_count(uint64_t ball) { return (uint32_t)__popcll(ball); }
+
+template <typename K>
+__global__ __launch_bounds__(BK_THREADS, 2) void bucket_kernel(BucketArgs a) {
+    constexpr int ITEMS = BkItems<K>::value;
+    constexpr int CAP = BK_THREADS * ITEMS;
+    __shared__ uint64_t s_table[BK_TABLE];
+    __shared__ uint16_t s_cnt[BK_WAVES][BK_BINS];
+    // exchange buffer with a sentinel slot on each side; holds the filter
+    // during screen/collect
+    __shared__ __align__(16) K s_exs[CAP + 2];
+    __shared__ uint32_t s_w[2][BK_WAVES];
+    __shared__ unsigned long long s_pos[2];
+
+    K *const s_ex = s_exs + 1;
+    uint64_t *s_filter = reinterpret_cast<uint64_t *>(s_exs);
+    const int tid0 = threadIdx.x;
+    const K *__restrict__ keys = static_cast<const K *>(a.keys);
+    K *__restrict__ gap_keys = static_cast<K *>(a.gap_keys);
+    const uint32_t n_tab = 1u << a.table_bits;
+    const uint32_t tmask = n_tab - 1;
+    if (a.screen)
+        for (uint32_t i = tid0; i < n_tab; i += BK_THREADS)
+            s_table[i] = a.table[i];
+
+    const uint64_t G = gridDim.x, g = blockIdx.x;
+    const uint64_t n = *a.n_dev;
+    if (tid0 == 0) {
+        s_pos[0] = next_bucket_start(keys, n, n * g / G, a.k, a.D);
+        s_pos[1] = next_bucket_start(keys, n, n * (g + 1) / G, a.k, a.D);
+    }
+    __syncthreads();
+    uint64_t pos = s_pos[0];
+    const uint64_t end = s_pos[1];
+    const int SB = 2 * a.k - a.D;  // key bits below the bucket digit
+    const int passes = SB > 0 ? (SB + BK_SORT_BITS - 1) / BK_SORT_BITS : 1;
+    unsigned long long st_coll = 0, st_runs = 0, st_single = 0, st_below = 0;
+
+    while (pos < end) {
+        // Thread indices are passed through an empty asm each iteration so
+        // the compiler recomputes what depends on them inside the loop
+        // instead of keeping dozens of hoisted lane masks alive across it.
+        int tid = tid0;
+        asm volatile("" : "+v"(tid));
+        const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
+        const uint32_t lane = (uint32_t)tid % WAVE;
+        const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+        // ---- bucket of key[pos]; load it into registers (item-major) ----
+        const uint32_t d = bucket_of(keys[pos], a.k, a.D);
+        K key[ITEMS];
+        uint32_t inm = 0;  // bit i: item i holds a window of this bucket
+        uint32_t n_s = 0;
+        bool more = true;
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            if (more) {  // uniform: the previous item batch was all in this bucket
+                const uint64_t e = pos + (uint64_t)i * BK_THREADS + tid;
+                bool in = false;
+                if (e < end) {
+                    key[i] = keys[e];
+                    in = bucket_of(key[i], a.k, a.D) == d;
+                }
+                inm |= (uint32_t)in << i;
+                const uint32_t c = (uint32_t)__syncthreads_count(in);
+                n_s += c;
+                more = c == BK_THREADS;
+            }
+        }
+        if (more) {
+            // every loaded key is in this bucket: it may be larger than the
+            // registers hold; measure it and hand it to the fallback path
+            if (tid == 0) {
+                const uint64_t e = bucket_end(keys, end, pos + CAP, d, a.k, a.D);
+                const uint64_t ns = e - pos;
+                s_pos[0] = e;
+                if (ns > (uint64_t)CAP) {
+                    const uint32_t slot = atomicAdd(a.fb_count, 1u);
+                    if (slot < a.fb_cap) {
+                        a.fb_list[3 * slot + 0] = d;
+                        a.fb_list[3 * slot + 1] = (uint32_t)pos;
+                        a.fb_list[3 * slot + 2] = (uint32_t)ns;
+                    }
+                    a.rec_start[d] = (uint32_t)pos;
+                }
+            }
+            __syncthreads();
+            const uint64_t e = s_pos[0];
+            __syncthreads();
+            if (e - pos > (uint64_t)CAP) {
+                pos = e;
+                continue;
+            }
+            // exactly CAP keys: fall through and process in LDS
+        }
+
+        // ---- screen and collect (two-plane filter of this bucket) ----
+        uint32_t sv = inm;  // bit i: item i survives the screen
+        if (a.screen) {
+            const uint32_t nb = max(1u, (uint32_t)(((uint64_t)a.beta * n_s + 255) / 256));
+            for (uint32_t i = tid; i < nb * 8; i += BK_THREADS)
+                s_filter[i] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                if ((inm >> i) & 1u) {
+                    const uint64_t h = key_hash(key[i]);
+                    uint64_t *b = s_filter + (uint64_t)__umul64hi(h, nb) * 8;
+#pragma unroll
+                    for (int w = 0; w < 4; w++) {
+                        const uint64_t m = s_table[(h >> (w * a.table_bits)) & tmask];
+                        const uint64_t old = atomicOr((unsigned long long *)(b + w), (unsigned long long)m);
+                        if (old & m)
+                            atomicOr((unsigned long long *)(b + 4 + w), (unsigned long long)(old & m));
+                    }
+                }
+            }
+            __syncthreads();
+            sv = 0;
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                if ((inm >> i) & 1u) {
+                    const uint64_t h = key_hash(key[i]);
+                    const uint64_t *b = s_filter + (uint64_t)__umul64hi(h, nb) * 8 + 4;
+                    bool all = true;
+#pragma unroll
+                    for (int w = 0; w < 4; w++) {
+                        const uint64_t m = s_table[(h >> (w * a.table_bits)) & tmask];
+                        all &= (b[w] & m) == m;
+                    }
+                    sv |= (uint32_t)all << i;
+                }
+            }
+            __syncthreads();  // the filter area becomes the exchange buffer
+        }
+
+        // ---- LSD radix sort of the survivors on bits [0, SB) ----
+        uint32_t n_surv = 0;
+        for (int p = 0; p < passes; p++) {
+            const int shift = p * BK_SORT_BITS;
+            const int bits = SB - shift < BK_SORT_BITS ? SB - shift : BK_SORT_BITS;
+            const uint32_t dmask = (1u << bits) - 1u;
+            for (int i = tid; i < BK_WAVES * BK_BINS; i += BK_THREADS)
+                (&s_cnt[0][0])[i] = 0;
+            __syncthreads();
+            uint32_t rd[ITEMS];  // (rank << 9) | digit
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                const bool act = (sv >> i) & 1u;
+                const uint32_t dg = act ? digit_of(key[i], shift, dmask) : 0u;
+                uint64_t peers = __ballot(act);
+                for (int b = 0; b < bits; b++) {
+                    const bool bit = (dg >> b) & 1u;
+                    const uint64_t m = __ballot(bit);
+                    peers &= bit ? m : ~m;
+                }
+                const uint32_t below = __popcll(peers & lt);
+                const uint32_t prior = s_cnt[wave][dg];
+                if (act && below == 0)
+                    s_cnt[wave][dg] = (uint16_t)(prior + (uint32_t)__popcll(peers));
+                rd[i] = ((prior + below) << BK_SORT_BITS) | dg;
+            }
+            __syncthreads();
+            {
+                // bin `tid`: total over waves, block-wide start, per-wave offsets
+                uint32_t tot = 0;
+#pragma unroll
+                for (int w = 0; w < BK_WAVES; w++)
+                    tot += s_cnt[w][tid];
+                uint32_t r = block_exclusive_sum<BK_THREADS>(tot, &n_surv);
+#pragma unroll
+                for (int w = 0; w < BK_WAVES; w++) {
+                    const uint32_t c = s_cnt[w][tid];
+                    s_cnt[w][tid] = (uint16_t)r;
+                    r += c;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++)
+                if ((sv >> i) & 1u)
+                    s_ex[s_cnt[wave][rd[i] & (BK_BINS - 1)] + (rd[i] >> BK_SORT_BITS)] = key[i];
+            __syncthreads();
+            if (p + 1 < passes) {
+                // reload wave-striped: element (wave, item, lane) in order
+                sv = 0;
+#pragma unroll
+                for (int i = 0; i < ITEMS; i++) {
+                    const uint32_t e = (uint32_t)(wave * ITEMS + i) * WAVE + lane;
+                    if (e < n_surv) {
+                        key[i] = s_ex[e];
+                        sv |= 1u << i;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+
+        // ---- run-length compaction of s_ex[0, n_surv) ----
+        // heads and tails in (wave, item, lane) order; the r-th head and the
+        // r-th tail delimit run r.  Run starts go to the bucket's slice of
+        // gap_counts (capacity n_s >= number of runs).
+        // sentinels: no key has all bits set (keys use at most 126 bits)
+        if (tid == 0) {
+            s_ex[-1] = sentinel<K>();
+            s_ex[n_surv] = sentinel<K>();
+        }
+        __syncthreads();
+        uint32_t *gcnt = a.gap_counts + pos;
+        uint32_t nh = 0, nt = 0;
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint32_t e = (uint32_t)(wave * ITEMS + i) * WAVE + lane;
+            bool h = false, t = false;
+            if (e < n_surv) {
+                const K x = s_ex[e];
+                h = s_ex[(int)e - 1] != x;
+                t = s_ex[e + 1] != x;
+            }
+            nh += wave_count(__ballot(h));
+            nt += wave_count(__ballot(t));
+        }
+        if (lane == 0) {
+            s_w[0][wave] = nh;
+            s_w[1][wave] = nt;
+        }
+        __syncthreads();
+        uint32_t hbase = 0, tbase = 0, n_runs = 0;
+        for (int w = 0; w < BK_WAVES; w++) {
+            hbase += w < wave ? s_w[0][w] : 0;
+            tbase += w < wave ? s_w[1][w] : 0;
+            n_runs += s_w[0][w];
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint32_t e = (uint32_t)(wave * ITEMS + i) * WAVE + lane;
+            const bool h = e < n_surv && s_ex[(int)e - 1] != s_ex[e];
+            const uint64_t hb = __ballot(h);
+            if (h)
+                gcnt[hbase + __popcll(hb & lt)] = e;
+            hbase += wave_count(hb);
+        }
+        __syncthreads();
+        uint32_t cnt[ITEMS];
+        uint32_t nk = 0, single = 0, below = 0;
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint32_t e = (uint32_t)(wave * ITEMS + i) * WAVE + lane;
+            const bool t = e < n_surv && s_ex[e + 1] != s_ex[e];
+            const uint64_t tb = __ballot(t);
+            cnt[i] = 0;
+            if (t) {
+                cnt[i] = e - gcnt[tbase + __popcll(tb & lt)] + 1;
+                single += cnt[i] == 1;
+                below += cnt[i] >= 2 && cnt[i] < a.c;
+            }
+            tbase += wave_count(tb);
+            nk += wave_count(__ballot(cnt[i] >= a.c));
+        }
+        __syncthreads();  // every run start has been read
+        if (lane == 0)
+            s_w[0][wave] = nk;
+        __syncthreads();
+        uint32_t kbase = 0, n_kept = 0;
+        for (int w = 0; w < BK_WAVES; w++) {
+            kbase += w < wave ? s_w[0][w] : 0;
+            n_kept += s_w[0][w];
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const bool keep = cnt[i] >= a.c;
+            const uint64_t kb = __ballot(keep);
+            if (keep) {
+                const uint32_t e = (uint32_t)(wave * ITEMS + i) * WAVE + lane;
+                const uint32_t o = kbase + (uint32_t)__popcll(kb & lt);
+                gap_keys[pos + o] = s_ex[e];
+                gcnt[o] = cnt[i];
+            }
+            kbase += wave_count(kb);
+        }
+        st_single += single;
+        st_below += below;
+        if (tid == 0) {
+            a.rec_start[d] = (uint32_t)pos;
+            a.rec_nout[d] = n_kept;
+            st_coll += n_surv;
+            st_runs += n_runs;
+        }
+        pos += n_s;
+        __syncthreads();  // s_ex / s_w reused by the next bucket
+    }
+    // per-workgroup statistics (no contended atomics)
+    const int tid = tid0;
+    const int wave = tid / WAVE;
+    const uint32_t lane = lane_id();
+    const uint64_t ws = wave_sum64(st_single), wb = wave_sum64(st_below);
+    __shared__ unsigned long long s_red[BK_WAVES][2];
+    if (lane == 0) {
+        s_red[wave][0] = ws;
+        s_red[wave][1] = wb;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long s1 = 0, s2 = 0;
+        for (int w = 0; w < BK_WAVES; w++) {
+            s1 += s_red[w][0];
+            s2 += s_red[w][1];
+        }
+        unsigned long long *o = a.wg_stats + 4 * g;
+        o[0] = st_coll;
+        o[1] = st_runs;
+        o[2] = s1;
+        o[3] = s2;
+    }
+}
+
+// ---- fallback: one oversized bucket with global-memory kernels ----------
+
+template <typename K>
+__global__ __launch_bounds__(256) void fb_screen(const K *__restrict__ keys, uint64_t n, const uint64_t *__restrict__ table,
+                                                 uint32_t table_bits, uint64_t *__restrict__ filter, uint64_t nb) {
+    const uint32_t tmask = (1u << table_bits) - 1u;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t h = key_hash(keys[i]);
+        uint64_t *b = filter + __umul64hi(h, nb) * 8;
+        for (int w = 0; w < 4; w++) {
+            const uint64_t m = table[(h >> (w * table_bits)) & tmask];
+            const uint64_t old = __hip_atomic_fetch_or(b + w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (old & m)
+                __hip_atomic_fetch_or(b + 4 + w, old & m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void fb_collect(const K *__restrict__ keys, uint64_t n, const uint64_t *__restrict__ table,
+                                                  uint32_t table_bits, const uint64_t *__restrict__ filter, uint64_t nb,
+                                                  int screen, K *__restrict__ out, unsigned long long *__restrict__ n_out) {
+    const uint32_t tmask = (1u << table_bits) - 1u;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+        const uint64_t i = base + threadIdx.x;
+        bool keep = false;
+        K key{};
+        if (i < n) {
+            key = keys[i];
+            keep = true;
+            if (screen) {
+                const uint64_t h = key_hash(key);
+                const uint64_t *b = filter + __umul64hi(h, nb) * 8 + 4;
+                for (int w = 0; w < 4; w++) {
+                    const uint64_t m = table[(h >> (w * table_bits)) & tmask];
+                    keep &= (b[w] & m) == m;
+                }
+            }
+        }
+        const uint64_t ball = __ballot(keep);
+        if (ball) {
+            uint64_t at = 0;
+            if (lane_id() == 0)
+                at = atomicAdd(n_out, (unsigned long long)__popcll(ball));
+            at = read_lane64(at, 0);
+            if (keep)
+                out[at + __popcll(ball & lanemask_lt())] = key;
+        }
+    }
+}
+
+// Folds one fallback bucket's compaction counters into the bucket record and
+// the fallback statistics.
+__global__ void fb_fold(const DevCounters *__restrict__ c, uint32_t bucket, uint32_t *__restrict__ rec_nout,
+                        unsigned long long *__restrict__ fb_stats) {
+    rec_nout[bucket] = (uint32_t)c->n_out;
+    fb_stats[0] += c->n_collected;
+    fb_stats[1] += c->n_runs;
+    fb_stats[2] += c->n_single;
+    fb_stats[3] += c->n_below;
+}
+
+// ---- gather: records of every bucket, in bucket order, into place ---------
+
+__global__ __launch_bounds__(256) void gather_kernel(const uint32_t *__restrict__ rec_start,
+                                                     const uint32_t *__restrict__ rec_nout,
+                                                     const uint32_t *__restrict__ rec_off, uint64_t n_buckets,
+                                                     const uint64_t *__restrict__ gap_keys,
+                                                     const uint32_t *__restrict__ gap_counts, int key_words,
+                                                     uint64_t *__restrict__ out_keys, uint32_t *__restrict__ out_counts) {
+    const uint64_t b = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (b >= n_buckets)
+        return;
+    const uint32_t n = rec_nout[b];
+    if (!n)
+        return;
+    const uint64_t src = rec_start[b], dst = rec_off[b];
+    for (uint32_t i = lane_id(); i < n; i += WAVE) {
+        out_counts[dst + i] = gap_counts[src + i];
+        if (key_words == 1) {
+            out_keys[dst + i] = gap_keys[src + i];
+        } else {
+            const ulonglong2 *s = reinterpret_cast<const ulonglong2 *>(gap_keys);
+            reinterpret_cast<ulonglong2 *>(out_keys)[dst + i] = s[src + i];
+        }
+    }
+}
+
+__global__ void stats_kernel(const unsigned long long *__restrict__ wg_stats, uint64_t n_wg,
+                             const unsigned long long *__restrict__ fb_stats, const uint32_t *__restrict__ totals,
+                             DevCounters *__restrict__ ctr) {
+    // one block: totals[0] = windows, totals[1] = records out
+    __shared__ unsigned long long s[4][256];
+    unsigned long long v[4] = {0, 0, 0, 0};
+    for (uint64_t i = threadIdx.x; i < n_wg; i += blockDim.x)
+        for (int j = 0; j < 4; j++)
+            v[j] += wg_stats[4 * i + j];
+    for (int j = 0; j < 4; j++)
+        s[j][threadIdx.x] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t[4] = {0, 0, 0, 0};
+        for (int i = 0; i < (int)blockDim.x; i++)
+            for (int j = 0; j < 4; j++)
+                t[j] += s[j][i];
+        ctr->n_windows = totals[0];
+        ctr->n_out = totals[1];
+        ctr->n_collected = t[0] + fb_stats[0];
+        ctr->n_runs = t[1] + fb_stats[1];
+        ctr->n_single = t[2] + fb_stats[2];
+        ctr->n_below = t[3] + fb_stats[3];
+    }
+}
+
+}  // namespace
+
+int bucket_grid() { return device_cu_count() * 2; }
+
+int bucket_capacity(int key_words) {
+    return BK_THREADS * (key_words == 2 ? BkItems<Key2>::value : BkItems<uint64_t>::value);
+}
+
+hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream) {
+    if (key_words == 2)
+        bucket_kernel<Key2><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
+    else
+        bucket_kernel<uint64_t><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fb_screen(const void *keys, uint64_t n, int key_words, const uint64_t *table, uint32_t table_bits,
+                            uint64_t *filter, uint64_t nb, hipStream_t stream) {
+    const unsigned g = (unsigned)std::min<uint64_t>(ceil_div(n ? n : 1, 256), (uint64_t)device_cu_count() * 8);
+    if (key_words == 2)
+        fb_screen<Key2><<<g, 256, 0, stream>>>(static_cast<const Key2 *>(keys), n, table, table_bits, filter, nb);
+    else
+        fb_screen<uint64_t><<<g, 256, 0, stream>>>(static_cast<const uint64_t *>(keys), n, table, table_bits, filter,
+                                                   nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_fb_collect(const void *keys, uint64_t n, int key_words, const uint64_t *table, uint32_t table_bits,
+                             const uint64_t *filter, uint64_t nb, bool screen, void *out,
+                             unsigned long long *n_out, hipStream_t stream) {
+    const unsigned g = (unsigned)std::min<uint64_t>(ceil_div(n ? n : 1, 256), (uint64_t)device_cu_count() * 8);
+    if (key_words == 2)
+        fb_collect<Key2><<<g, 256, 0, stream>>>(static_cast<const Key2 *>(keys), n, table, table_bits, filter, nb,
+                                                screen, static_cast<Key2 *>(out), n_out);
+    else
+        fb_collect<uint64_t><<<g, 256, 0, stream>>>(static_cast<const uint64_t *>(keys), n, table, table_bits,
+                                                    filter, nb, screen, static_cast<uint64_t *>(out), n_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fb_fold(const DevCounters *c, uint32_t bucket, uint32_t *rec_nout, unsigned long long *fb_stats,
+                          hipStream_t stream) {
+    fb_fold<<<1, 1, 0, stream>>>(c, bucket, rec_nout, fb_stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const uint32_t *rec_start, const uint32_t *rec_nout, const uint32_t *rec_off,
+                         uint64_t n_buckets, const uint64_t *gap_keys, const uint32_t *gap_counts, int key_words,
+                         uint64_t *out_keys, uint32_t *out_counts, hipStream_t stream) {
+    const uint64_t per_block = 256 / WAVE;
+    const uint64_t g = ceil_div(n_buckets, per_block);
+    if (!g)
+        return hipSuccess;
+    gather_kernel<<<dim3((unsigned)g), dim3(256), 0, stream>>>(rec_start, rec_nout, rec_off, n_buckets, gap_keys,
+                                                               gap_counts, key_words, out_keys, out_counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const unsigned long long *wg_stats, uint64_t n_wg, const unsigned long long *fb_stats,
+                        const uint32_t *totals, DevCounters *ctr, hipStream_t stream) {
+    stats_kernel<<<1, 256, 0, stream>>>(wg_stats, n_wg, fb_stats, totals, ctr);
+    return hipGetLastError();
+}
+
+}  // namespace tk

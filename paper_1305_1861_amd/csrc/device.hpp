@@ -41,8 +41,12 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t key, int shift, uint32_t m
     return (uint32_t)(key >> shift) & mask;
 }
 __device__ __forceinline__ uint32_t digit_of(const Key2 &key, int shift, uint32_t mask) {
-    return shift >= 64 ? ((uint32_t)(key.hi >> (shift - 64)) & mask)
-                       : (uint32_t)(key.lo >> shift) & mask;
+    if (shift >= 64)
+        return (uint32_t)(key.hi >> (shift - 64)) & mask;
+    if (shift == 0)
+        return (uint32_t)key.lo & mask;
+    // a digit may straddle the two words
+    return (uint32_t)((key.lo >> shift) | (key.hi << (64 - shift))) & mask;
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -107,5 +111,74 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *to
     __syncthreads();  // s_wave / s_total may be reused by the next call
     return r;
 }
+
+// ---------------------------------------------------------------------------
+// Canonical key of a k-mer window (paper §2.1, k-mer extraction): the window
+// ending at base p = 32w + t is a contiguous 2k-bit field of the big-endian
+// concatenation of packed words (first base most significant); the reverse
+// complement is the complemented field with its 2-bit groups reversed; the
+// key is the smaller of the two.
+// ---------------------------------------------------------------------------
+// Forward/reverse-complement extraction of the window ending at base p.
+// k <= 31: one-word key.
+__device__ __forceinline__ uint64_t window_key1(const uint64_t *__restrict__ packed, uint64_t w, uint32_t t, int k) {
+    const uint64_t w0 = packed[w];
+    const uint64_t w1 = w ? packed[w - 1] : 0;
+    const uint32_t s = 62 - 2 * t;  // bit of the window's last base in w0
+    const uint64_t cat = s ? (w0 >> s) | (w1 << (64 - s)) : w0;
+    const uint64_t fwd = cat & ((1ull << (2 * k)) - 1);
+    const uint64_t rc = ~group_reverse(fwd) >> (64 - 2 * k);
+    return fwd < rc ? fwd : rc;
+}
+
+// 32 <= k <= 63: two-word key {hi, lo}.
+__device__ __forceinline__ Key2 window_key2(const uint64_t *__restrict__ packed, uint64_t w, uint32_t t, int k) {
+    const uint64_t w0 = packed[w];
+    const uint64_t w1 = w ? packed[w - 1] : 0;
+    const uint64_t w2 = w > 1 ? packed[w - 2] : 0;
+    const uint32_t s = 62 - 2 * t;
+    uint64_t lo, hi;
+    if (s) {
+        lo = (w0 >> s) | (w1 << (64 - s));
+        hi = (w1 >> s) | (w2 << (64 - s));
+    } else {
+        lo = w0;
+        hi = w1;
+    }
+    const int hb = 2 * k - 64;  // bits of the key in hi, 0..62
+    hi &= (1ull << hb) - 1;
+    // reverse complement of the 2k-bit value: reverse the 64 groups of the
+    // 128-bit word, complement, shift right by 128 - 2k
+    const uint64_t a_hi = ~group_reverse(lo);
+    const uint64_t a_lo = ~group_reverse(hi);
+    const int sh = 128 - 2 * k;  // 2..64
+    uint64_t rlo, rhi;
+    if (sh == 64) {
+        rlo = a_hi;
+        rhi = 0;
+    } else {
+        rlo = (a_lo >> sh) | (a_hi << (64 - sh));
+        rhi = a_hi >> sh;
+    }
+    const bool fwd_smaller = hi < rhi || (hi == rhi && lo <= rlo);
+    return fwd_smaller ? Key2{hi, lo} : Key2{rhi, rlo};
+}
+
+template <bool TWO>
+struct KeyOf;
+template <>
+struct KeyOf<false> {
+    using type = uint64_t;
+    __device__ __forceinline__ static uint64_t get(const uint64_t *packed, uint64_t w, uint32_t t, int k) {
+        return window_key1(packed, w, t, k);
+    }
+};
+template <>
+struct KeyOf<true> {
+    using type = Key2;
+    __device__ __forceinline__ static Key2 get(const uint64_t *packed, uint64_t w, uint32_t t, int k) {
+        return window_key2(packed, w, t, k);
+    }
+};
 
 }  // namespace tk

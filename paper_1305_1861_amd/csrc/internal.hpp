@@ -6,6 +6,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <type_traits>
+
 namespace tk {
 
 // Device counters of one counting call (zeroed before the call).
@@ -23,7 +26,7 @@ inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ---- pack.hip -------------------------------------------------------------
-// starts: n_words uint32, must be zero on entry.
+// starts: n_words uint32, must be zero on entry.  n_windows may be null.
 hipError_t launch_pack(const uint8_t *bases, const uint64_t *offsets, uint64_t n_bases,
                        uint64_t n_reads, int k, uint64_t *packed, uint32_t *valid,
                        uint32_t *starts, unsigned long long *n_windows, hipStream_t stream);
@@ -43,6 +46,60 @@ hipError_t launch_screen(const BloomArgs &a, int grid, hipStream_t stream);
 // screen = false collects every valid window (c = 1).
 hipError_t launch_collect(const BloomArgs &a, bool screen, void *keys, uint64_t capacity,
                           unsigned long long *n_collected, int grid, hipStream_t stream);
+
+// ---- partition.hip --------------------------------------------------------
+// One stable radix pass on key bits [shift, shift + bits), bits <= 10.  The
+// source is either every window of the packed reads (from_windows: element =
+// base position, n_elems = n_words * 32) or a key array of n_elems keys.
+struct PartArgs {
+    const uint64_t *packed;
+    const uint32_t *valid;
+    const void *keys_in;
+    uint64_t n_elems;
+    int k;
+    int shift, bits;
+    uint64_t n_chunks;      // set by the pass
+    const uint32_t *n_dev;  // if set, the element count is min(n_elems, *n_dev)
+};
+size_t partition_scratch_words(uint64_t n_elems, int key_words);
+// *total (device) receives the number of keys written.
+hipError_t partition_pass(const PartArgs &a, bool from_windows, void *out, uint32_t *scratch, size_t scratch_words,
+                          uint32_t *total, hipStream_t stream);
+
+// ---- bucket.hip -----------------------------------------------------------
+struct BucketArgs {
+    const void *keys;         // keys ordered by bucket (top D bits)
+    const uint32_t *n_dev;    // number of keys (device)
+    int k, D;
+    uint32_t c;
+    int screen;
+    uint32_t beta;
+    const uint64_t *table;
+    uint32_t table_bits;
+    void *gap_keys;        // records of a bucket start at the bucket's first index
+    uint32_t *gap_counts;
+    uint32_t *rec_start;   // per bucket: first index, number of records
+    uint32_t *rec_nout;
+    unsigned long long *wg_stats;  // per workgroup: collected, runs, singletons, below c
+    uint32_t *fb_list;     // oversized buckets: (bucket, start, size)
+    uint32_t *fb_count;
+    uint32_t fb_cap;
+};
+int bucket_grid();
+int bucket_capacity(int key_words);
+hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream);
+hipError_t launch_fb_screen(const void *keys, uint64_t n, int key_words, const uint64_t *table, uint32_t table_bits,
+                            uint64_t *filter, uint64_t nb, hipStream_t stream);
+hipError_t launch_fb_collect(const void *keys, uint64_t n, int key_words, const uint64_t *table, uint32_t table_bits,
+                             const uint64_t *filter, uint64_t nb, bool screen, void *out,
+                             unsigned long long *n_out, hipStream_t stream);
+hipError_t launch_fb_fold(const DevCounters *c, uint32_t bucket, uint32_t *rec_nout, unsigned long long *fb_stats,
+                          hipStream_t stream);
+hipError_t launch_gather(const uint32_t *rec_start, const uint32_t *rec_nout, const uint32_t *rec_off,
+                         uint64_t n_buckets, const uint64_t *gap_keys, const uint32_t *gap_counts, int key_words,
+                         uint64_t *out_keys, uint32_t *out_counts, hipStream_t stream);
+hipError_t launch_stats(const unsigned long long *wg_stats, uint64_t n_wg, const unsigned long long *fb_stats,
+                        const uint32_t *totals, DevCounters *ctr, hipStream_t stream);
 
 // ---- scan.hip -------------------------------------------------------------
 // Exclusive prefix sum of n uint32 values (in may equal out).  *total (device)

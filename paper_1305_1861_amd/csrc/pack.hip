@@ -136,6 +136,8 @@ __global__ __launch_bounds__(PACK_THREADS) void pack_kernel(const uint8_t *__res
         valid[w] = vbits;
     }
     // valid windows of the block -> one atomic per block
+    if (!n_windows)
+        return;
     uint64_t cnt = wave_sum64((uint64_t)__popc(vbits));
     __shared__ unsigned long long s_cnt[PACK_THREADS / WAVE];
     if (lane_id() == 0)

@@ -44,6 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_default_options(lib):
     o = tk.tk_default_options()
     assert (o.bloom_beta, o.bloom_table_bits, o.bloom_bits, o.bloom_seed, o.bloom_blocks) == (4, 10, 2, 1305, 0)
+    assert o.part_bits == -1 and o.flags == 0
 
 
 def test_strerror(lib):
@@ -53,7 +54,7 @@ def test_strerror(lib):
 
 
 def test_pattern_table_matches_oracle(oracle_lib, lib):
-    for bits, table_bits, seed in [(2, 10, 1305), (1, 4, 7), (3, 12, 99), (16, 6, 5)]:
+    for bits, table_bits, seed in [(2, 10, 1305), (1, 4, 7), (3, 9, 99), (16, 6, 5)]:
         got = tk.tk_pattern_table(dict(bloom_bits=bits, bloom_table_bits=table_bits, bloom_seed=seed))
         want = oracle_lib.pattern_masks(1 << table_bits, bits, seed)
         assert (got == want).all()
@@ -66,6 +67,24 @@ def test_bloom_size_rule_matches_oracle(oracle_lib, lib, n_bases, n_reads, k):
         assert tk.tk_bloom_blocks(n_bases, n_reads, k, dict(bloom_beta=beta)) == \
             oracle_lib.default_blocks(n_bases, n_reads, k, beta)
     assert tk.tk_bloom_blocks(n_bases, n_reads, k, dict(bloom_blocks=12345)) == 12345
+
+
+@pytest.mark.parametrize("n_bases,n_reads,k", [(0, 0, 31), (10_000_000, 100_000, 31), (99, 1, 63),
+                                               (5, 5, 2), (1_500_000_000, 15_000_000, 31),
+                                               (800_000_000, 5_333_333, 63), (4095, 1, 1), (1 << 31, 1, 40)])
+def test_partition_rule_matches_oracle(oracle_lib, lib, n_bases, n_reads, k):
+    assert tk.tk_part_bits(n_bases, n_reads, k) == oracle_lib.partition_bits(n_bases, n_reads, k)
+    for explicit in (0, 3, 20):
+        assert tk.tk_part_bits(n_bases, n_reads, k, dict(part_bits=explicit)) == \
+            oracle_lib.partition_bits(n_bases, n_reads, k, explicit)
+
+
+def test_partition_rule_values(lib):
+    # the workloads: about 2^11 (one-word keys) or 2^10 (two-word keys) windows per bucket
+    assert tk.tk_part_bits(1_500_000_000, 15_000_000, 31) == 19
+    assert tk.tk_part_bits(10_000_000, 100_000, 31) == 12
+    assert tk.tk_part_bits(800_000_000, 5_333_333, 63) == 19
+    assert tk.tk_part_bits(100, 1, 1) == 0
 
 
 def test_workspace_size_grows(lib):
@@ -108,7 +127,8 @@ def test_overflow_rejected(lib):
 
 
 def test_bad_options_rejected(lib):
-    for bad in (dict(bloom_table_bits=13), dict(bloom_bits=17), dict(bloom_beta=5000)):
+    for bad in (dict(bloom_table_bits=11), dict(bloom_bits=17), dict(bloom_beta=5000),
+                dict(bloom_beta=33), dict(part_bits=21), dict(part_bits=-2)):
         with pytest.raises(tk.TurtleError) as e:
             tk.tk_workspace_size(1000, 10, 31, 2, bad)
         assert e.value.status == tk.TK_EINVAL

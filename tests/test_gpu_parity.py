@@ -66,8 +66,23 @@ def assert_same(keys, counts, res, k):
     assert (counts.astype(np.uint64) == res.count).all()
 
 
-def check_against_oracle(tk, oracle_lib, bases, offsets, k, c, shift=0, bloom=True):
-    keys, counts, r = gpu_count(tk, bases, offsets, k, c, shift=shift)
+def expected_bloom(oracle_lib, bases, offsets, k, opts=None):
+    """The oracle's Bloom statistics for the filter layout these options select."""
+    opts = dict(opts or {})
+    n_reads = offsets.size - 1
+    beta = opts.get("bloom_beta", 4)
+    tb = 1 << opts.get("bloom_table_bits", 10)
+    bits = opts.get("bloom_bits", 2)
+    seed = opts.get("bloom_seed", 1305)
+    if opts.get("flags", 0) & 2:  # one global filter
+        nb = opts.get("bloom_blocks") or oracle_lib.default_blocks(bases.size, n_reads, k, beta)
+        return oracle_lib.bloom_model(bases, offsets, k, nb, tb, bits, seed), nb, -1
+    D = oracle_lib.partition_bits(bases.size, n_reads, k, opts.get("part_bits", -1))
+    return oracle_lib.bloom_model_buckets(bases, offsets, k, D, beta, tb, bits, seed), 0, D
+
+
+def check_against_oracle(tk, oracle_lib, bases, offsets, k, c, shift=0, opts=None):
+    keys, counts, r = gpu_count(tk, bases, offsets, k, c, opts=opts, shift=shift)
     ora = oracle_lib.kmer_count(bases, offsets, k, c)
     assert_same(keys, counts, ora, k)
     assert r.n_windows == ora.n_windows
@@ -75,15 +90,16 @@ def check_against_oracle(tk, oracle_lib, bases, offsets, k, c, shift=0, bloom=Tr
         assert r.n_collected == ora.n_windows
         assert r.n_distinct == ora.n_distinct
         assert r.bloom_blocks == 0
-    elif bloom:
-        n_reads = offsets.size - 1
-        nb = oracle_lib.default_blocks(bases.size, n_reads, k)
-        assert r.bloom_blocks == nb
-        m = oracle_lib.bloom_model(bases, offsets, k, nb)
+    else:
+        m, nb, D = expected_bloom(oracle_lib, bases, offsets, k, opts)
+        assert r.bloom_blocks == nb and r.part_bits == D
         assert (r.n_collected, r.n_distinct, r.n_singletons) == (m.n_cand_occ, m.n_cand, m.n_cand_single)
         all2 = oracle_lib.kmer_count(bases, offsets, k, 2)
         assert r.n_below_c == int(((all2.count >= 2) & (all2.count < c)).sum())
     return r
+
+
+GLOBAL = dict(flags=2)
 
 
 def library(seed, n_reads, max_len, k, dup=0.3):
@@ -271,13 +287,14 @@ def test_host_entry_point(tk, oracle_lib):
         assert r.n_windows == ora.n_windows
 
 
-def test_repeat_runs_identical(tk):
+@pytest.mark.parametrize("opts", [None, GLOBAL])
+def test_repeat_runs_identical(tk, opts):
     """The screen's outcome does not depend on the order atomics land in."""
     lib = readsim.small_library(scale=0.2)
-    case("repeatability")
+    case(f"repeatability {opts}")
     first = None
     for _ in range(3):
-        keys, counts, r = gpu_count(tk, lib.bases, lib.offsets, 31, 2)
+        keys, counts, r = gpu_count(tk, lib.bases, lib.offsets, 31, 2, opts=opts)
         cur = (keys.tobytes(), counts.tobytes(), r.n_collected, r.n_distinct, r.n_singletons)
         if first is None:
             first = cur
@@ -285,19 +302,46 @@ def test_repeat_runs_identical(tk):
 
 
 @pytest.mark.parametrize("opts", [dict(bloom_beta=1), dict(bloom_bits=1, bloom_table_bits=4),
-                                  dict(bloom_blocks=3), dict(bloom_bits=5, bloom_seed=77)])
+                                  dict(bloom_bits=5, bloom_seed=77), dict(bloom_beta=32),
+                                  dict(part_bits=0), dict(part_bits=3), dict(part_bits=16),
+                                  dict(GLOBAL, bloom_beta=1), dict(GLOBAL, bloom_blocks=3),
+                                  dict(GLOBAL, bloom_bits=5, bloom_seed=77)])
 def test_bloom_options(tk, oracle_lib, opts):
-    """Other filter sizes and tables: same exact answer, model-exact statistics."""
+    """Other filter layouts, sizes and tables: same exact answer, model-exact statistics."""
     bases, offsets = library(4242, 800, 160, 31, dup=0.5)
     case(f"bloom options {opts}")
-    keys, counts, r = gpu_count(tk, bases, offsets, 31, 2, opts=opts)
-    ora = oracle_lib.kmer_count(bases, offsets, 31, 2)
-    assert_same(keys, counts, ora, 31)
-    nb = opts.get("bloom_blocks") or oracle_lib.default_blocks(bases.size, offsets.size - 1, 31,
-                                                               opts.get("bloom_beta", 4))
-    m = oracle_lib.bloom_model(bases, offsets, 31, nb, 1 << opts.get("bloom_table_bits", 10),
-                               opts.get("bloom_bits", 2), opts.get("bloom_seed", 1305))
-    assert (r.n_collected, r.n_distinct, r.n_singletons) == (m.n_cand_occ, m.n_cand, m.n_cand_single)
+    check_against_oracle(tk, oracle_lib, bases, offsets, 31, 2, opts=opts)
+
+
+@pytest.mark.parametrize("k", [5, 31, 32, 63])
+@pytest.mark.parametrize("c", [1, 2, 3])
+def test_global_filter_path(tk, oracle_lib, k, c):
+    bases, offsets = library(300 + 3 * k + c, 500, 2 * k + 100, k)
+    case(f"global filter k={k} c={c}")
+    check_against_oracle(tk, oracle_lib, bases, offsets, k, c, opts=GLOBAL)
+
+
+@pytest.mark.parametrize("k,part_bits", [(31, 0), (31, 2), (63, 0), (63, 3), (21, 1)])
+@pytest.mark.parametrize("c", [1, 2])
+def test_oversized_buckets_fallback(tk, oracle_lib, k, part_bits, c):
+    """Buckets larger than the LDS capacity go through the global-memory
+    fallback with the same per-bucket filter rule."""
+    bases, offsets = library(900 + k + part_bits, 3000, 2 * k + 120, k, dup=0.4)
+    case(f"fallback k={k} part_bits={part_bits} c={c} n_bases={bases.size}")
+    r = check_against_oracle(tk, oracle_lib, bases, offsets, k, c, opts=dict(part_bits=part_bits))
+    assert r.n_fallback >= 1
+
+
+def test_bucket_capacity_edges(tk, oracle_lib):
+    """Buckets of exactly the register capacity and one more."""
+    rng = np.random.default_rng(77)
+    for n_windows in (7679, 7680, 7681, 3584, 3585):
+        for k in (31, 63):
+            L = n_windows + k - 1
+            read = "".join("ACGT"[x] for x in rng.integers(0, 4, L))
+            bases, offsets = readsim.from_strings([read, read[: L // 2]])
+            case(f"capacity edge windows={n_windows} k={k}")
+            check_against_oracle(tk, oracle_lib, bases, offsets, k, 2, opts=dict(part_bits=0))
 
 
 # --------------------------------------------------------------------------
@@ -309,6 +353,8 @@ def test_small_library_full(tk, oracle_lib):
     case(f"{lib.name} full n_bases={lib.n_bases}")
     r = check_against_oracle(tk, oracle_lib, lib.bases, lib.offsets, lib.k, lib.c)
     assert r.n_windows == lib.n_reads * (100 - 31 + 1)
+    case(f"{lib.name} full, global filter")
+    check_against_oracle(tk, oracle_lib, lib.bases, lib.offsets, lib.k, lib.c, opts=GLOBAL)
 
 
 def test_large_library_reduced(tk, oracle_lib):

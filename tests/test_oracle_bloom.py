@@ -180,3 +180,47 @@ def test_default_block_rule(oracle_lib):
     assert oracle_lib.default_blocks(100, 1, 31) == math.ceil(4 * 70 / 256)
     assert oracle_lib.default_blocks(10_000_000, 100_000, 31) == math.ceil(4 * 7_000_000 / 256)
     assert oracle_lib.default_blocks(10, 5, 31) == 1
+
+
+def test_bucket_model_single_bucket_equals_global(oracle_lib):
+    """With D = 0 there is one bucket whose filter is sized from all windows."""
+    rng = np.random.default_rng(21)
+    lo = rng.integers(0, 1 << 62, size=5000, dtype=np.int64).astype(np.uint64)
+    lo = np.concatenate([lo, lo[:2000], lo[:300]])
+    hi = np.zeros_like(lo)
+    for beta in (1, 4, 9):
+        a = oracle_lib.bloom_model_buckets_keys(hi, lo, 31, 0, beta)
+        nb = max(1, -(-beta * lo.size // 256))
+        b = oracle_lib.bloom_model_keys(hi, lo, False, nb)
+        assert (a.n_cand_occ, a.n_cand, a.n_cand_single) == (b.n_cand_occ, b.n_cand, b.n_cand_single)
+
+
+@pytest.mark.parametrize("k,D", [(31, 6), (63, 9), (33, 4), (5, 10), (2, 4)])
+def test_bucket_model_is_sum_over_buckets(oracle_lib, k, D):
+    """Grouping by the top D bits (done here in Python) and summing the
+    one-filter model per group reproduces the per-bucket model."""
+    bases, offsets = readsim.random_reads(700 + k + D, 400, 0, 3 * k + 10, 0.01, 0.0, 0.0)
+    reads = readsim.to_strings(bases, offsets)
+    reads = reads + reads[:150]
+    keys, hi, lo = _window_keys(reads, k)
+    beta = 3
+    want = [0, 0, 0]
+    groups = {}
+    for x in keys:
+        groups.setdefault(x >> (2 * k - D), []).append(x)
+    for g in groups.values():
+        gh = np.array([x >> 64 for x in g], np.uint64)
+        gl = np.array([x & M64 for x in g], np.uint64)
+        nb = max(1, -(-beta * len(g) // 256))
+        st = oracle_lib.bloom_model_keys(gh, gl, k > 31, nb)
+        want[0] += st.n_cand_occ
+        want[1] += st.n_cand
+        want[2] += st.n_cand_single
+    got = oracle_lib.bloom_model_buckets_keys(hi, lo, k, D, beta)
+    assert [got.n_cand_occ, got.n_cand, got.n_cand_single] == want
+    b, o = readsim.from_strings(reads)
+    lib_level = oracle_lib.bloom_model_buckets(b, o, k, D, beta)
+    assert (lib_level.n_cand_occ, lib_level.n_cand, lib_level.n_cand_single) == tuple(want)
+    # every key seen at least twice is a candidate
+    mult = Counter(keys)
+    assert got.n_cand_occ >= sum(v for v in mult.values() if v >= 2)
