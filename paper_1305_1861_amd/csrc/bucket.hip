@@ -87,16 +87,22 @@ __device__ __forceinline__ Key2 sentinel<Key2>() { return Key2{~0ull, ~0ull}; }
 __device__ __forceinline__ uint32_t wave_count(uint64_t ball) { return (uint32_t)__popcll(ball); }
 
 template <typename K>
-__global__ __launch_bounds__(BK_THREADS, 2) void bucket_kernel(BucketArgs a) {
+__global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
     constexpr int ITEMS = BkItems<K>::value;
     constexpr int CAP = BK_THREADS * ITEMS;
+    // filter blocks that fit in the exchange buffer
+    constexpr uint32_t FMAX = (uint32_t)((CAP + 2) * sizeof(K) / 64);
     __shared__ uint64_t s_table[BK_TABLE];
-    __shared__ uint16_t s_cnt[BK_WAVES][BK_BINS];
-    // exchange buffer with a sentinel slot on each side; holds the filter
+    __shared__ __align__(16) uint16_t s_cnt[BK_WAVES][BK_BINS];
+    // exchange buffer with a sentinel slot on each side; holds the filters
     // during screen/collect
     __shared__ __align__(16) K s_exs[CAP + 2];
+    __shared__ uint16_t s_start[CAP + 1];  // first index of each bucket of the group
+    __shared__ uint16_t s_fo[CAP + 1];     // first filter block of each bucket
+    __shared__ uint32_t s_part[ITEMS][BK_WAVES];
     __shared__ uint32_t s_w[2][BK_WAVES];
     __shared__ unsigned long long s_pos[2];
+    __shared__ uint32_t s_u[4];
 
     K *const s_ex = s_exs + 1;
     uint64_t *s_filter = reinterpret_cast<uint64_t *>(s_exs);
@@ -119,7 +125,6 @@ __global__ __launch_bounds__(BK_THREADS, 2) void bucket_kernel(BucketArgs a) {
     uint64_t pos = s_pos[0];
     const uint64_t end = s_pos[1];
     const int SB = 2 * a.k - a.D;  // key bits below the bucket digit
-    const int passes = SB > 0 ? (SB + BK_SORT_BITS - 1) / BK_SORT_BITS : 1;
     unsigned long long st_coll = 0, st_runs = 0, st_single = 0, st_below = 0;
 
     while (pos < end) {
@@ -131,66 +136,135 @@ __global__ __launch_bounds__(BK_THREADS, 2) void bucket_kernel(BucketArgs a) {
         const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
         const uint32_t lane = (uint32_t)tid % WAVE;
         const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-        // ---- bucket of key[pos]; load it into registers (item-major) ----
-        const uint32_t d = bucket_of(keys[pos], a.k, a.D);
+
+        // ---- a group of whole buckets: load up to CAP keys (item-major) ----
+        const uint32_t n_load = (uint32_t)min<uint64_t>(CAP, end - pos);
+        const int n_items = (int)((n_load + BK_THREADS - 1) / BK_THREADS);
+        const uint32_t d0 = bucket_of(keys[pos], a.k, a.D);
+        // does the last loaded bucket continue past the loaded keys?
+        bool incomplete = false;
+        if (pos + n_load < end)
+            incomplete = bucket_of(keys[pos + n_load], a.k, a.D) == bucket_of(keys[pos + n_load - 1], a.k, a.D);
         K key[ITEMS];
-        uint32_t inm = 0;  // bit i: item i holds a window of this bucket
-        uint32_t n_s = 0;
-        bool more = true;
+        uint32_t rb[ITEMS];  // bucket index within the group
+        uint32_t hm = 0;     // bit i: item i starts a bucket
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
-            if (more) {  // uniform: the previous item batch was all in this bucket
-                const uint64_t e = pos + (uint64_t)i * BK_THREADS + tid;
-                bool in = false;
-                if (e < end) {
-                    key[i] = keys[e];
-                    in = bucket_of(key[i], a.k, a.D) == d;
+            if (i < n_items) {
+                const uint32_t e = (uint32_t)i * BK_THREADS + tid;
+                bool head = false;
+                if (e < n_load) {
+                    key[i] = keys[pos + e];
+                    head = e == 0 || bucket_of(keys[pos + e - 1], a.k, a.D) != bucket_of(key[i], a.k, a.D);
                 }
-                inm |= (uint32_t)in << i;
-                const uint32_t c = (uint32_t)__syncthreads_count(in);
-                n_s += c;
-                more = c == BK_THREADS;
+                hm |= (uint32_t)head << i;
+                const uint64_t hb = __ballot(head);
+                rb[i] = (uint32_t)__popcll(hb & lt) + (uint32_t)head;  // inclusive, within the wave
+                if (lane == 0)
+                    s_part[i][wave] = (uint32_t)__popcll(hb);
             }
         }
-        if (more) {
-            // every loaded key is in this bucket: it may be larger than the
-            // registers hold; measure it and hand it to the fallback path
+        __syncthreads();
+        if (tid < WAVE) {
+            // exclusive prefix of the head counts in (item, wave) order
+            const int m = n_items * BK_WAVES;
+            uint32_t v0 = 2 * tid < m ? (&s_part[0][0])[2 * tid] : 0;
+            uint32_t v1 = 2 * tid + 1 < m ? (&s_part[0][0])[2 * tid + 1] : 0;
+            const uint32_t inc = wave_inclusive_sum(v0 + v1);
+            const uint32_t ex = inc - v0 - v1;
+            if (2 * tid < m)
+                (&s_part[0][0])[2 * tid] = ex;
+            if (2 * tid + 1 < m)
+                (&s_part[0][0])[2 * tid + 1] = ex + v0;
+            if (tid == WAVE - 1)
+                s_u[0] = inc;  // number of buckets in the loaded keys
+        }
+        __syncthreads();
+        const uint32_t R = s_u[0];
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            if (i < n_items) {
+                const uint32_t e = (uint32_t)i * BK_THREADS + tid;
+                rb[i] += s_part[i][wave];  // heads at positions <= e
+                if (e < n_load) {
+                    rb[i] -= 1;
+                    if ((hm >> i) & 1u)
+                        s_start[rb[i]] = (uint16_t)e;
+                }
+            }
+        }
+        if (tid == 0)
+            s_start[R] = (uint16_t)n_load;
+        __syncthreads();
+
+        // ---- per-bucket filter sizes, their offsets, and where the group ends ----
+        // thread t owns buckets [t * rpt, (t + 1) * rpt)
+        const uint32_t rpt = (R + BK_THREADS - 1) / BK_THREADS;
+        uint32_t nb_sum = 0;
+        for (uint32_t j = 0; j < rpt; j++) {
+            const uint32_t r = tid * rpt + j;
+            if (r < R) {
+                const uint32_t ns = (uint32_t)s_start[r + 1] - s_start[r];
+                nb_sum += a.screen ? max(1u, (a.beta * ns + 255) / 256) : 0u;
+            }
+        }
+        uint32_t nb_total;
+        uint32_t fo = block_exclusive_sum<BK_THREADS>(nb_sum, &nb_total);
+        uint32_t fits = 0;
+        for (uint32_t j = 0; j < rpt; j++) {
+            const uint32_t r = tid * rpt + j;
+            if (r < R) {
+                const uint32_t ns = (uint32_t)s_start[r + 1] - s_start[r];
+                const uint32_t nb = a.screen ? max(1u, (a.beta * ns + 255) / 256) : 0u;
+                s_fo[r] = (uint16_t)min(fo, 0xFFFFu);
+                const bool whole = !(incomplete && r + 1 == R);
+                fits += (whole && fo + nb <= FMAX) ? 1u : 0u;
+                fo += nb;
+            }
+        }
+        uint32_t r_cut;
+        block_exclusive_sum<BK_THREADS>(fits, &r_cut);
+        if (r_cut == 0) {
+            // the first bucket alone exceeds the registers: fallback path
             if (tid == 0) {
-                const uint64_t e = bucket_end(keys, end, pos + CAP, d, a.k, a.D);
+                const uint64_t e = bucket_end(keys, end, pos + n_load, d0, a.k, a.D);
                 const uint64_t ns = e - pos;
                 s_pos[0] = e;
-                if (ns > (uint64_t)CAP) {
-                    const uint32_t slot = atomicAdd(a.fb_count, 1u);
-                    if (slot < a.fb_cap) {
-                        a.fb_list[3 * slot + 0] = d;
-                        a.fb_list[3 * slot + 1] = (uint32_t)pos;
-                        a.fb_list[3 * slot + 2] = (uint32_t)ns;
-                    }
-                    a.rec_start[d] = (uint32_t)pos;
+                const uint32_t slot = atomicAdd(a.fb_count, 1u);
+                if (slot < a.fb_cap) {
+                    a.fb_list[3 * slot + 0] = d0;
+                    a.fb_list[3 * slot + 1] = (uint32_t)pos;
+                    a.fb_list[3 * slot + 2] = (uint32_t)ns;
                 }
+                a.rec_start[d0] = (uint32_t)pos;
             }
             __syncthreads();
-            const uint64_t e = s_pos[0];
+            pos = s_pos[0];
             __syncthreads();
-            if (e - pos > (uint64_t)CAP) {
-                pos = e;
-                continue;
-            }
-            // exactly CAP keys: fall through and process in LDS
+            continue;
         }
+        const uint32_t n_sb = r_cut == R ? n_load : (uint32_t)s_start[r_cut];
+        const uint32_t blocks_cut = r_cut == R ? nb_total : (uint32_t)s_fo[r_cut];
+        if (tid == 0)
+            s_fo[r_cut] = (uint16_t)blocks_cut;
+        // span of bucket ids in the group -> bits of the bucket part of the sort key
+        const uint32_t d_last = bucket_of(keys[pos + n_sb - 1], a.k, a.D);
+        const uint32_t span = d_last - d0;
+        const int RB = span ? 32 - __clz(span) : 0;
+        __syncthreads();
 
-        // ---- screen and collect (two-plane filter of this bucket) ----
-        uint32_t sv = inm;  // bit i: item i survives the screen
+        // ---- screen and collect, each bucket against its own filter ----
+        uint32_t sv = 0;  // bit i: item i survives
         if (a.screen) {
-            const uint32_t nb = max(1u, (uint32_t)(((uint64_t)a.beta * n_s + 255) / 256));
-            for (uint32_t i = tid; i < nb * 8; i += BK_THREADS)
+            for (uint32_t i = tid; i < blocks_cut * 8; i += BK_THREADS)
                 s_filter[i] = 0;
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < ITEMS; i++) {
-                if ((inm >> i) & 1u) {
+                if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb) {
+                    const uint32_t f0 = s_fo[rb[i]], nb = (uint32_t)s_fo[rb[i] + 1] - f0;
                     const uint64_t h = key_hash(key[i]);
-                    uint64_t *b = s_filter + (uint64_t)__umul64hi(h, nb) * 8;
+                    uint64_t *b = s_filter + ((uint64_t)f0 + __umul64hi(h, nb)) * 8;
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
                         const uint64_t m = s_table[(h >> (w * a.table_bits)) & tmask];
@@ -201,12 +275,12 @@ __global__ __launch_bounds__(BK_THREADS, 2) void bucket_kernel(BucketArgs a) {
                 }
             }
             __syncthreads();
-            sv = 0;
 #pragma unroll
             for (int i = 0; i < ITEMS; i++) {
-                if ((inm >> i) & 1u) {
+                if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb) {
+                    const uint32_t f0 = s_fo[rb[i]], nb = (uint32_t)s_fo[rb[i] + 1] - f0;
                     const uint64_t h = key_hash(key[i]);
-                    const uint64_t *b = s_filter + (uint64_t)__umul64hi(h, nb) * 8 + 4;
+                    const uint64_t *b = s_filter + ((uint64_t)f0 + __umul64hi(h, nb)) * 8 + 4;
                     bool all = true;
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
@@ -217,33 +291,52 @@ __global__ __launch_bounds__(BK_THREADS, 2) void bucket_kernel(BucketArgs a) {
                 }
             }
             __syncthreads();  // the filter area becomes the exchange buffer
+        } else {
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++)
+                if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb)
+                    sv |= 1u << i;
         }
 
-        // ---- LSD radix sort of the survivors on bits [0, SB) ----
+        // ---- LSD radix sort of the survivors on (bucket - d0, key bits below
+        // the bucket digit), 9-bit digits ----
+        const int TB = SB + RB;
+        const int passes = TB > 0 ? (TB + BK_SORT_BITS - 1) / BK_SORT_BITS : 1;
+        int act_items = n_items;
         uint32_t n_surv = 0;
         for (int p = 0; p < passes; p++) {
             const int shift = p * BK_SORT_BITS;
-            const int bits = SB - shift < BK_SORT_BITS ? SB - shift : BK_SORT_BITS;
-            const uint32_t dmask = (1u << bits) - 1u;
-            for (int i = tid; i < BK_WAVES * BK_BINS; i += BK_THREADS)
-                (&s_cnt[0][0])[i] = 0;
+            const int bits = TB - shift < BK_SORT_BITS ? TB - shift : BK_SORT_BITS;
+            const int lowbits = shift < SB ? min(bits, SB - shift) : 0;
+            const int hshift = shift > SB ? shift - SB : 0;
+            for (int i = tid; i < BK_WAVES * BK_BINS / 4; i += BK_THREADS)
+                reinterpret_cast<uint64_t *>(&s_cnt[0][0])[i] = 0;
             __syncthreads();
             uint32_t rd[ITEMS];  // (rank << 9) | digit
 #pragma unroll
             for (int i = 0; i < ITEMS; i++) {
-                const bool act = (sv >> i) & 1u;
-                const uint32_t dg = act ? digit_of(key[i], shift, dmask) : 0u;
-                uint64_t peers = __ballot(act);
-                for (int b = 0; b < bits; b++) {
-                    const bool bit = (dg >> b) & 1u;
-                    const uint64_t m = __ballot(bit);
-                    peers &= bit ? m : ~m;
+                if (i < act_items) {
+                    const bool act = (sv >> i) & 1u;
+                    uint32_t dg = 0;
+                    if (act) {
+                        if (lowbits)
+                            dg = digit_of(key[i], shift, (1u << lowbits) - 1u);
+                        if (bits > lowbits)
+                            dg |= (((bucket_of(key[i], a.k, a.D) - d0) >> hshift) & ((1u << (bits - lowbits)) - 1u))
+                                  << lowbits;
+                    }
+                    uint64_t peers = __ballot(act);
+                    for (int b = 0; b < bits; b++) {
+                        const bool bit = (dg >> b) & 1u;
+                        const uint64_t m = __ballot(bit);
+                        peers &= bit ? m : ~m;
+                    }
+                    const uint32_t below = __popcll(peers & lt);
+                    const uint32_t prior = s_cnt[wave][dg];
+                    if (act && below == 0)
+                        s_cnt[wave][dg] = (uint16_t)(prior + (uint32_t)__popcll(peers));
+                    rd[i] = ((prior + below) << BK_SORT_BITS) | dg;
                 }
-                const uint32_t below = __popcll(peers & lt);
-                const uint32_t prior = s_cnt[wave][dg];
-                if (act && below == 0)
-                    s_cnt[wave][dg] = (uint16_t)(prior + (uint32_t)__popcll(peers));
-                rd[i] = ((prior + below) << BK_SORT_BITS) | dg;
             }
             __syncthreads();
             {
@@ -263,18 +356,21 @@ __global__ __launch_bounds__(BK_THREADS, 2) void bucket_kernel(BucketArgs a) {
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < ITEMS; i++)
-                if ((sv >> i) & 1u)
+                if (i < act_items && ((sv >> i) & 1u))
                     s_ex[s_cnt[wave][rd[i] & (BK_BINS - 1)] + (rd[i] >> BK_SORT_BITS)] = key[i];
             __syncthreads();
             if (p + 1 < passes) {
                 // reload wave-striped: element (wave, item, lane) in order
+                act_items = (int)((n_surv + BK_THREADS - 1) / BK_THREADS);
                 sv = 0;
 #pragma unroll
                 for (int i = 0; i < ITEMS; i++) {
-                    const uint32_t e = (uint32_t)(wave * ITEMS + i) * WAVE + lane;
-                    if (e < n_surv) {
-                        key[i] = s_ex[e];
-                        sv |= 1u << i;
+                    if (i < act_items) {
+                        const uint32_t e = (uint32_t)(wave * act_items + i) * WAVE + lane;
+                        if (e < n_surv) {
+                            key[i] = s_ex[e];
+                            sv |= 1u << i;
+                        }
                     }
                 }
                 __syncthreads();
@@ -282,10 +378,10 @@ __global__ __launch_bounds__(BK_THREADS, 2) void bucket_kernel(BucketArgs a) {
         }
 
         // ---- run-length compaction of s_ex[0, n_surv) ----
-        // heads and tails in (wave, item, lane) order; the r-th head and the
-        // r-th tail delimit run r.  Run starts go to the bucket's slice of
-        // gap_counts (capacity n_s >= number of runs).
-        // sentinels: no key has all bits set (keys use at most 126 bits)
+        // positions in (wave, item, lane) order with n_it items per wave; the
+        // r-th head and the r-th tail delimit run r.  Run starts go to the
+        // group's slice of gap_counts (capacity n_sb >= number of runs).
+        const int n_it = (int)((n_surv + BK_THREADS - 1) / BK_THREADS);
         if (tid == 0) {
             s_ex[-1] = sentinel<K>();
             s_ex[n_surv] = sentinel<K>();
@@ -295,15 +391,17 @@ __global__ __launch_bounds__(BK_THREADS, 2) void bucket_kernel(BucketArgs a) {
         uint32_t nh = 0, nt = 0;
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
-            const uint32_t e = (uint32_t)(wave * ITEMS + i) * WAVE + lane;
-            bool h = false, t = false;
-            if (e < n_surv) {
-                const K x = s_ex[e];
-                h = s_ex[(int)e - 1] != x;
-                t = s_ex[e + 1] != x;
+            if (i < n_it) {
+                const uint32_t e = (uint32_t)(wave * n_it + i) * WAVE + lane;
+                bool h = false, t = false;
+                if (e < n_surv) {
+                    const K x = s_ex[e];
+                    h = s_ex[(int)e - 1] != x;
+                    t = s_ex[e + 1] != x;
+                }
+                nh += wave_count(__ballot(h));
+                nt += wave_count(__ballot(t));
             }
-            nh += wave_count(__ballot(h));
-            nt += wave_count(__ballot(t));
         }
         if (lane == 0) {
             s_w[0][wave] = nh;
@@ -318,29 +416,33 @@ __global__ __launch_bounds__(BK_THREADS, 2) void bucket_kernel(BucketArgs a) {
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
-            const uint32_t e = (uint32_t)(wave * ITEMS + i) * WAVE + lane;
-            const bool h = e < n_surv && s_ex[(int)e - 1] != s_ex[e];
-            const uint64_t hb = __ballot(h);
-            if (h)
-                gcnt[hbase + __popcll(hb & lt)] = e;
-            hbase += wave_count(hb);
+            if (i < n_it) {
+                const uint32_t e = (uint32_t)(wave * n_it + i) * WAVE + lane;
+                const bool h = e < n_surv && s_ex[(int)e - 1] != s_ex[e];
+                const uint64_t hb = __ballot(h);
+                if (h)
+                    gcnt[hbase + __popcll(hb & lt)] = e;
+                hbase += wave_count(hb);
+            }
         }
         __syncthreads();
         uint32_t cnt[ITEMS];
         uint32_t nk = 0, single = 0, below = 0;
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
-            const uint32_t e = (uint32_t)(wave * ITEMS + i) * WAVE + lane;
-            const bool t = e < n_surv && s_ex[e + 1] != s_ex[e];
-            const uint64_t tb = __ballot(t);
             cnt[i] = 0;
-            if (t) {
-                cnt[i] = e - gcnt[tbase + __popcll(tb & lt)] + 1;
-                single += cnt[i] == 1;
-                below += cnt[i] >= 2 && cnt[i] < a.c;
+            if (i < n_it) {
+                const uint32_t e = (uint32_t)(wave * n_it + i) * WAVE + lane;
+                const bool t = e < n_surv && s_ex[e + 1] != s_ex[e];
+                const uint64_t tb = __ballot(t);
+                if (t) {
+                    cnt[i] = e - gcnt[tbase + __popcll(tb & lt)] + 1;
+                    single += cnt[i] == 1;
+                    below += cnt[i] >= 2 && cnt[i] < a.c;
+                }
+                tbase += wave_count(tb);
+                nk += wave_count(__ballot(cnt[i] >= a.c));
             }
-            tbase += wave_count(tb);
-            nk += wave_count(__ballot(cnt[i] >= a.c));
         }
         __syncthreads();  // every run start has been read
         if (lane == 0)
@@ -353,26 +455,29 @@ __global__ __launch_bounds__(BK_THREADS, 2) void bucket_kernel(BucketArgs a) {
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
-            const bool keep = cnt[i] >= a.c;
-            const uint64_t kb = __ballot(keep);
-            if (keep) {
-                const uint32_t e = (uint32_t)(wave * ITEMS + i) * WAVE + lane;
-                const uint32_t o = kbase + (uint32_t)__popcll(kb & lt);
-                gap_keys[pos + o] = s_ex[e];
-                gcnt[o] = cnt[i];
+            if (i < n_it) {
+                const bool keep = cnt[i] >= a.c;
+                const uint64_t kb = __ballot(keep);
+                if (keep) {
+                    const uint32_t e = (uint32_t)(wave * n_it + i) * WAVE + lane;
+                    const uint32_t o = kbase + (uint32_t)__popcll(kb & lt);
+                    gap_keys[pos + o] = s_ex[e];
+                    gcnt[o] = cnt[i];
+                }
+                kbase += wave_count(kb);
             }
-            kbase += wave_count(kb);
         }
         st_single += single;
         st_below += below;
         if (tid == 0) {
-            a.rec_start[d] = (uint32_t)pos;
-            a.rec_nout[d] = n_kept;
+            // the group's records are filed under its first bucket
+            a.rec_start[d0] = (uint32_t)pos;
+            a.rec_nout[d0] = n_kept;
             st_coll += n_surv;
             st_runs += n_runs;
         }
-        pos += n_s;
-        __syncthreads();  // s_ex / s_w reused by the next bucket
+        pos += n_sb;
+        __syncthreads();  // shared buffers are reused by the next group
     }
     // per-workgroup statistics (no contended atomics)
     const int tid = tid0;
