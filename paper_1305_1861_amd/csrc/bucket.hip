@@ -32,12 +32,13 @@ template <typename K>
 struct BkItems;
 template <>
 struct BkItems<uint64_t> {
-    static constexpr int value = 15;  // 7680 windows per bucket in LDS
+    static constexpr int value = 14;  // 7168 windows per group in registers
 };
 template <>
 struct BkItems<Key2> {
-    static constexpr int value = 7;  // 3584 windows per bucket in LDS
+    static constexpr int value = 7;  // 3584 windows per group in registers
 };
+constexpr int BK_RMAX = 1024;  // buckets per group
 
 template <typename K>
 __device__ __forceinline__ uint32_t bucket_of(const K &key, int k, int D) {
@@ -87,7 +88,10 @@ __device__ __forceinline__ Key2 sentinel<Key2>() { return Key2{~0ull, ~0ull}; }
 __device__ __forceinline__ uint32_t wave_count(uint64_t ball) { return (uint32_t)__popcll(ball); }
 
 template <typename K>
-__global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
+// Two workgroups per CU (LDS < 80 KB each) hide more latency than the
+// registers saved by running one: the kernel is bound by LDS and ballot
+// latency, not by issue rate.
+__global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void bucket_kernel(BucketArgs a) {
     constexpr int ITEMS = BkItems<K>::value;
     constexpr int CAP = BK_THREADS * ITEMS;
     // filter blocks that fit in the exchange buffer
@@ -97,8 +101,8 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
     // exchange buffer with a sentinel slot on each side; holds the filters
     // during screen/collect
     __shared__ __align__(16) K s_exs[CAP + 2];
-    __shared__ uint16_t s_start[CAP + 1];  // first index of each bucket of the group
-    __shared__ uint16_t s_fo[CAP + 1];     // first filter block of each bucket
+    __shared__ uint16_t s_start[BK_RMAX + 1];  // first index of each bucket of the group
+    __shared__ uint16_t s_fo[BK_RMAX + 1];     // first filter block of each bucket
     __shared__ uint32_t s_part[ITEMS][BK_WAVES];
     __shared__ uint32_t s_w[2][BK_WAVES];
     __shared__ unsigned long long s_pos[2];
@@ -148,15 +152,25 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
         K key[ITEMS];
         uint32_t rb[ITEMS];  // bucket index within the group
         uint32_t hm = 0;     // bit i: item i starts a bucket
+        // issue every load of the group before using any of them
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint32_t e = (uint32_t)i * BK_THREADS + tid;
+            if (i < n_items && e < n_load)
+                key[i] = keys[pos + e];
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint32_t e = (uint32_t)i * BK_THREADS + tid;
+            rb[i] = 0;
+            if (i < n_items && e < n_load && e > 0)
+                rb[i] = bucket_of(keys[pos + e - 1], a.k, a.D);  // bucket of the previous key
+        }
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             if (i < n_items) {
                 const uint32_t e = (uint32_t)i * BK_THREADS + tid;
-                bool head = false;
-                if (e < n_load) {
-                    key[i] = keys[pos + e];
-                    head = e == 0 || bucket_of(keys[pos + e - 1], a.k, a.D) != bucket_of(key[i], a.k, a.D);
-                }
+                const bool head = e < n_load && (e == 0 || rb[i] != bucket_of(key[i], a.k, a.D));
                 hm |= (uint32_t)head << i;
                 const uint64_t hb = __ballot(head);
                 rb[i] = (uint32_t)__popcll(hb & lt) + (uint32_t)head;  // inclusive, within the wave
@@ -180,7 +194,9 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
                 s_u[0] = inc;  // number of buckets in the loaded keys
         }
         __syncthreads();
-        const uint32_t R = s_u[0];
+        // buckets beyond the first BK_RMAX wait for the next group
+        const uint32_t R_all = s_u[0];
+        const uint32_t R = min(R_all, (uint32_t)BK_RMAX);
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             if (i < n_items) {
@@ -188,12 +204,12 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
                 rb[i] += s_part[i][wave];  // heads at positions <= e
                 if (e < n_load) {
                     rb[i] -= 1;
-                    if ((hm >> i) & 1u)
+                    if (((hm >> i) & 1u) && rb[i] <= (uint32_t)BK_RMAX)
                         s_start[rb[i]] = (uint16_t)e;
                 }
             }
         }
-        if (tid == 0)
+        if (tid == 0 && R_all <= (uint32_t)BK_RMAX)
             s_start[R] = (uint16_t)n_load;
         __syncthreads();
 
@@ -217,7 +233,7 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
                 const uint32_t ns = (uint32_t)s_start[r + 1] - s_start[r];
                 const uint32_t nb = a.screen ? max(1u, (a.beta * ns + 255) / 256) : 0u;
                 s_fo[r] = (uint16_t)min(fo, 0xFFFFu);
-                const bool whole = !(incomplete && r + 1 == R);
+                const bool whole = !(incomplete && r + 1 == R_all);
                 fits += (whole && fo + nb <= FMAX) ? 1u : 0u;
                 fo += nb;
             }
@@ -243,7 +259,7 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
             __syncthreads();
             continue;
         }
-        const uint32_t n_sb = r_cut == R ? n_load : (uint32_t)s_start[r_cut];
+        const uint32_t n_sb = r_cut == R_all ? n_load : (uint32_t)s_start[r_cut];
         const uint32_t blocks_cut = r_cut == R ? nb_total : (uint32_t)s_fo[r_cut];
         if (tid == 0)
             s_fo[r_cut] = (uint16_t)blocks_cut;
@@ -254,6 +270,9 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
         __syncthreads();
 
         // ---- screen and collect, each bucket against its own filter ----
+        // In LDS the group's filters are stored as 8 word planes (word q of
+        // block x at q * blocks_cut + x) so that the lanes of a wave touching
+        // the same word of different blocks fall in different banks.
         uint32_t sv = 0;  // bit i: item i survives
         if (a.screen) {
             for (uint32_t i = tid; i < blocks_cut * 8; i += BK_THREADS)
@@ -264,13 +283,14 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
                 if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb) {
                     const uint32_t f0 = s_fo[rb[i]], nb = (uint32_t)s_fo[rb[i] + 1] - f0;
                     const uint64_t h = key_hash(key[i]);
-                    uint64_t *b = s_filter + ((uint64_t)f0 + __umul64hi(h, nb)) * 8;
+                    uint64_t *b = s_filter + f0 + (uint32_t)__umul64hi(h, nb);
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
                         const uint64_t m = s_table[(h >> (w * a.table_bits)) & tmask];
-                        const uint64_t old = atomicOr((unsigned long long *)(b + w), (unsigned long long)m);
+                        const uint64_t old =
+                            atomicOr((unsigned long long *)(b + w * blocks_cut), (unsigned long long)m);
                         if (old & m)
-                            atomicOr((unsigned long long *)(b + 4 + w), (unsigned long long)(old & m));
+                            atomicOr((unsigned long long *)(b + (4 + w) * blocks_cut), (unsigned long long)(old & m));
                     }
                 }
             }
@@ -280,12 +300,12 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
                 if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb) {
                     const uint32_t f0 = s_fo[rb[i]], nb = (uint32_t)s_fo[rb[i] + 1] - f0;
                     const uint64_t h = key_hash(key[i]);
-                    const uint64_t *b = s_filter + ((uint64_t)f0 + __umul64hi(h, nb)) * 8 + 4;
+                    const uint64_t *b = s_filter + f0 + (uint32_t)__umul64hi(h, nb) + 4 * blocks_cut;
                     bool all = true;
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
                         const uint64_t m = s_table[(h >> (w * a.table_bits)) & tmask];
-                        all &= (b[w] & m) == m;
+                        all &= (b[w * blocks_cut] & m) == m;
                     }
                     sv |= (uint32_t)all << i;
                 }
@@ -304,54 +324,86 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
         const int passes = TB > 0 ? (TB + BK_SORT_BITS - 1) / BK_SORT_BITS : 1;
         int act_items = n_items;
         uint32_t n_surv = 0;
+        for (int i = tid; i < BK_WAVES * BK_BINS / 4; i += BK_THREADS)
+            reinterpret_cast<uint64_t *>(&s_cnt[0][0])[i] = 0;
+        __syncthreads();
         for (int p = 0; p < passes; p++) {
+            // digit p of the virtual key V = ((bucket - d0) << SB) | (key bits
+            // below the bucket digit); digits are always 9 bits wide (the bits
+            // of V above TB are zero for every key)
             const int shift = p * BK_SORT_BITS;
-            const int bits = TB - shift < BK_SORT_BITS ? TB - shift : BK_SORT_BITS;
-            const int lowbits = shift < SB ? min(bits, SB - shift) : 0;
+            const int lowbits = shift < SB ? min(BK_SORT_BITS, SB - shift) : 0;
             const int hshift = shift > SB ? shift - SB : 0;
-            for (int i = tid; i < BK_WAVES * BK_BINS / 4; i += BK_THREADS)
-                reinterpret_cast<uint64_t *>(&s_cnt[0][0])[i] = 0;
-            __syncthreads();
+            const uint32_t lowmask = lowbits ? (1u << lowbits) - 1u : 0u;
             uint32_t rd[ITEMS];  // (rank << 9) | digit
+            constexpr int IL = 3;  // items ranked together (independent ballot chains)
 #pragma unroll
-            for (int i = 0; i < ITEMS; i++) {
-                if (i < act_items) {
-                    const bool act = (sv >> i) & 1u;
-                    uint32_t dg = 0;
-                    if (act) {
-                        if (lowbits)
-                            dg = digit_of(key[i], shift, (1u << lowbits) - 1u);
-                        if (bits > lowbits)
-                            dg |= (((bucket_of(key[i], a.k, a.D) - d0) >> hshift) & ((1u << (bits - lowbits)) - 1u))
-                                  << lowbits;
+            for (int i0 = 0; i0 < ITEMS; i0 += IL) {
+                if (i0 < act_items) {
+                    uint32_t dg[IL];
+                    uint64_t peers[IL];
+                    bool act[IL];
+#pragma unroll
+                    for (int j = 0; j < IL; j++) {
+                        const int i = i0 + j;
+                        act[j] = i < ITEMS && ((sv >> i) & 1u);
+                        dg[j] = 0;
+                        if (act[j]) {
+                            if (lowbits)
+                                dg[j] = digit_of(key[i], shift, lowmask);
+                            if (lowbits < BK_SORT_BITS)
+                                dg[j] |= (((bucket_of(key[i], a.k, a.D) - d0) >> hshift) << lowbits) & (BK_BINS - 1);
+                        }
+                        peers[j] = __ballot(act[j]);
                     }
-                    uint64_t peers = __ballot(act);
-                    for (int b = 0; b < bits; b++) {
-                        const bool bit = (dg >> b) & 1u;
-                        const uint64_t m = __ballot(bit);
-                        peers &= bit ? m : ~m;
+#pragma unroll
+                    for (int b = 0; b < BK_SORT_BITS; b++) {
+#pragma unroll
+                        for (int j = 0; j < IL; j++) {
+                            const bool bit = (dg[j] >> b) & 1u;
+                            const uint64_t m = __ballot(bit);
+                            peers[j] &= bit ? m : ~m;
+                        }
                     }
-                    const uint32_t below = __popcll(peers & lt);
-                    const uint32_t prior = s_cnt[wave][dg];
-                    if (act && below == 0)
-                        s_cnt[wave][dg] = (uint16_t)(prior + (uint32_t)__popcll(peers));
-                    rd[i] = ((prior + below) << BK_SORT_BITS) | dg;
+#pragma unroll
+                    for (int j = 0; j < IL; j++) {
+                        const int i = i0 + j;
+                        if (i < ITEMS) {
+                            const uint32_t below = __popcll(peers[j] & lt);
+                            const uint32_t prior = s_cnt[wave][dg[j]];
+                            if (act[j] && below == 0)
+                                s_cnt[wave][dg[j]] = (uint16_t)(prior + (uint32_t)__popcll(peers[j]));
+                            rd[i] = ((prior + below) << BK_SORT_BITS) | dg[j];
+                        }
+                    }
                 }
             }
             __syncthreads();
-            {
-                // bin `tid`: total over waves, block-wide start, per-wave offsets
-                uint32_t tot = 0;
+            // bin `tid`: total over waves; exclusive prefix over bins by a wave
+            // scan plus the totals of the waves before
+            uint32_t c[BK_WAVES];
+            uint32_t tot = 0;
 #pragma unroll
-                for (int w = 0; w < BK_WAVES; w++)
-                    tot += s_cnt[w][tid];
-                uint32_t r = block_exclusive_sum<BK_THREADS>(tot, &n_surv);
+            for (int w = 0; w < BK_WAVES; w++) {
+                c[w] = s_cnt[w][tid];
+                tot += c[w];
+            }
+            const uint32_t inc = wave_inclusive_sum(tot);
+            if (lane == WAVE - 1)
+                s_w[0][wave] = inc;
+            __syncthreads();
+            uint32_t r = inc - tot;
+            n_surv = 0;
 #pragma unroll
-                for (int w = 0; w < BK_WAVES; w++) {
-                    const uint32_t c = s_cnt[w][tid];
-                    s_cnt[w][tid] = (uint16_t)r;
-                    r += c;
-                }
+            for (int w = 0; w < BK_WAVES; w++) {
+                const uint32_t t = s_w[0][w];
+                r += w < wave ? t : 0;
+                n_surv += t;
+            }
+#pragma unroll
+            for (int w = 0; w < BK_WAVES; w++) {
+                s_cnt[w][tid] = (uint16_t)r;
+                r += c[w];
             }
             __syncthreads();
 #pragma unroll
@@ -359,8 +411,12 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
                 if (i < act_items && ((sv >> i) & 1u))
                     s_ex[s_cnt[wave][rd[i] & (BK_BINS - 1)] + (rd[i] >> BK_SORT_BITS)] = key[i];
             __syncthreads();
+            // counters are free again: clear them for the next pass while
+            // reloading the keys wave-striped, element (wave, item, lane)
+#pragma unroll
+            for (int w = 0; w < BK_WAVES; w++)
+                s_cnt[w][tid] = 0;
             if (p + 1 < passes) {
-                // reload wave-striped: element (wave, item, lane) in order
                 act_items = (int)((n_surv + BK_THREADS - 1) / BK_THREADS);
                 sv = 0;
 #pragma unroll
@@ -373,8 +429,8 @@ __global__ __launch_bounds__(BK_THREADS) void bucket_kernel(BucketArgs a) {
                         }
                     }
                 }
-                __syncthreads();
             }
+            __syncthreads();
         }
 
         // ---- run-length compaction of s_ex[0, n_surv) ----
