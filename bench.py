@@ -104,6 +104,9 @@ def main() -> int:
                     help="one Bloom filter in HBM for the whole library (device-scope atomics)")
     ap.add_argument("--traffic", default=None,
                     help="JSON file with measured HBM bytes per launch of the dominant kernel")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times with a plain "
+                         "device copy kernel (reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -204,6 +207,13 @@ def main() -> int:
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
         },
     }
+    if args.calibrate_copy_mib:
+        src = torch.ones(args.calibrate_copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = int(src.numel())
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(lib)
