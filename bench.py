@@ -23,6 +23,16 @@ if ROOT not in sys.path:
 
 METRIC = "frequent k-mers/sec counted (exact) + % HBM peak; p50/p99 job latency served"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_1305_1861_amd", "csrc")
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE; used
+# only while the kernel sources still hash to the recorded digest
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bucket_large-library.json")
+STAGE_SOURCES = {
+    "bucket": ["bucket.hip", "device.hpp", "internal.hpp"],
+    "partition": ["partition.hip", "scan.hip", "device.hpp", "internal.hpp"],
+    "pack": ["pack.hip", "device.hpp", "internal.hpp"],
+    "gather": ["bucket.hip", "device.hpp", "internal.hpp"],
+}
 
 WORKLOAD_INFO = {
     "small": dict(genome_bp=1_000_000, coverage=10, read_len=100, sub_rate=0.01, n_rate=0.0, repeats=None),
@@ -60,6 +70,31 @@ def algorithmic_bytes(n_bases: int, n_windows: int, n_collected: int, n_out: int
     bucket = key_bytes * n_windows + (key_bytes + 4) * n_out
     gather = 2.0 * (key_bytes + 4) * n_out
     return dict(pack=pack, partition=part, bucket=bucket, gather=gather)
+
+
+def sources_digest(stage: str) -> str:
+    """sha256 over the HIP sources that define a stage's kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in STAGE_SOURCES.get(stage, []):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(path: str, stage: str, workload: str):
+    """HBM bytes per launch of `stage` from a counter record, or None when the
+    record is missing, covers another stage or workload, or predates the
+    current kernel sources."""
+    if not path or not os.path.exists(path):
+        return None, "no counter record"
+    with open(path) as f:
+        tr = json.load(f)
+    if tr.get("stage") != stage or tr.get("workload") != workload:
+        return None, f"counter record covers {tr.get('stage')} on {tr.get('workload')}"
+    if tr.get("sources_sha256") != sources_digest(stage):
+        return None, "kernel sources changed since the counters were taken"
+    return tr.get("bytes"), tr.get("source", path)
 
 
 def cpu_baseline(lib, target_s: float = 12.0) -> dict:
@@ -102,8 +137,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--global-filter", action="store_true",
                     help="one Bloom filter in HBM for the whole library (device-scope atomics)")
-    ap.add_argument("--traffic", default=None,
-                    help="JSON file with measured HBM bytes per launch of the dominant kernel")
+    ap.add_argument("--traffic", default=TRAFFIC_FILE,
+                    help="JSON record of measured HBM bytes per launch of the dominant kernel")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain "
                          "device copy kernel (reference for HBM byte counters)")
@@ -163,12 +198,7 @@ def main() -> int:
                               lib.c >= 2, r.part_bits)
     dominant = max(model, key=lambda s: stage_ms.get(s, 0.0))
     achieved = model[dominant] / (stage_ms[dominant] * 1e-3) / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            tr = json.load(f)
-        if tr.get("stage") == dominant:
-            traffic = tr.get("bytes")
+    traffic, traffic_src = measured_traffic(args.traffic, dominant, lib.name)
     path_bytes = sum(model.values())
     step_s = ms_per_step * 1e-3
     out = {
@@ -204,7 +234,8 @@ def main() -> int:
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
         "roofline": {
             "bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
+            "algorithmic_bytes": int(model[dominant]), "launch_ms": stage_ms[dominant],
         },
     }
     if args.calibrate_copy_mib:

@@ -107,6 +107,11 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     __shared__ uint32_t s_w[2][BK_WAVES];
     __shared__ unsigned long long s_pos[2];
     __shared__ uint32_t s_u[4];
+    // statistics accumulated over the workgroup's groups: per wave (false
+    // positives, counts in [2, c)) and per workgroup (survivors, runs); every
+    // sum is below the number of windows, hence below 2^32
+    __shared__ uint32_t s_acc[BK_WAVES][2];
+    __shared__ uint32_t s_tot[2];
 
     K *const s_ex = s_exs + 1;
     uint64_t *s_filter = reinterpret_cast<uint64_t *>(s_exs);
@@ -118,6 +123,10 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     if (a.screen)
         for (uint32_t i = tid0; i < n_tab; i += BK_THREADS)
             s_table[i] = a.table[i];
+    if (tid0 < 2 * BK_WAVES)
+        (&s_acc[0][0])[tid0] = 0;
+    if (tid0 < 2)
+        s_tot[tid0] = 0;
 
     const uint64_t G = gridDim.x, g = blockIdx.x;
     const uint64_t n = *a.n_dev;
@@ -129,7 +138,6 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     uint64_t pos = s_pos[0];
     const uint64_t end = s_pos[1];
     const int SB = 2 * a.k - a.D;  // key bits below the bucket digit
-    unsigned long long st_coll = 0, st_runs = 0, st_single = 0, st_below = 0;
 
     while (pos < end) {
         // Thread indices are passed through an empty asm each iteration so
@@ -336,6 +344,9 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             const int hshift = shift > SB ? shift - SB : 0;
             const uint32_t lowmask = lowbits ? (1u << lowbits) - 1u : 0u;
             uint32_t rd[ITEMS];  // (rank << 9) | digit
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++)
+                rd[i] = 0;
             constexpr int IL = 3;  // items ranked together (independent ballot chains)
 #pragma unroll
             for (int i0 = 0; i0 < ITEMS; i0 += IL) {
@@ -483,7 +494,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         }
         __syncthreads();
         uint32_t cnt[ITEMS];
-        uint32_t nk = 0, single = 0, below = 0;
+        uint32_t nk = 0, single = 0, below = 0;  // wave-uniform
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             cnt[i] = 0;
@@ -493,9 +504,9 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                 const uint64_t tb = __ballot(t);
                 if (t) {
                     cnt[i] = e - gcnt[tbase + __popcll(tb & lt)] + 1;
-                    single += cnt[i] == 1;
-                    below += cnt[i] >= 2 && cnt[i] < a.c;
                 }
+                single += wave_count(__ballot(cnt[i] == 1));
+                below += wave_count(__ballot(cnt[i] >= 2 && cnt[i] < a.c));
                 tbase += wave_count(tb);
                 nk += wave_count(__ballot(cnt[i] >= a.c));
             }
@@ -523,38 +534,31 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                 kbase += wave_count(kb);
             }
         }
-        st_single += single;
-        st_below += below;
+        if (lane == 0) {
+            s_acc[wave][0] += single;
+            s_acc[wave][1] += below;
+        }
         if (tid == 0) {
             // the group's records are filed under its first bucket
             a.rec_start[d0] = (uint32_t)pos;
             a.rec_nout[d0] = n_kept;
-            st_coll += n_surv;
-            st_runs += n_runs;
+            s_tot[0] += n_surv;
+            s_tot[1] += n_runs;
         }
         pos += n_sb;
         __syncthreads();  // shared buffers are reused by the next group
     }
     // per-workgroup statistics (no contended atomics)
-    const int tid = tid0;
-    const int wave = tid / WAVE;
-    const uint32_t lane = lane_id();
-    const uint64_t ws = wave_sum64(st_single), wb = wave_sum64(st_below);
-    __shared__ unsigned long long s_red[BK_WAVES][2];
-    if (lane == 0) {
-        s_red[wave][0] = ws;
-        s_red[wave][1] = wb;
-    }
     __syncthreads();
-    if (tid == 0) {
+    if (tid0 == 0) {
         unsigned long long s1 = 0, s2 = 0;
         for (int w = 0; w < BK_WAVES; w++) {
-            s1 += s_red[w][0];
-            s2 += s_red[w][1];
+            s1 += s_acc[w][0];
+            s2 += s_acc[w][1];
         }
         unsigned long long *o = a.wg_stats + 4 * g;
-        o[0] = st_coll;
-        o[1] = st_runs;
+        o[0] = s_tot[0];
+        o[1] = s_tot[1];
         o[2] = s1;
         o[3] = s2;
     }
