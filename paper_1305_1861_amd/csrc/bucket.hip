@@ -39,6 +39,13 @@ struct BkItems<Key2> {
     static constexpr int value = 7;  // 3584 windows per group in registers
 };
 constexpr int BK_RMAX = 1024;  // buckets per group
+constexpr int BK_MSD_BITS = 12;  // first (MSD) sort pass: 4096 bins, 16-bit counters in the LSD counter array
+constexpr int BK_MSD_BINS = 1 << BK_MSD_BITS;
+constexpr int BK_PMAX = 2 * (BK_RMAX + 1);  // keys of mixed bins radix-sorted through a position map
+constexpr int BK_LIST_MAX = BK_PMAX / 2;     // mixed bins listed for the rank sort
+constexpr int BK_RANK_MAX = 256;             // largest bin the rank sort takes (4 keys per lane)
+static_assert(BK_MSD_BINS == 8 * BK_THREADS, "bin starts: eight bins per thread");
+static_assert(BK_MSD_BINS / 2 == BK_WAVES * BK_BINS / 2, "MSD counters reuse the LSD counter array");
 
 template <typename K>
 __device__ __forceinline__ uint32_t bucket_of(const K &key, int k, int D) {
@@ -84,6 +91,43 @@ __device__ __forceinline__ uint64_t sentinel<uint64_t>() { return ~0ull; }
 template <>
 __device__ __forceinline__ Key2 sentinel<Key2>() { return Key2{~0ull, ~0ull}; }
 
+// Bits [shift, shift + nbits) of a group's virtual sort key
+// V = ((bucket - d0) << SB) | (key bits below the bucket digit), nbits <= 12.
+template <typename K>
+__device__ __forceinline__ uint32_t vdigit(const K &key, int shift, int nbits, int SB, int k, int D, uint32_t d0) {
+    const int lowbits = shift < SB ? min(nbits, SB - shift) : 0;
+    const int hshift = shift > SB ? shift - SB : 0;
+    uint32_t d = 0;
+    if (lowbits)
+        d = digit_of(key, shift, (1u << lowbits) - 1u);
+    if (lowbits < nbits)
+        d |= (((bucket_of(key, k, D) - d0) >> hshift) << lowbits) & ((1u << nbits) - 1u);
+    return d;
+}
+
+// Start and size of bin d of the MSD pass (starts packed two per word).
+__device__ __forceinline__ uint32_t msd_bin_start(const uint32_t *s_c32, uint32_t d) {
+    return (s_c32[d >> 1] >> ((d & 1u) * 16u)) & 0xFFFFu;
+}
+__device__ __forceinline__ uint32_t msd_bin_size(const uint32_t *s_c32, uint32_t d, uint32_t n) {
+    const uint32_t end = d + 1 < (uint32_t)BK_MSD_BINS ? msd_bin_start(s_c32, d + 1) : n;
+    return end - msd_bin_start(s_c32, d);
+}
+
+// In-place exclusive prefix of m <= 2 * WAVE counters v[0, m), run by the
+// lanes of one wave; lane WAVE - 1 returns the total.
+__device__ __forceinline__ uint32_t exclusive_parts(uint32_t *v, int m, int lane) {
+    const uint32_t v0 = 2 * lane < m ? v[2 * lane] : 0u;
+    const uint32_t v1 = 2 * lane + 1 < m ? v[2 * lane + 1] : 0u;
+    const uint32_t inc = wave_inclusive_sum(v0 + v1);
+    const uint32_t ex = inc - v0 - v1;
+    if (2 * lane < m)
+        v[2 * lane] = ex;
+    if (2 * lane + 1 < m)
+        v[2 * lane + 1] = ex + v0;
+    return inc;
+}
+
 // Number of lanes whose flag is set in a ballot.
 __device__ __forceinline__ uint32_t wave_count(uint64_t ball) { return (uint32_t)__popcll(ball); }
 
@@ -101,8 +145,12 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     // exchange buffer with a sentinel slot on each side; holds the filters
     // during screen/collect
     __shared__ __align__(16) K s_exs[CAP + 2];
-    __shared__ uint16_t s_start[BK_RMAX + 1];  // first index of each bucket of the group
-    __shared__ uint16_t s_fo[BK_RMAX + 1];     // first filter block of each bucket
+    // first index of each bucket of the group, then the first filter block of
+    // each bucket; during the sort, the position map of the mixed bins
+    __shared__ __align__(16) uint16_t s_aux[2 * (BK_RMAX + 1)];
+    uint16_t *const s_start = s_aux;
+    uint16_t *const s_fo = s_aux + BK_RMAX + 1;
+    __shared__ uint32_t s_mix[BK_MSD_BINS / 32];  // mixed-bin flags of the MSD pass
     __shared__ uint32_t s_part[ITEMS][BK_WAVES];
     __shared__ uint32_t s_w[2][BK_WAVES];
     __shared__ unsigned long long s_pos[2];
@@ -157,6 +205,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         bool incomplete = false;
         if (pos + n_load < end)
             incomplete = bucket_of(keys[pos + n_load], a.k, a.D) == bucket_of(keys[pos + n_load - 1], a.k, a.D);
+        // every element is assigned on each iteration, so that no value is
+        // carried (and kept in registers) from one group to the next
         K key[ITEMS];
         uint32_t rb[ITEMS];  // bucket index within the group
         uint32_t hm = 0;     // bit i: item i starts a bucket
@@ -164,6 +214,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             const uint32_t e = (uint32_t)i * BK_THREADS + tid;
+            key[i] = sentinel<K>();
             if (i < n_items && e < n_load)
                 key[i] = keys[pos + e];
         }
@@ -189,17 +240,9 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         __syncthreads();
         if (tid < WAVE) {
             // exclusive prefix of the head counts in (item, wave) order
-            const int m = n_items * BK_WAVES;
-            uint32_t v0 = 2 * tid < m ? (&s_part[0][0])[2 * tid] : 0;
-            uint32_t v1 = 2 * tid + 1 < m ? (&s_part[0][0])[2 * tid + 1] : 0;
-            const uint32_t inc = wave_inclusive_sum(v0 + v1);
-            const uint32_t ex = inc - v0 - v1;
-            if (2 * tid < m)
-                (&s_part[0][0])[2 * tid] = ex;
-            if (2 * tid + 1 < m)
-                (&s_part[0][0])[2 * tid + 1] = ex + v0;
+            const uint32_t tot = exclusive_parts(&s_part[0][0], n_items * BK_WAVES, tid);
             if (tid == WAVE - 1)
-                s_u[0] = inc;  // number of buckets in the loaded keys
+                s_u[0] = tot;  // number of buckets in the loaded keys
         }
         __syncthreads();
         // buckets beyond the first BK_RMAX wait for the next group
@@ -326,122 +369,348 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                     sv |= 1u << i;
         }
 
-        // ---- LSD radix sort of the survivors on (bucket - d0, key bits below
-        // the bucket digit), 9-bit digits ----
+        // ---- sort the survivors by the virtual key V = ((bucket - d0) << SB) |
+        // (key bits below the bucket digit), TB bits; within the group V is
+        // a bijection of the key, so sorting by V sorts the keys ----
+        // (1) one MSD pass on the top MB <= 12 bits of V into 4096 bins
+        //     (unordered within a bin: LDS atomics on packed 16-bit counters);
+        // (2) a bin whose keys are not all equal is "mixed";
+        // (3) the keys of mixed bins -- a few percent of them, since every
+        //     distinct key recurs about coverage times -- are sorted by an
+        //     LSD radix sort (9-bit digits, stable wave-match ranking) over
+        //     just their positions; if there are too many of them to map,
+        //     the LSD sort runs over the whole group instead.
         const int TB = SB + RB;
-        const int passes = TB > 0 ? (TB + BK_SORT_BITS - 1) / BK_SORT_BITS : 1;
-        int act_items = n_items;
-        uint32_t n_surv = 0;
+        const int MB = min(BK_MSD_BITS, TB);
+        const int mshift = TB - MB;
+        uint32_t *const s_c32 = reinterpret_cast<uint32_t *>(&s_cnt[0][0]);
         for (int i = tid; i < BK_WAVES * BK_BINS / 4; i += BK_THREADS)
             reinterpret_cast<uint64_t *>(&s_cnt[0][0])[i] = 0;
+        if (tid < BK_MSD_BINS / 32)
+            s_mix[tid] = 0;
         __syncthreads();
-        for (int p = 0; p < passes; p++) {
-            // digit p of the virtual key V = ((bucket - d0) << SB) | (key bits
-            // below the bucket digit); digits are always 9 bits wide (the bits
-            // of V above TB are zero for every key)
-            const int shift = p * BK_SORT_BITS;
-            const int lowbits = shift < SB ? min(BK_SORT_BITS, SB - shift) : 0;
-            const int hshift = shift > SB ? shift - SB : 0;
-            const uint32_t lowmask = lowbits ? (1u << lowbits) - 1u : 0u;
-            uint32_t rd[ITEMS];  // (rank << 9) | digit
+        uint32_t rd[ITEMS];  // MSD pass: (rank << 12) | bin; LSD passes: (rank << 9) | digit
 #pragma unroll
-            for (int i = 0; i < ITEMS; i++)
-                rd[i] = 0;
-            constexpr int IL = 3;  // items ranked together (independent ballot chains)
+        for (int i = 0; i < ITEMS; i++) {
+            rd[i] = 0;
+            if (i < n_items && ((sv >> i) & 1u)) {
+                const uint32_t d = vdigit(key[i], mshift, MB, SB, a.k, a.D, d0);
+                const uint32_t sh = (d & 1u) * 16u;
+                const uint32_t old = atomicAdd(&s_c32[d >> 1], 1u << sh);
+                rd[i] = (((old >> sh) & 0xFFFFu) << BK_MSD_BITS) | d;
+            }
+        }
+        __syncthreads();
+        uint32_t n_surv;
+        {
+            // bin starts; thread t owns bins 8t .. 8t+7 (words 4t .. 4t+3)
+            uint4 w = reinterpret_cast<const uint4 *>(s_c32)[tid];
+            const uint32_t c0 = w.x & 0xFFFFu, c1 = w.x >> 16, c2 = w.y & 0xFFFFu, c3 = w.y >> 16;
+            const uint32_t c4 = w.z & 0xFFFFu, c5 = w.z >> 16, c6 = w.w & 0xFFFFu, c7 = w.w >> 16;
+            const uint32_t s0 = block_exclusive_sum<BK_THREADS>(c0 + c1 + c2 + c3 + c4 + c5 + c6 + c7, &n_surv);
+            const uint32_t s1 = s0 + c0, s2 = s1 + c1, s3 = s2 + c2, s4 = s3 + c3, s5 = s4 + c4, s6 = s5 + c5,
+                           s7 = s6 + c6;
+            w = make_uint4(s0 | (s1 << 16), s2 | (s3 << 16), s4 | (s5 << 16), s6 | (s7 << 16));
+            reinterpret_cast<uint4 *>(s_c32)[tid] = w;
+        }
+        __syncthreads();
 #pragma unroll
-            for (int i0 = 0; i0 < ITEMS; i0 += IL) {
-                if (i0 < act_items) {
-                    uint32_t dg[IL];
-                    uint64_t peers[IL];
-                    bool act[IL];
+        for (int i = 0; i < ITEMS; i++) {
+            if (i < n_items && ((sv >> i) & 1u)) {
+                const uint32_t d = rd[i] & (BK_MSD_BINS - 1);
+                const uint32_t st = (s_c32[d >> 1] >> ((d & 1u) * 16u)) & 0xFFFFu;
+                s_ex[st + (rd[i] >> BK_MSD_BITS)] = key[i];
+            }
+        }
+        __syncthreads();
+        // mixed bins: a key differing from its left neighbour in the same bin
+        const int n_ch = (int)((n_surv + BK_THREADS - 1) / BK_THREADS);
 #pragma unroll
-                    for (int j = 0; j < IL; j++) {
-                        const int i = i0 + j;
-                        act[j] = i < ITEMS && ((sv >> i) & 1u);
-                        dg[j] = 0;
-                        if (act[j]) {
-                            if (lowbits)
-                                dg[j] = digit_of(key[i], shift, lowmask);
-                            if (lowbits < BK_SORT_BITS)
-                                dg[j] |= (((bucket_of(key[i], a.k, a.D) - d0) >> hshift) << lowbits) & (BK_BINS - 1);
-                        }
-                        peers[j] = __ballot(act[j]);
-                    }
-#pragma unroll
-                    for (int b = 0; b < BK_SORT_BITS; b++) {
-#pragma unroll
-                        for (int j = 0; j < IL; j++) {
-                            const bool bit = (dg[j] >> b) & 1u;
-                            const uint64_t m = __ballot(bit);
-                            peers[j] &= bit ? m : ~m;
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < IL; j++) {
-                        const int i = i0 + j;
-                        if (i < ITEMS) {
-                            const uint32_t below = __popcll(peers[j] & lt);
-                            const uint32_t prior = s_cnt[wave][dg[j]];
-                            if (act[j] && below == 0)
-                                s_cnt[wave][dg[j]] = (uint16_t)(prior + (uint32_t)__popcll(peers[j]));
-                            rd[i] = ((prior + below) << BK_SORT_BITS) | dg[j];
-                        }
+        for (int i = 0; i < ITEMS; i++) {
+            const uint32_t e = (uint32_t)i * BK_THREADS + tid;
+            if (i < n_ch && e > 0 && e < n_surv) {
+                const K x = s_ex[e], y = s_ex[e - 1];
+                if (x != y) {
+                    const uint32_t dx = vdigit(x, mshift, MB, SB, a.k, a.D, d0);
+                    if (dx == vdigit(y, mshift, MB, SB, a.k, a.D, d0))
+                        atomicOr(&s_mix[dx >> 5], 1u << (dx & 31u));
+                }
+            }
+        }
+        __syncthreads();
+        // mixed bins of this thread (bins 8t .. 8t+7): number, keys, oversized
+        // ones, packed into one sum (each field stays below 2^13, 2^13, 2^6)
+        const uint32_t mixw = (s_mix[tid >> 2] >> ((tid & 3u) * 8u)) & 0xFFu;
+        uint32_t mine = 0;
+        if (mixw) {
+            for (int j = 0; j < 8; j++) {
+                if ((mixw >> j) & 1u) {
+                    const uint32_t m = msd_bin_size(s_c32, tid * 8 + j, n_surv);
+                    mine += m | (1u << 13) | ((m > BK_RANK_MAX ? 1u : 0u) << 26);
+                }
+            }
+        }
+        uint32_t mix_tot;
+        const uint32_t mix_ex = block_exclusive_sum<BK_THREADS>(mine, &mix_tot);
+        uint32_t n_sort = mix_tot & 0x1FFFu;
+        const uint32_t n_mb = (mix_tot >> 13) & 0x1FFFu, n_big = mix_tot >> 26;
+        if (n_sort > 0 && n_big == 0 && n_mb <= BK_LIST_MAX) {
+            // one wave per mixed bin, keys in registers (up to 4 per lane).
+            // A key's place in its bin is the number of smaller keys in the
+            // bin plus the number of equal keys before it.  Distinct values
+            // are taken one at a time (a value of a pending lane, its number
+            // of smaller keys by ballots); a bin with many distinct values
+            // finishes with a scan of the bin per key instead.
+            uint32_t *const s_list = reinterpret_cast<uint32_t *>(s_aux);  // (start, size) of each mixed bin
+            if (mixw) {
+                uint32_t idx = (mix_ex >> 13) & 0x1FFFu;
+                for (int j = 0; j < 8; j++) {
+                    if ((mixw >> j) & 1u) {
+                        const uint32_t d = tid * 8 + j;
+                        s_list[idx++] = msd_bin_start(s_c32, d) | (msd_bin_size(s_c32, d, n_surv) << 16);
                     }
                 }
             }
+            if (tid == 0)
+                s_u[2] = 0;
             __syncthreads();
-            // bin `tid`: total over waves; exclusive prefix over bins by a wave
-            // scan plus the totals of the waves before
-            uint32_t c[BK_WAVES];
-            uint32_t tot = 0;
+            for (;;) {
+                uint32_t idx = 0;
+                if (lane == 0)
+                    idx = atomicAdd(&s_u[2], 1u);
+                idx = __builtin_amdgcn_readfirstlane(idx);
+                if (idx >= n_mb)
+                    break;
+                const uint32_t ent = s_list[idx];
+                const uint32_t st = ent & 0xFFFFu, m = ent >> 16;
+                constexpr int Q = BK_RANK_MAX / WAVE;
+                const int nq = (int)((m + WAVE - 1) / WAVE);
+                K x[Q];
+                uint32_t rk[Q];
+                uint32_t pend = 0;  // bit q: key q of this lane has no place yet
 #pragma unroll
-            for (int w = 0; w < BK_WAVES; w++) {
-                c[w] = s_cnt[w][tid];
-                tot += c[w];
+                for (int q = 0; q < Q; q++) {
+                    rk[q] = 0;
+                    x[q] = sentinel<K>();
+                    if ((uint32_t)(q * WAVE) + lane < m) {
+                        x[q] = s_ex[st + q * WAVE + lane];
+                        pend |= 1u << q;
+                    }
+                }
+                const uint32_t cap = 8u + m / 16u;  // distinct values taken before switching
+                for (uint32_t it = 0;; it++) {
+                    int q0 = -1;
+                    uint64_t b0 = 0;
+#pragma unroll
+                    for (int q = 0; q < Q; q++) {
+                        if (q < nq) {
+                            const uint64_t b = __ballot((pend >> q) & 1u);
+                            if (q0 < 0 && b) {
+                                q0 = q;
+                                b0 = b;
+                            }
+                        }
+                    }
+                    if (q0 < 0 || it == cap)
+                        break;
+                    const int l0 = (int)__builtin_ctzll(b0);
+                    K v = sentinel<K>();
+#pragma unroll
+                    for (int q = 0; q < Q; q++)
+                        if (q == q0)
+                            v = read_lane(x[q], l0);
+                    uint32_t less = 0;
+#pragma unroll
+                    for (int q = 0; q < Q; q++)
+                        if (q < nq)
+                            less += (uint32_t)__popcll(__ballot(x[q] < v));  // invalid slots hold the sentinel
+#pragma unroll
+                    for (int q = 0; q < Q; q++) {
+                        if (q < nq) {
+                            const bool eq = ((pend >> q) & 1u) && x[q] == v;
+                            const uint64_t b = __ballot(eq);
+                            if (eq) {
+                                rk[q] = less + (uint32_t)__popcll(b & lt);
+                                pend &= ~(1u << q);
+                            }
+                            less += (uint32_t)__popcll(b);
+                        }
+                    }
+                }
+                if (__ballot(pend != 0)) {
+                    // remaining keys: scan the whole bin (four keys per step)
+                    for (uint32_t j0 = 0; j0 < m; j0 += 4) {
+                        K y[4];
+#pragma unroll
+                        for (int u = 0; u < 4; u++)
+                            y[u] = j0 + u < m ? s_ex[st + j0 + u] : sentinel<K>();
+#pragma unroll
+                        for (int u = 0; u < 4; u++) {
+                            const uint32_t j = j0 + u;
+#pragma unroll
+                            for (int q = 0; q < Q; q++)
+                                if (q < nq && ((pend >> q) & 1u))
+                                    rk[q] += (y[u] < x[q] || (y[u] == x[q] && j < (uint32_t)(q * WAVE) + lane)) ? 1u : 0u;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < Q; q++)
+                    if ((uint32_t)(q * WAVE) + lane < m)
+                        s_ex[st + rk[q]] = x[q];
             }
-            const uint32_t inc = wave_inclusive_sum(tot);
-            if (lane == WAVE - 1)
-                s_w[0][wave] = inc;
             __syncthreads();
-            uint32_t r = inc - tot;
-            n_surv = 0;
+            n_sort = 0;
+        }
+        if (n_sort > 0) {
+            // radix fallback over the keys of the mixed bins
+            for (int i = tid; i < BK_WAVES * BK_BINS / 4; i += BK_THREADS)
+                reinterpret_cast<uint64_t *>(&s_cnt[0][0])[i] = 0;
+            uint32_t fm = 0;  // bit i: position i * BK_THREADS + tid lies in a mixed bin
 #pragma unroll
-            for (int w = 0; w < BK_WAVES; w++) {
-                const uint32_t t = s_w[0][w];
-                r += w < wave ? t : 0;
-                n_surv += t;
+            for (int i = 0; i < ITEMS; i++) {
+                if (i < n_ch) {
+                    const uint32_t e = (uint32_t)i * BK_THREADS + tid;
+                    bool f = false;
+                    if (e < n_surv) {
+                        const uint32_t d = vdigit(s_ex[e], mshift, MB, SB, a.k, a.D, d0);
+                        f = (s_mix[d >> 5] >> (d & 31u)) & 1u;
+                    }
+                    fm |= (uint32_t)f << i;
+                    const uint64_t fb = __ballot(f);
+                    if (lane == 0)
+                        s_part[i][wave] = (uint32_t)__popcll(fb);
+                }
             }
-#pragma unroll
-            for (int w = 0; w < BK_WAVES; w++) {
-                s_cnt[w][tid] = (uint16_t)r;
-                r += c[w];
-            }
             __syncthreads();
-#pragma unroll
-            for (int i = 0; i < ITEMS; i++)
-                if (i < act_items && ((sv >> i) & 1u))
-                    s_ex[s_cnt[wave][rd[i] & (BK_BINS - 1)] + (rd[i] >> BK_SORT_BITS)] = key[i];
+            if (tid < WAVE)
+                exclusive_parts(&s_part[0][0], n_ch * BK_WAVES, tid);
             __syncthreads();
-            // counters are free again: clear them for the next pass while
-            // reloading the keys wave-striped, element (wave, item, lane)
-#pragma unroll
-            for (int w = 0; w < BK_WAVES; w++)
-                s_cnt[w][tid] = 0;
-            if (p + 1 < passes) {
-                act_items = (int)((n_surv + BK_THREADS - 1) / BK_THREADS);
-                sv = 0;
+            const bool mapped = n_sort <= BK_PMAX;
+            uint16_t *const s_map = s_aux;  // sorted position j lives at s_ex[s_map[j]]
+            if (mapped) {
 #pragma unroll
                 for (int i = 0; i < ITEMS; i++) {
-                    if (i < act_items) {
-                        const uint32_t e = (uint32_t)(wave * act_items + i) * WAVE + lane;
-                        if (e < n_surv) {
-                            key[i] = s_ex[e];
-                            sv |= 1u << i;
-                        }
+                    if (i < n_ch) {
+                        const bool f = (fm >> i) & 1u;
+                        const uint64_t fb = __ballot(f);
+                        if (f)
+                            s_map[s_part[i][wave] + (uint32_t)__popcll(fb & lt)] =
+                                (uint16_t)((uint32_t)i * BK_THREADS + tid);
+                    }
+                }
+            } else {
+                n_sort = n_surv;
+            }
+            __syncthreads();
+            // keys to sort, wave-striped: element (wave, item, lane)
+            int act_items = (int)((n_sort + BK_THREADS - 1) / BK_THREADS);
+            sv = 0;
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                if (i < act_items) {
+                    const uint32_t e = (uint32_t)(wave * act_items + i) * WAVE + lane;
+                    if (e < n_sort) {
+                        key[i] = s_ex[mapped ? (uint32_t)s_map[e] : e];
+                        sv |= 1u << i;
                     }
                 }
             }
             __syncthreads();
+            const int passes = (TB + BK_SORT_BITS - 1) / BK_SORT_BITS;
+            for (int p = 0; p < passes; p++) {
+                const int shift = p * BK_SORT_BITS;
+#pragma unroll
+                for (int i = 0; i < ITEMS; i++)
+                    rd[i] = 0;
+                constexpr int IL = 3;  // items ranked together (independent ballot chains)
+#pragma unroll
+                for (int i0 = 0; i0 < ITEMS; i0 += IL) {
+                    if (i0 < act_items) {
+                        uint32_t dg[IL];
+                        uint64_t peers[IL];
+                        bool act[IL];
+#pragma unroll
+                        for (int j = 0; j < IL; j++) {
+                            const int i = i0 + j;
+                            act[j] = i < ITEMS && ((sv >> i) & 1u);
+                            dg[j] = act[j] ? vdigit(key[i], shift, BK_SORT_BITS, SB, a.k, a.D, d0) : 0u;
+                            peers[j] = __ballot(act[j]);
+                        }
+#pragma unroll
+                        for (int b = 0; b < BK_SORT_BITS; b++) {
+#pragma unroll
+                            for (int j = 0; j < IL; j++) {
+                                const bool bit = (dg[j] >> b) & 1u;
+                                const uint64_t m = __ballot(bit);
+                                peers[j] &= bit ? m : ~m;
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < IL; j++) {
+                            const int i = i0 + j;
+                            if (i < ITEMS) {
+                                const uint32_t below = __popcll(peers[j] & lt);
+                                const uint32_t prior = s_cnt[wave][dg[j]];
+                                if (act[j] && below == 0)
+                                    s_cnt[wave][dg[j]] = (uint16_t)(prior + (uint32_t)__popcll(peers[j]));
+                                rd[i] = ((prior + below) << BK_SORT_BITS) | dg[j];
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                // bin `tid`: total over waves; exclusive prefix over bins by a
+                // wave scan plus the totals of the waves before
+                uint32_t c[BK_WAVES];
+                uint32_t tot = 0;
+#pragma unroll
+                for (int w = 0; w < BK_WAVES; w++) {
+                    c[w] = s_cnt[w][tid];
+                    tot += c[w];
+                }
+                const uint32_t inc = wave_inclusive_sum(tot);
+                if (lane == WAVE - 1)
+                    s_w[0][wave] = inc;
+                __syncthreads();
+                uint32_t r = inc - tot;
+#pragma unroll
+                for (int w = 0; w < BK_WAVES; w++)
+                    r += w < wave ? s_w[0][w] : 0u;
+#pragma unroll
+                for (int w = 0; w < BK_WAVES; w++) {
+                    s_cnt[w][tid] = (uint16_t)r;
+                    r += c[w];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < ITEMS; i++) {
+                    if (i < act_items && ((sv >> i) & 1u)) {
+                        const uint32_t dst = s_cnt[wave][rd[i] & (BK_BINS - 1)] + (rd[i] >> BK_SORT_BITS);
+                        s_ex[mapped ? (uint32_t)s_map[dst] : dst] = key[i];
+                    }
+                }
+                __syncthreads();
+                // counters are free again: clear them for the next pass while
+                // reloading the keys wave-striped
+#pragma unroll
+                for (int w = 0; w < BK_WAVES; w++)
+                    s_cnt[w][tid] = 0;
+                if (p + 1 < passes) {
+                    sv = 0;
+#pragma unroll
+                    for (int i = 0; i < ITEMS; i++) {
+                        if (i < act_items) {
+                            const uint32_t e = (uint32_t)(wave * act_items + i) * WAVE + lane;
+                            if (e < n_sort) {
+                                key[i] = s_ex[mapped ? (uint32_t)s_map[e] : e];
+                                sv |= 1u << i;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
         }
 
         // ---- run-length compaction of s_ex[0, n_surv) ----

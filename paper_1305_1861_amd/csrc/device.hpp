@@ -15,6 +15,9 @@ struct Key2 {
 
 __device__ __forceinline__ bool operator==(const Key2 &a, const Key2 &b) { return a.hi == b.hi && a.lo == b.lo; }
 __device__ __forceinline__ bool operator!=(const Key2 &a, const Key2 &b) { return !(a == b); }
+__device__ __forceinline__ bool operator<(const Key2 &a, const Key2 &b) {
+    return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
 
 // 64-bit finaliser of MurmurHash3 (fmix64).
 __device__ __forceinline__ uint64_t fmix64(uint64_t x) {
@@ -61,6 +64,11 @@ __device__ __forceinline__ uint64_t read_lane64(uint64_t x, int src) {
     uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
     uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
     return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t read_lane(uint64_t x, int src) { return read_lane64(x, src); }
+__device__ __forceinline__ Key2 read_lane(const Key2 &x, int src) {
+    return Key2{read_lane64(x.hi, src), read_lane64(x.lo, src)};
 }
 
 // Inclusive prefix sum across the wave.
