@@ -156,10 +156,10 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     __shared__ unsigned long long s_pos[2];
     __shared__ uint32_t s_u[4];
     // statistics accumulated over the workgroup's groups: per wave (false
-    // positives, counts in [2, c)) and per workgroup (survivors, runs); every
+    // positives, counts in [2, c), runs) and per workgroup (survivors); every
     // sum is below the number of windows, hence below 2^32
-    __shared__ uint32_t s_acc[BK_WAVES][2];
-    __shared__ uint32_t s_tot[2];
+    __shared__ uint32_t s_acc[BK_WAVES][3];
+    __shared__ uint32_t s_tot[1];
 
     K *const s_ex = s_exs + 1;
     uint64_t *s_filter = reinterpret_cast<uint64_t *>(s_exs);
@@ -171,10 +171,10 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     if (a.screen)
         for (uint32_t i = tid0; i < n_tab; i += BK_THREADS)
             s_table[i] = a.table[i];
-    if (tid0 < 2 * BK_WAVES)
+    if (tid0 < 3 * BK_WAVES)
         (&s_acc[0][0])[tid0] = 0;
-    if (tid0 < 2)
-        s_tot[tid0] = 0;
+    if (tid0 == 0)
+        s_tot[0] = 0;
 
     const uint64_t G = gridDim.x, g = blockIdx.x;
     const uint64_t n = *a.n_dev;
@@ -714,73 +714,69 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         }
 
         // ---- run-length compaction of s_ex[0, n_surv) ----
-        // positions in (wave, item, lane) order with n_it items per wave; the
-        // r-th head and the r-th tail delimit run r.  Run starts go to the
-        // group's slice of gap_counts (capacity n_sb >= number of runs).
+        // positions in (wave, item, lane) order with n_it items per wave.  A
+        // run's count is its tail position minus its head position plus one;
+        // the head of a tail is the last head at or before it, found from the
+        // head ballots of this wave (and, for the first run of a wave, the
+        // last head of the waves before).
         const int n_it = (int)((n_surv + BK_THREADS - 1) / BK_THREADS);
         if (tid == 0) {
             s_ex[-1] = sentinel<K>();
             s_ex[n_surv] = sentinel<K>();
         }
         __syncthreads();
-        uint32_t *gcnt = a.gap_counts + pos;
-        uint32_t nh = 0, nt = 0;
+        uint32_t rh = 0, rt = 0;  // bit i: item i is a run head / a run tail
+        uint32_t last = 0;        // 1 + position of this wave's last head (0: none)
+        uint32_t nh = 0;          // heads (runs) in this wave, wave-uniform
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
+            key[i] = sentinel<K>();
             if (i < n_it) {
-                const uint32_t e = (uint32_t)(wave * n_it + i) * WAVE + lane;
+                const uint32_t base = (uint32_t)(wave * n_it + i) * WAVE;
+                const uint32_t e = base + lane;
                 bool h = false, t = false;
                 if (e < n_surv) {
-                    const K x = s_ex[e];
-                    h = s_ex[(int)e - 1] != x;
-                    t = s_ex[e + 1] != x;
+                    key[i] = s_ex[e];
+                    h = s_ex[(int)e - 1] != key[i];
+                    t = s_ex[e + 1] != key[i];
                 }
-                nh += wave_count(__ballot(h));
-                nt += wave_count(__ballot(t));
-            }
-        }
-        if (lane == 0) {
-            s_w[0][wave] = nh;
-            s_w[1][wave] = nt;
-        }
-        __syncthreads();
-        uint32_t hbase = 0, tbase = 0, n_runs = 0;
-        for (int w = 0; w < BK_WAVES; w++) {
-            hbase += w < wave ? s_w[0][w] : 0;
-            tbase += w < wave ? s_w[1][w] : 0;
-            n_runs += s_w[0][w];
-        }
-#pragma unroll
-        for (int i = 0; i < ITEMS; i++) {
-            if (i < n_it) {
-                const uint32_t e = (uint32_t)(wave * n_it + i) * WAVE + lane;
-                const bool h = e < n_surv && s_ex[(int)e - 1] != s_ex[e];
+                rh |= (uint32_t)h << i;
+                rt |= (uint32_t)t << i;
                 const uint64_t hb = __ballot(h);
-                if (h)
-                    gcnt[hbase + __popcll(hb & lt)] = e;
-                hbase += wave_count(hb);
+                nh += wave_count(hb);
+                if (hb)
+                    last = base + 64u - (uint32_t)__clzll(hb);
             }
         }
+        if (lane == 0)
+            s_w[1][wave] = last;
         __syncthreads();
+        uint32_t carry = 0;  // position of the last head before the current item
+#pragma unroll
+        for (int w = 0; w < BK_WAVES; w++) {
+            const uint32_t l = s_w[1][w];
+            if (w < wave && l)
+                carry = l - 1;
+        }
         uint32_t cnt[ITEMS];
         uint32_t nk = 0, single = 0, below = 0;  // wave-uniform
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             cnt[i] = 0;
             if (i < n_it) {
-                const uint32_t e = (uint32_t)(wave * n_it + i) * WAVE + lane;
-                const bool t = e < n_surv && s_ex[e + 1] != s_ex[e];
-                const uint64_t tb = __ballot(t);
-                if (t) {
-                    cnt[i] = e - gcnt[tbase + __popcll(tb & lt)] + 1;
-                }
+                const uint32_t base = (uint32_t)(wave * n_it + i) * WAVE;
+                const uint64_t hb = __ballot((rh >> i) & 1u);
+                const uint64_t upto = hb & (lt | (1ull << lane));  // heads at lanes <= this one
+                const uint32_t hp = upto ? base + 63u - (uint32_t)__clzll(upto) : carry;
+                if ((rt >> i) & 1u)
+                    cnt[i] = base + lane - hp + 1;
+                if (hb)
+                    carry = base + 63u - (uint32_t)__clzll(hb);
                 single += wave_count(__ballot(cnt[i] == 1));
                 below += wave_count(__ballot(cnt[i] >= 2 && cnt[i] < a.c));
-                tbase += wave_count(tb);
                 nk += wave_count(__ballot(cnt[i] >= a.c));
             }
         }
-        __syncthreads();  // every run start has been read
         if (lane == 0)
             s_w[0][wave] = nk;
         __syncthreads();
@@ -789,15 +785,15 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             kbase += w < wave ? s_w[0][w] : 0;
             n_kept += s_w[0][w];
         }
+        uint32_t *gcnt = a.gap_counts + pos;
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             if (i < n_it) {
                 const bool keep = cnt[i] >= a.c;
                 const uint64_t kb = __ballot(keep);
                 if (keep) {
-                    const uint32_t e = (uint32_t)(wave * n_it + i) * WAVE + lane;
                     const uint32_t o = kbase + (uint32_t)__popcll(kb & lt);
-                    gap_keys[pos + o] = s_ex[e];
+                    gap_keys[pos + o] = key[i];
                     gcnt[o] = cnt[i];
                 }
                 kbase += wave_count(kb);
@@ -806,13 +802,13 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         if (lane == 0) {
             s_acc[wave][0] += single;
             s_acc[wave][1] += below;
+            s_acc[wave][2] += nh;
         }
         if (tid == 0) {
             // the group's records are filed under its first bucket
             a.rec_start[d0] = (uint32_t)pos;
             a.rec_nout[d0] = n_kept;
             s_tot[0] += n_surv;
-            s_tot[1] += n_runs;
         }
         pos += n_sb;
         __syncthreads();  // shared buffers are reused by the next group
@@ -820,14 +816,15 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     // per-workgroup statistics (no contended atomics)
     __syncthreads();
     if (tid0 == 0) {
-        unsigned long long s1 = 0, s2 = 0;
+        unsigned long long s1 = 0, s2 = 0, s3 = 0;
         for (int w = 0; w < BK_WAVES; w++) {
             s1 += s_acc[w][0];
             s2 += s_acc[w][1];
+            s3 += s_acc[w][2];
         }
         unsigned long long *o = a.wg_stats + 4 * g;
         o[0] = s_tot[0];
-        o[1] = s_tot[1];
+        o[1] = s3;
         o[2] = s1;
         o[3] = s2;
     }
