@@ -149,7 +149,7 @@ struct Plan {
     uint64_t n_bases, n_reads, n_words, cap, n_blocks;
     size_t key_bytes;
     // partitioned path
-    int D, shift1, bits1, shift2, bits2;  // bits2 == 0: one pass
+    int D;  // bucket bits
     uint64_t n_buckets, fb_cap, fb_nb_max;
     size_t part_words;
     // workspace offsets
@@ -194,23 +194,12 @@ tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const
     if (p->n_blocks > (1ull << 40))
         return fail(TK_EINVAL, "filter of %llu blocks is too large", (unsigned long long)p->n_blocks);
     p->D = p->global ? -1 : part_bits_for(n_bases, n_reads, k, p->opts);
-    p->bits2 = 0;
-    p->shift2 = 0;
     if (!p->global) {
         const int D = p->D;
-        if (D <= 10) {
-            p->bits1 = D;
-            p->shift1 = 2 * k - D;
-        } else {
-            p->bits1 = D / 2;
-            p->shift1 = 2 * k - D;
-            p->bits2 = D - p->bits1;
-            p->shift2 = 2 * k - p->bits2;
-        }
         p->n_buckets = 1ull << D;
         p->fb_cap = p->cap / ((uint64_t)bucket_capacity(p->key_words) + 1) + 1;
         p->fb_nb_max = p->screen ? ceil_div((uint64_t)p->opts.beta * std::max<uint64_t>(p->cap, 1), 256) : 0;
-        p->part_words = partition_scratch_words(std::max<uint64_t>(p->n_words * 32, 1), p->key_words);
+        p->part_words = partition_scratch_words(p->n_words * 32, p->key_words);
     }
     p->sort_bytes = radix_scratch_bytes(p->cap, p->key_words);
     p->compact_bytes = compact_scratch_bytes(p->cap);
@@ -472,16 +461,15 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
     if ((st = tm.end(TK_STAGE_PACK, s)) != TK_OK || (st = tm.mark(TK_STAGE_PARTITION, s)) != TK_OK)
         return st;
 
-    // keys ordered by bucket: windows -> A (-> B)
-    PartArgs pa{packed, valid, nullptr, p.n_words * 32, p.k, p.shift1, p.bits1, 0, nullptr};
-    TK_HIP(partition_pass(pa, true, keys_a, part, p.part_words, &misc->totals[0], s));
+    // keys ordered by bucket: windows -> A (through B when D > 10)
+    PartArgs pa{};
+    pa.packed = packed;
+    pa.valid = valid;
+    pa.n_elems = p.n_words * 32;
+    pa.k = p.k;
+    pa.bits = p.D;
+    TK_HIP(partition_keys(pa, keys_b, keys_a, part, p.part_words, &misc->totals[0], &misc->totals[2], s));
     uint64_t *sorted = keys_a, *other = keys_b;
-    if (p.bits2) {
-        PartArgs pb{nullptr, nullptr, keys_a, p.cap, p.k, p.shift2, p.bits2, 0, &misc->totals[0]};
-        TK_HIP(partition_pass(pb, false, keys_b, part, p.part_words, &misc->totals[2], s));
-        sorted = keys_b;
-        other = keys_a;
-    }
     if ((st = tm.end(TK_STAGE_PARTITION, s)) != TK_OK || (st = tm.mark(TK_STAGE_BUCKET, s)) != TK_OK)
         return st;
 

@@ -127,11 +127,11 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *to
 // complement is the complemented field with its 2-bit groups reversed; the
 // key is the smaller of the two.
 // ---------------------------------------------------------------------------
-// Forward/reverse-complement extraction of the window ending at base p.
+// Forward/reverse-complement extraction of the window ending at base
+// p = 32w + t from the packed words w0 = packed[w], w1 = packed[w - 1] and
+// w2 = packed[w - 2] (zero before the first word).
 // k <= 31: one-word key.
-__device__ __forceinline__ uint64_t window_key1(const uint64_t *__restrict__ packed, uint64_t w, uint32_t t, int k) {
-    const uint64_t w0 = packed[w];
-    const uint64_t w1 = w ? packed[w - 1] : 0;
+__device__ __forceinline__ uint64_t window_key1(uint64_t w0, uint64_t w1, uint32_t t, int k) {
     const uint32_t s = 62 - 2 * t;  // bit of the window's last base in w0
     const uint64_t cat = s ? (w0 >> s) | (w1 << (64 - s)) : w0;
     const uint64_t fwd = cat & ((1ull << (2 * k)) - 1);
@@ -140,10 +140,7 @@ __device__ __forceinline__ uint64_t window_key1(const uint64_t *__restrict__ pac
 }
 
 // 32 <= k <= 63: two-word key {hi, lo}.
-__device__ __forceinline__ Key2 window_key2(const uint64_t *__restrict__ packed, uint64_t w, uint32_t t, int k) {
-    const uint64_t w0 = packed[w];
-    const uint64_t w1 = w ? packed[w - 1] : 0;
-    const uint64_t w2 = w > 1 ? packed[w - 2] : 0;
+__device__ __forceinline__ Key2 window_key2(uint64_t w0, uint64_t w1, uint64_t w2, uint32_t t, int k) {
     const uint32_t s = 62 - 2 * t;
     uint64_t lo, hi;
     if (s) {
@@ -172,6 +169,13 @@ __device__ __forceinline__ Key2 window_key2(const uint64_t *__restrict__ packed,
     return fwd_smaller ? Key2{hi, lo} : Key2{rhi, rlo};
 }
 
+__device__ __forceinline__ uint64_t window_key1(const uint64_t *__restrict__ packed, uint64_t w, uint32_t t, int k) {
+    return window_key1(packed[w], w ? packed[w - 1] : 0, t, k);
+}
+__device__ __forceinline__ Key2 window_key2(const uint64_t *__restrict__ packed, uint64_t w, uint32_t t, int k) {
+    return window_key2(packed[w], w ? packed[w - 1] : 0, w > 1 ? packed[w - 2] : 0, t, k);
+}
+
 template <bool TWO>
 struct KeyOf;
 template <>
@@ -180,12 +184,18 @@ struct KeyOf<false> {
     __device__ __forceinline__ static uint64_t get(const uint64_t *packed, uint64_t w, uint32_t t, int k) {
         return window_key1(packed, w, t, k);
     }
+    __device__ __forceinline__ static uint64_t get(uint64_t w0, uint64_t w1, uint64_t, uint32_t t, int k) {
+        return window_key1(w0, w1, t, k);
+    }
 };
 template <>
 struct KeyOf<true> {
     using type = Key2;
     __device__ __forceinline__ static Key2 get(const uint64_t *packed, uint64_t w, uint32_t t, int k) {
         return window_key2(packed, w, t, k);
+    }
+    __device__ __forceinline__ static Key2 get(uint64_t w0, uint64_t w1, uint64_t w2, uint32_t t, int k) {
+        return window_key2(w0, w1, w2, t, k);
     }
 };
 

@@ -48,23 +48,27 @@ hipError_t launch_collect(const BloomArgs &a, bool screen, void *keys, uint64_t 
                           unsigned long long *n_collected, int grid, hipStream_t stream);
 
 // ---- partition.hip --------------------------------------------------------
-// One stable radix pass on key bits [shift, shift + bits), bits <= 10.  The
-// source is either every window of the packed reads (from_windows: element =
-// base position, n_elems = n_words * 32) or a key array of n_elems keys.
+// Keys of every valid window ordered by their top D = bits bits (D <= 20),
+// in one pass (D <= 10) or two; the order inside a bucket is unspecified.
+// Input: the packed reads (n_elems = n_words * 32 window positions).  tmp
+// (pass-1 output when D > 10) and out hold n_elems keys each; out receives
+// the result and *total (device) the number of keys; *total2 (device) the
+// number moved by pass 2.
 struct PartArgs {
     const uint64_t *packed;
     const uint32_t *valid;
-    const void *keys_in;
+    const void *keys_in;  // pass 2: the pass-1 output
     uint64_t n_elems;
     int k;
     int shift, bits;
-    uint64_t n_chunks;      // set by the pass
-    const uint32_t *n_dev;  // if set, the element count is min(n_elems, *n_dev)
+    uint64_t n_chunks;    // pass 1: chunks
+    const uint32_t *seg;  // pass 2: segment starts (nseg + 1)
+    const uint32_t *cb;   // pass 2: first chunk of each segment (nseg + 1)
+    uint32_t nseg;
 };
-size_t partition_scratch_words(uint64_t n_elems, int key_words);
-// *total (device) receives the number of keys written.
-hipError_t partition_pass(const PartArgs &a, bool from_windows, void *out, uint32_t *scratch, size_t scratch_words,
-                          uint32_t *total, hipStream_t stream);
+size_t partition_scratch_words(uint64_t n_pos, int key_words);
+hipError_t partition_keys(const PartArgs &a, void *tmp, void *out, uint32_t *scratch, size_t scratch_words,
+                          uint32_t *total, uint32_t *total2, hipStream_t stream);
 
 // ---- bucket.hip -----------------------------------------------------------
 struct BucketArgs {
