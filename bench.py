@@ -137,6 +137,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--global-filter", action="store_true",
                     help="one Bloom filter in HBM for the whole library (device-scope atomics)")
+    ap.add_argument("--part-bits", type=int, default=-1,
+                    help="bucket bits D of the per-bucket plan (-1: the library's size rule)")
     ap.add_argument("--traffic", default=TRAFFIC_FILE,
                     help="JSON record of measured HBM bytes per launch of the dominant kernel")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -169,6 +171,7 @@ def main() -> int:
     offsets = torch.from_numpy(lib.offsets.view(np.int64)).to(dev)
     opts = tk.tk_default_options()
     opts.flags = tk.TK_FLAG_TIMING | (tk.TK_FLAG_GLOBAL_FILTER if args.global_filter else 0)
+    opts.part_bits = args.part_bits
     need = tk.tk_workspace_size(lib.n_bases, lib.n_reads, lib.k, lib.c, opts)
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()

@@ -156,7 +156,7 @@ struct Plan {
     size_t off_ctr, off_table, off_packed, off_valid, off_starts, off_filter;
     size_t off_keys_a, off_keys_b, off_counts, off_sort, off_compact;
     size_t off_gapc, off_f, off_part, off_rec_start, off_rec_nout, off_rec_off, off_rec_scan;
-    size_t off_wg, off_fb_list, off_misc, total;
+    size_t off_wg, off_fb_list, off_fb_ent, off_fbc, off_misc, total;
     size_t sort_bytes, compact_bytes;
 };
 
@@ -198,7 +198,7 @@ tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const
         const int D = p->D;
         p->n_buckets = 1ull << D;
         p->fb_cap = p->cap / ((uint64_t)bucket_capacity(p->key_words) + 1) + 1;
-        p->fb_nb_max = p->screen ? ceil_div((uint64_t)p->opts.beta * std::max<uint64_t>(p->cap, 1), 256) : 0;
+        p->fb_nb_max = p->screen ? ceil_div((uint64_t)p->opts.beta * std::max<uint64_t>(p->cap, 1), 256) + p->fb_cap : 0;
         p->part_words = partition_scratch_words(p->n_words * 32, p->key_words);
     }
     p->sort_bytes = radix_scratch_bytes(p->cap, p->key_words);
@@ -232,6 +232,8 @@ tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const
         p->off_rec_scan = take(scan_scratch_words(p->n_buckets) * sizeof(uint32_t));
         p->off_wg = take(MAX_BUCKET_GRID * 4 * sizeof(unsigned long long));
         p->off_fb_list = take(p->fb_cap * 3 * sizeof(uint32_t));
+        p->off_fb_ent = take(p->fb_cap * sizeof(FbEntry));
+        p->off_fbc = take(p->cap * sizeof(uint32_t));
         p->off_misc = take(sizeof(Misc));
     }
     p->total = off;
@@ -503,39 +505,52 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
         return fail(TK_EDEVICE, "%u oversized buckets exceed the list of %llu", hm.fb_count,
                     (unsigned long long)p.fb_cap);
 
-    // buckets too large for LDS: global-memory kernels, same filter rule
+    // buckets too large for LDS: global-memory kernels, same filter rule, all
+    // of them at once
     if ((st = tm.mark(TK_STAGE_FALLBACK, s)) != TK_OK)
         return st;
     if (hm.fb_count) {
-        std::vector<uint32_t> list(3 * (size_t)hm.fb_count);
+        const uint32_t nf = hm.fb_count;
+        std::vector<uint32_t> list(3 * (size_t)nf);
         TK_HIP(hipMemcpyAsync(list.data(), fb_list, list.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         TK_HIP(hipStreamSynchronize(s));
-        const int SB = 2 * p.k - p.D;
-        for (uint32_t i = 0; i < hm.fb_count; i++) {
-            const uint32_t b = list[3 * i], start = list[3 * i + 1], ns = list[3 * i + 2];
-            const uint64_t *kb = sorted + (size_t)start * kw;
-            uint64_t *gap = other + (size_t)start * kw;
-            const uint64_t nb = std::max<uint64_t>(1, ceil_div((uint64_t)p.opts.beta * ns, 256));
-            if (p.screen) {
-                TK_HIP(zero_bytes(filter, nb * 64, s));
-                TK_HIP(launch_fb_screen(kb, ns, kw, table, p.opts.table_bits, filter, nb, s));
-            }
-            TK_HIP(zero_bytes(&misc->fb_ctr, sizeof(DevCounters), s));
-            TK_HIP(launch_fb_collect(kb, ns, kw, table, p.opts.table_bits, filter, nb, p.screen, fbuf,
-                                     &misc->fb_ctr.n_collected, s));
-            unsigned long long n_surv = 0;
-            TK_HIP(hipMemcpyAsync(&n_surv, &misc->fb_ctr.n_collected, sizeof n_surv, hipMemcpyDeviceToHost, s));
-            TK_HIP(hipStreamSynchronize(s));
-            uint64_t *srt = nullptr;
-            int passes = 0;
-            TK_HIP(radix_sort(fbuf, gap, n_surv, kw, SB, ws + p.off_sort, p.sort_bytes, s, &srt, &passes));
-            uint64_t *dst = srt == fbuf ? gap : fbuf;
-            TK_HIP(compact(srt, n_surv, kw, p.c, dst, gap_counts + start, ws + p.off_compact, p.compact_bytes,
-                           &misc->fb_ctr, s));
-            if (dst != gap && n_surv)
-                TK_HIP(hipMemcpyAsync(gap, dst, n_surv * p.key_bytes, hipMemcpyDeviceToDevice, s));
-            TK_HIP(launch_fb_fold(&misc->fb_ctr, b, rec_nout, misc->fb_stats, s));
+        std::vector<FbEntry> ent(nf);
+        for (uint32_t i = 0; i < nf; i++)
+            ent[i] = FbEntry{list[3 * i], list[3 * i + 1], list[3 * i + 2], 0, 0, 0};
+        std::sort(ent.begin(), ent.end(), [](const FbEntry &x, const FbEntry &y) { return x.d < y.d; });
+        uint64_t n_win = 0, n_blk = 0;
+        for (auto &e : ent) {
+            e.wpre = (uint32_t)n_win;
+            e.fpre = (uint32_t)n_blk;
+            e.nb = p.screen ? (uint32_t)std::max<uint64_t>(1, ceil_div((uint64_t)p.opts.beta * e.ns, 256)) : 0u;
+            n_win += e.ns;
+            n_blk += e.nb;
         }
+        if (n_blk > p.fb_nb_max)
+            return fail(TK_EDEVICE, "fallback filters of %llu blocks exceed the reserved %llu",
+                        (unsigned long long)n_blk, (unsigned long long)p.fb_nb_max);
+        FbEntry *d_ent = reinterpret_cast<FbEntry *>(ws + p.off_fb_ent);
+        TK_HIP(hipMemcpyAsync(d_ent, ent.data(), nf * sizeof(FbEntry), hipMemcpyHostToDevice, s));
+        if (p.screen) {
+            TK_HIP(zero_bytes(filter, n_blk * 64, s));
+            TK_HIP(launch_fb_screen(sorted, d_ent, nf, n_win, kw, table, p.opts.table_bits, filter, s));
+        }
+        TK_HIP(zero_bytes(&misc->fb_ctr, sizeof(DevCounters), s));
+        TK_HIP(launch_fb_collect(sorted, d_ent, nf, n_win, kw, table, p.opts.table_bits, filter, p.screen, fbuf,
+                                 &misc->fb_ctr.n_collected, s));
+        unsigned long long n_surv = 0;
+        TK_HIP(hipMemcpyAsync(&n_surv, &misc->fb_ctr.n_collected, sizeof n_surv, hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+        // the partitioned keys are no longer needed: `sorted` is the radix
+        // sort's second buffer
+        uint64_t *srt = nullptr;
+        int passes = 0;
+        TK_HIP(radix_sort(fbuf, sorted, n_surv, kw, 2 * p.k, ws + p.off_sort, p.sort_bytes, s, &srt, &passes));
+        uint64_t *dst = srt == fbuf ? sorted : fbuf;
+        uint32_t *fb_counts = reinterpret_cast<uint32_t *>(ws + p.off_fbc);
+        TK_HIP(compact(srt, n_surv, kw, p.c, dst, fb_counts, ws + p.off_compact, p.compact_bytes, &misc->fb_ctr, s));
+        TK_HIP(launch_fb_distribute(dst, fb_counts, &misc->fb_ctr, d_ent, nf, kw, p.k, p.D, other, gap_counts,
+                                    rec_nout, misc->fb_stats, s));
     }
     if ((st = tm.end(TK_STAGE_FALLBACK, s)) != TK_OK || (st = tm.mark(TK_STAGE_GATHER, s)) != TK_OK)
         return st;

@@ -830,16 +830,37 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     }
 }
 
-// ---- fallback: one oversized bucket with global-memory kernels ----------
+// ---- fallback: oversized buckets, all at once, with global-memory kernels --
+// Entry i of the table (buckets in key order): bucket d, first key start,
+// ns keys, wpre = windows of the entries before, fpre = filter blocks of the
+// entries before, nb = filter blocks.  Every bucket keeps its own filter of
+// nb blocks (the same rule as in LDS); the survivors of all of them are
+// sorted together -- buckets partition the key space in order -- compacted,
+// and each bucket's records are copied to its own slot.
+
+// Entry holding window g: the largest i with e[i].wpre <= g.
+__device__ __forceinline__ uint32_t fb_entry_of(const FbEntry *__restrict__ e, uint32_t n, uint64_t g) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (e[mid].wpre <= g)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
 
 template <typename K>
-__global__ __launch_bounds__(256) void fb_screen(const K *__restrict__ keys, uint64_t n, const uint64_t *__restrict__ table,
-                                                 uint32_t table_bits, uint64_t *__restrict__ filter, uint64_t nb) {
+__global__ __launch_bounds__(256) void fb_screen(const K *__restrict__ keys, const FbEntry *__restrict__ ent,
+                                                 uint32_t n_ent, uint64_t n, const uint64_t *__restrict__ table,
+                                                 uint32_t table_bits, uint64_t *__restrict__ filter) {
     const uint32_t tmask = (1u << table_bits) - 1u;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint64_t h = key_hash(keys[i]);
-        uint64_t *b = filter + __umul64hi(h, nb) * 8;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
+        const FbEntry e = ent[fb_entry_of(ent, n_ent, g)];
+        const uint64_t h = key_hash(keys[e.start + (g - e.wpre)]);
+        uint64_t *b = filter + ((uint64_t)e.fpre + __umul64hi(h, (uint64_t)e.nb)) * 8;
         for (int w = 0; w < 4; w++) {
             const uint64_t m = table[(h >> (w * table_bits)) & tmask];
             const uint64_t old = __hip_atomic_fetch_or(b + w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -850,21 +871,23 @@ __global__ __launch_bounds__(256) void fb_screen(const K *__restrict__ keys, uin
 }
 
 template <typename K>
-__global__ __launch_bounds__(256) void fb_collect(const K *__restrict__ keys, uint64_t n, const uint64_t *__restrict__ table,
-                                                  uint32_t table_bits, const uint64_t *__restrict__ filter, uint64_t nb,
-                                                  int screen, K *__restrict__ out, unsigned long long *__restrict__ n_out) {
+__global__ __launch_bounds__(256) void fb_collect(const K *__restrict__ keys, const FbEntry *__restrict__ ent,
+                                                  uint32_t n_ent, uint64_t n, const uint64_t *__restrict__ table,
+                                                  uint32_t table_bits, const uint64_t *__restrict__ filter, int screen,
+                                                  K *__restrict__ out, unsigned long long *__restrict__ n_out) {
     const uint32_t tmask = (1u << table_bits) - 1u;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-        const uint64_t i = base + threadIdx.x;
+        const uint64_t g = base + threadIdx.x;
         bool keep = false;
         K key{};
-        if (i < n) {
-            key = keys[i];
+        if (g < n) {
+            const FbEntry e = ent[fb_entry_of(ent, n_ent, g)];
+            key = keys[e.start + (g - e.wpre)];
             keep = true;
             if (screen) {
                 const uint64_t h = key_hash(key);
-                const uint64_t *b = filter + __umul64hi(h, nb) * 8 + 4;
+                const uint64_t *b = filter + ((uint64_t)e.fpre + __umul64hi(h, (uint64_t)e.nb)) * 8 + 4;
                 for (int w = 0; w < 4; w++) {
                     const uint64_t m = table[(h >> (w * table_bits)) & tmask];
                     keep &= (b[w] & m) == m;
@@ -883,11 +906,41 @@ __global__ __launch_bounds__(256) void fb_collect(const K *__restrict__ keys, ui
     }
 }
 
-// Folds one fallback bucket's compaction counters into the bucket record and
-// the fallback statistics.
-__global__ void fb_fold(const DevCounters *__restrict__ c, uint32_t bucket, uint32_t *__restrict__ rec_nout,
-                        unsigned long long *__restrict__ fb_stats) {
-    rec_nout[bucket] = (uint32_t)c->n_out;
+// One block per entry: the records of bucket d (a contiguous range of the
+// sorted records) go to the bucket's slot in gap_keys / gap_counts.
+template <typename K>
+__global__ __launch_bounds__(256) void fb_distribute(const K *__restrict__ rec_keys, const uint32_t *__restrict__ rec_counts,
+                                                     const DevCounters *__restrict__ c, const FbEntry *__restrict__ ent,
+                                                     int k, int D, K *__restrict__ gap_keys,
+                                                     uint32_t *__restrict__ gap_counts, uint32_t *__restrict__ rec_nout) {
+    __shared__ uint64_t s_r[2];
+    const FbEntry e = ent[blockIdx.x];
+    const uint64_t n = c->n_out;
+    if (threadIdx.x < 2) {
+        // first record with bucket >= d (+ threadIdx.x)
+        const uint32_t want = e.d + threadIdx.x;
+        uint64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (bucket_of(rec_keys[mid], k, D) < want)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        s_r[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    const uint64_t r0 = s_r[0], m = s_r[1] - r0;
+    for (uint64_t i = threadIdx.x; i < m; i += blockDim.x) {
+        gap_keys[e.start + i] = rec_keys[r0 + i];
+        gap_counts[e.start + i] = rec_counts[r0 + i];
+    }
+    if (threadIdx.x == 0)
+        rec_nout[e.d] = (uint32_t)m;
+}
+
+// Folds the fallback's compaction counters into the fallback statistics.
+__global__ void fb_fold(const DevCounters *__restrict__ c, unsigned long long *__restrict__ fb_stats) {
     fb_stats[0] += c->n_collected;
     fb_stats[1] += c->n_runs;
     fb_stats[2] += c->n_single;
@@ -962,33 +1015,48 @@ hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_fb_screen(const void *keys, uint64_t n, int key_words, const uint64_t *table, uint32_t table_bits,
-                            uint64_t *filter, uint64_t nb, hipStream_t stream) {
+hipError_t launch_fb_screen(const void *keys, const FbEntry *ent, uint32_t n_ent, uint64_t n, int key_words,
+                            const uint64_t *table, uint32_t table_bits, uint64_t *filter, hipStream_t stream) {
     const unsigned g = (unsigned)std::min<uint64_t>(ceil_div(n ? n : 1, 256), (uint64_t)device_cu_count() * 8);
     if (key_words == 2)
-        fb_screen<Key2><<<g, 256, 0, stream>>>(static_cast<const Key2 *>(keys), n, table, table_bits, filter, nb);
+        fb_screen<Key2><<<g, 256, 0, stream>>>(static_cast<const Key2 *>(keys), ent, n_ent, n, table, table_bits,
+                                               filter);
     else
-        fb_screen<uint64_t><<<g, 256, 0, stream>>>(static_cast<const uint64_t *>(keys), n, table, table_bits, filter,
-                                                   nb);
+        fb_screen<uint64_t><<<g, 256, 0, stream>>>(static_cast<const uint64_t *>(keys), ent, n_ent, n, table,
+                                                   table_bits, filter);
     return hipGetLastError();
 }
 
-hipError_t launch_fb_collect(const void *keys, uint64_t n, int key_words, const uint64_t *table, uint32_t table_bits,
-                             const uint64_t *filter, uint64_t nb, bool screen, void *out,
-                             unsigned long long *n_out, hipStream_t stream) {
+hipError_t launch_fb_collect(const void *keys, const FbEntry *ent, uint32_t n_ent, uint64_t n, int key_words,
+                             const uint64_t *table, uint32_t table_bits, const uint64_t *filter, bool screen,
+                             void *out, unsigned long long *n_out, hipStream_t stream) {
     const unsigned g = (unsigned)std::min<uint64_t>(ceil_div(n ? n : 1, 256), (uint64_t)device_cu_count() * 8);
     if (key_words == 2)
-        fb_collect<Key2><<<g, 256, 0, stream>>>(static_cast<const Key2 *>(keys), n, table, table_bits, filter, nb,
-                                                screen, static_cast<Key2 *>(out), n_out);
+        fb_collect<Key2><<<g, 256, 0, stream>>>(static_cast<const Key2 *>(keys), ent, n_ent, n, table, table_bits,
+                                                filter, screen, static_cast<Key2 *>(out), n_out);
     else
-        fb_collect<uint64_t><<<g, 256, 0, stream>>>(static_cast<const uint64_t *>(keys), n, table, table_bits,
-                                                    filter, nb, screen, static_cast<uint64_t *>(out), n_out);
+        fb_collect<uint64_t><<<g, 256, 0, stream>>>(static_cast<const uint64_t *>(keys), ent, n_ent, n, table,
+                                                    table_bits, filter, screen, static_cast<uint64_t *>(out), n_out);
     return hipGetLastError();
 }
 
-hipError_t launch_fb_fold(const DevCounters *c, uint32_t bucket, uint32_t *rec_nout, unsigned long long *fb_stats,
-                          hipStream_t stream) {
-    fb_fold<<<1, 1, 0, stream>>>(c, bucket, rec_nout, fb_stats);
+hipError_t launch_fb_distribute(const void *rec_keys, const uint32_t *rec_counts, const DevCounters *c,
+                                const FbEntry *ent, uint32_t n_ent, int key_words, int k, int D, void *gap_keys,
+                                uint32_t *gap_counts, uint32_t *rec_nout, unsigned long long *fb_stats,
+                                hipStream_t stream) {
+    if (n_ent) {
+        if (key_words == 2)
+            fb_distribute<Key2><<<n_ent, 256, 0, stream>>>(static_cast<const Key2 *>(rec_keys), rec_counts, c, ent, k,
+                                                           D, static_cast<Key2 *>(gap_keys), gap_counts, rec_nout);
+        else
+            fb_distribute<uint64_t><<<n_ent, 256, 0, stream>>>(static_cast<const uint64_t *>(rec_keys), rec_counts, c,
+                                                               ent, k, D, static_cast<uint64_t *>(gap_keys),
+                                                               gap_counts, rec_nout);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    fb_fold<<<1, 1, 0, stream>>>(c, fb_stats);
     return hipGetLastError();
 }
 

@@ -92,13 +92,23 @@ struct BucketArgs {
 int bucket_grid();
 int bucket_capacity(int key_words);
 hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream);
-hipError_t launch_fb_screen(const void *keys, uint64_t n, int key_words, const uint64_t *table, uint32_t table_bits,
-                            uint64_t *filter, uint64_t nb, hipStream_t stream);
-hipError_t launch_fb_collect(const void *keys, uint64_t n, int key_words, const uint64_t *table, uint32_t table_bits,
-                             const uint64_t *filter, uint64_t nb, bool screen, void *out,
-                             unsigned long long *n_out, hipStream_t stream);
-hipError_t launch_fb_fold(const DevCounters *c, uint32_t bucket, uint32_t *rec_nout, unsigned long long *fb_stats,
-                          hipStream_t stream);
+// Oversized buckets (more keys than a workgroup holds), in key order.
+struct FbEntry {
+    uint32_t d, start, ns;  // bucket, first key, number of keys
+    uint32_t wpre, fpre;    // keys and filter blocks of the entries before
+    uint32_t nb;            // filter blocks of this bucket
+};
+hipError_t launch_fb_screen(const void *keys, const FbEntry *ent, uint32_t n_ent, uint64_t n, int key_words,
+                            const uint64_t *table, uint32_t table_bits, uint64_t *filter, hipStream_t stream);
+hipError_t launch_fb_collect(const void *keys, const FbEntry *ent, uint32_t n_ent, uint64_t n, int key_words,
+                             const uint64_t *table, uint32_t table_bits, const uint64_t *filter, bool screen,
+                             void *out, unsigned long long *n_out, hipStream_t stream);
+// Copies each bucket's records (sorted records of all entries, c->n_out of
+// them) to its slot, sets rec_nout, and adds the counters to fb_stats.
+hipError_t launch_fb_distribute(const void *rec_keys, const uint32_t *rec_counts, const DevCounters *c,
+                                const FbEntry *ent, uint32_t n_ent, int key_words, int k, int D, void *gap_keys,
+                                uint32_t *gap_counts, uint32_t *rec_nout, unsigned long long *fb_stats,
+                                hipStream_t stream);
 hipError_t launch_gather(const uint32_t *rec_start, const uint32_t *rec_nout, const uint32_t *rec_off,
                          uint64_t n_buckets, const uint64_t *gap_keys, const uint32_t *gap_counts, int key_words,
                          uint64_t *out_keys, uint32_t *out_counts, hipStream_t stream);

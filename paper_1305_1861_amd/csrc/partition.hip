@@ -27,9 +27,11 @@ namespace {
 constexpr int PT_THREADS = 1024;
 constexpr int PT_WAVES = PT_THREADS / WAVE;
 constexpr int PT_MAX_BITS = 10;
-constexpr int PT_MAX_BINS = 1 << PT_MAX_BITS;  // == PT_THREADS: one bin per thread
-constexpr int PT_CH = 8;                       // tiles per chunk
-static_assert(PT_MAX_BINS == PT_THREADS, "one bin per thread");
+constexpr int PT_MAX_BINS = 1 << PT_MAX_BITS;
+constexpr int PT_BPT = PT_MAX_BINS / PT_THREADS;  // digit bins per thread
+constexpr int PT_CH = 8;                          // tiles per chunk
+constexpr int SEG_THREADS = 1024;                 // one thread per segment
+static_assert(PT_BPT * PT_THREADS == PT_MAX_BINS, "bins spread evenly over the threads");
 
 template <typename K>
 struct PtItems;
@@ -88,7 +90,7 @@ __device__ __forceinline__ uint32_t load_tile(const PartArgs &a, uint64_t t0, ui
             const uint64_t w0 = a.packed[w];
             const uint64_t w1 = w ? a.packed[w - 1] : 0;
             const uint64_t w2 = (std::is_same<K, Key2>::value && w > 1) ? a.packed[w - 2] : 0;
-            const uint32_t ok = (a.valid[w] >> first) & ((1u << ITEMS) - 1u);
+            const uint32_t ok = (a.valid[w] >> first) & (ITEMS == 32 ? ~0u : (1u << (ITEMS & 31)) - 1u);
 #pragma unroll
             for (int i = 0; i < ITEMS; i++) {
                 key[i] = K{};
@@ -155,7 +157,8 @@ __global__ __launch_bounds__(PT_THREADS) void pt_hist(PartArgs a, uint32_t *__re
         }
         return;
     }
-    s_h[tid] = 0;
+    for (int d = tid; d < PT_MAX_BINS; d += PT_THREADS)
+        s_h[d] = 0;
     __syncthreads();
     for (uint64_t t0 = c0; t0 < c1; t0 += pt_tile<K>()) {
         K key[ITEMS];
@@ -166,8 +169,8 @@ __global__ __launch_bounds__(PT_THREADS) void pt_hist(PartArgs a, uint32_t *__re
                 atomicAdd(&s_h[digit_of(key[i], a.shift, mask)], 1u);
     }
     __syncthreads();
-    if ((uint32_t)tid < bins)
-        hist[hidx + (uint64_t)tid * hstride] = s_h[tid];
+    for (uint32_t d = tid; d < bins; d += PT_THREADS)
+        hist[hidx + (uint64_t)d * hstride] = s_h[d];
 }
 
 template <typename K, bool FROM_WIN>
@@ -187,10 +190,14 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PartArgs a, const uint3
     uint32_t hstride;
     if (!chunk_range<K, FROM_WIN>(a, c0, c1, hidx, hstride))
         return;  // uniform over the block
-    const bool binned = (uint32_t)tid < bins;
-    if (binned)
-        s_cur[tid] = offs[hidx + (uint64_t)tid * hstride];
-    s_cnt[tid] = 0;
+    // thread t owns digits t * PT_BPT .. t * PT_BPT + PT_BPT - 1
+    const uint32_t d0 = (uint32_t)tid * PT_BPT;
+#pragma unroll
+    for (int j = 0; j < PT_BPT; j++) {
+        if (d0 + j < bins)
+            s_cur[d0 + j] = offs[hidx + (uint64_t)(d0 + j) * hstride];
+        s_cnt[d0 + j] = 0;
+    }
     __syncthreads();
     for (uint64_t t0 = c0; t0 < c1; t0 += TILE) {
         K key[ITEMS];
@@ -205,9 +212,15 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PartArgs a, const uint3
             }
         }
         __syncthreads();
-        // starts of the digits in the tile: thread = digit
-        const uint32_t c = s_cnt[tid];
-        const uint32_t inc = wave_inclusive_sum(c);
+        // starts of the digits in the tile
+        uint32_t c[PT_BPT];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < PT_BPT; j++) {
+            c[j] = s_cnt[d0 + j];
+            sum += c[j];
+        }
+        const uint32_t inc = wave_inclusive_sum(sum);
         if (lane == WAVE - 1)
             s_wt[wave] = inc;
         __syncthreads();
@@ -218,7 +231,12 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PartArgs a, const uint3
             before += w < wave ? t : 0u;
             n_tile += t;
         }
-        s_cnt[tid] = before + inc - c;
+        uint32_t run = before + inc - sum;
+#pragma unroll
+        for (int j = 0; j < PT_BPT; j++) {
+            s_cnt[d0 + j] = run;
+            run += c[j];
+        }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < ITEMS; i++)
@@ -233,9 +251,12 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PartArgs a, const uint3
             out[(uint64_t)s_cur[d] + (j - s_cnt[d])] = x;
         }
         __syncthreads();
-        if (binned)
-            s_cur[tid] += c;
-        s_cnt[tid] = 0;
+#pragma unroll
+        for (int j = 0; j < PT_BPT; j++) {
+            if (d0 + j < bins)
+                s_cur[d0 + j] += c[j];
+            s_cnt[d0 + j] = 0;
+        }
         __syncthreads();
     }
 }
@@ -244,7 +265,7 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PartArgs a, const uint3
 // scanned pass-1 counts (entry d * n_chunks of the scan is the start of
 // digit d).  One block.
 template <typename K>
-__global__ __launch_bounds__(PT_THREADS) void pt_segments(const uint32_t *__restrict__ offs1, uint64_t n_chunks1,
+__global__ __launch_bounds__(SEG_THREADS) void pt_segments(const uint32_t *__restrict__ offs1, uint64_t n_chunks1,
                                                           uint32_t nseg, const uint32_t *__restrict__ total,
                                                           uint32_t *__restrict__ seg, uint32_t *__restrict__ cb) {
     const uint32_t s = threadIdx.x;
@@ -256,7 +277,7 @@ __global__ __launch_bounds__(PT_THREADS) void pt_segments(const uint32_t *__rest
         end = offs1[(uint64_t)(s + 1) * n_chunks1];
     const uint32_t ch = s < nseg ? (uint32_t)(((uint64_t)(end - start) + pt_chunk<K>() - 1) / pt_chunk<K>()) : 0u;
     uint32_t n_ch;
-    const uint32_t first = block_exclusive_sum<PT_THREADS>(ch, &n_ch);
+    const uint32_t first = block_exclusive_sum<SEG_THREADS>(ch, &n_ch);
     if (s < nseg) {
         seg[s] = start;
         cb[s] = first;
@@ -312,7 +333,7 @@ hipError_t run_partition(const PartArgs &a0, void *tmp, void *out, uint32_t *scr
 
     // pass 2: tmp -> out, each segment by the next D2 bits
     const uint32_t nseg = 1u << D1;
-    pt_segments<K><<<dim3(1), block, 0, stream>>>(hist, a.n_chunks, nseg, total, seg, cb);
+    pt_segments<K><<<dim3(1), dim3(SEG_THREADS), 0, stream>>>(hist, a.n_chunks, nseg, total, seg, cb);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     PartArgs b = a0;

@@ -332,6 +332,16 @@ def test_oversized_buckets_fallback(tk, oracle_lib, k, part_bits, c):
     assert r.n_fallback >= 1
 
 
+@pytest.mark.parametrize("which,part_bits", [("small", 6), ("small", 8), ("long_k", 10)])
+def test_many_oversized_buckets(tk, oracle_lib, which, part_bits):
+    """Dozens to hundreds of oversized buckets, alone or mixed with buckets
+    that fit a workgroup, all through one fallback batch."""
+    lib = readsim.small_library(scale=0.2) if which == "small" else readsim.long_k_library(scale=0.01)
+    case(f"many oversized buckets {lib.name} part_bits={part_bits} n_bases={lib.n_bases}")
+    r = check_against_oracle(tk, oracle_lib, lib.bases, lib.offsets, lib.k, lib.c, opts=dict(part_bits=part_bits))
+    assert r.n_fallback >= 8
+
+
 def test_bucket_capacity_edges(tk, oracle_lib):
     """Buckets of exactly the register capacity and one more."""
     rng = np.random.default_rng(77)
