@@ -128,6 +128,16 @@ __device__ __forceinline__ uint32_t exclusive_parts(uint32_t *v, int m, int lane
     return inc;
 }
 
+// The value of lane - 1 (lane 0 receives its own value): a wave-wide DPP
+// shift by one lane.
+__device__ __forceinline__ uint32_t shift_up_lane(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint64_t shift_up_lane(uint64_t x) {
+    return ((uint64_t)shift_up_lane((uint32_t)(x >> 32)) << 32) | shift_up_lane((uint32_t)x);
+}
+__device__ __forceinline__ Key2 shift_up_lane(const Key2 &x) { return Key2{shift_up_lane(x.hi), shift_up_lane(x.lo)}; }
+
 // Number of lanes whose flag is set in a ballot.
 __device__ __forceinline__ uint32_t wave_count(uint64_t ball) { return (uint32_t)__popcll(ball); }
 
@@ -151,6 +161,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     uint16_t *const s_start = s_aux;
     uint16_t *const s_fo = s_aux + BK_RMAX + 1;
     __shared__ uint32_t s_mix[BK_MSD_BINS / 32];  // mixed-bin flags of the MSD pass
+    __shared__ K s_xk[ITEMS][BK_WAVES];           // key of lane 63 of every (item, wave)
+    __shared__ uint32_t s_b[4];                   // bucket ids: first key, key past the group, last loaded, last kept
     __shared__ uint32_t s_part[ITEMS][BK_WAVES];
     __shared__ uint32_t s_w[2][BK_WAVES];
     __shared__ unsigned long long s_pos[2];
@@ -186,6 +198,25 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     uint64_t pos = s_pos[0];
     const uint64_t end = s_pos[1];
     const int SB = 2 * a.k - a.D;  // key bits below the bucket digit
+    // keys of the group starting at p (item-major, sentinel past the group)
+    // and, in thread 0, the first key past it; every element is assigned so
+    // that no value is carried from one group to the next
+    K key[ITEMS];
+    K beyond = sentinel<K>();
+    auto load_group = [&](uint64_t p, int t) {
+        const uint32_t nl = (uint32_t)min<uint64_t>(CAP, end - p);
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint32_t e = (uint32_t)i * BK_THREADS + t;
+            key[i] = sentinel<K>();
+            if (p < end && e < nl)
+                key[i] = keys[p + e];
+        }
+        beyond = sentinel<K>();
+        if (t == 0 && p + nl < end)
+            beyond = keys[p + nl];
+    };
+    load_group(pos, tid0);
 
     while (pos < end) {
         // Thread indices are passed through an empty asm each iteration so
@@ -197,39 +228,44 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         const uint32_t lane = (uint32_t)tid % WAVE;
         const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
 
-        // ---- a group of whole buckets: load up to CAP keys (item-major) ----
+        // ---- a group of whole buckets: up to CAP keys, loaded by the
+        // previous iteration (item-major) ----
         const uint32_t n_load = (uint32_t)min<uint64_t>(CAP, end - pos);
         const int n_items = (int)((n_load + BK_THREADS - 1) / BK_THREADS);
-        const uint32_t d0 = bucket_of(keys[pos], a.k, a.D);
+        // publish what other lanes need: lane 63's keys (the previous key of
+        // the next wave's lane 0), the first key's bucket, the buckets of the
+        // last loaded key and of the key past the group
+        if (lane == WAVE - 1) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++)
+                if (i < n_items)
+                    s_xk[i][wave] = key[i];
+        }
+        if (tid == 0) {
+            s_b[0] = bucket_of(key[0], a.k, a.D);
+            s_b[1] = pos + n_load < end ? bucket_of(beyond, a.k, a.D) : ~0u;
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++)
+            if ((uint32_t)i * BK_THREADS + tid == n_load - 1)
+                s_b[2] = bucket_of(key[i], a.k, a.D);
+        __syncthreads();
+        const uint32_t d0 = s_b[0];
         // does the last loaded bucket continue past the loaded keys?
-        bool incomplete = false;
-        if (pos + n_load < end)
-            incomplete = bucket_of(keys[pos + n_load], a.k, a.D) == bucket_of(keys[pos + n_load - 1], a.k, a.D);
-        // every element is assigned on each iteration, so that no value is
-        // carried (and kept in registers) from one group to the next
-        K key[ITEMS];
+        const bool incomplete = s_b[1] == s_b[2];
         uint32_t rb[ITEMS];  // bucket index within the group
         uint32_t hm = 0;     // bit i: item i starts a bucket
-        // issue every load of the group before using any of them
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
-            const uint32_t e = (uint32_t)i * BK_THREADS + tid;
-            key[i] = sentinel<K>();
-            if (i < n_items && e < n_load)
-                key[i] = keys[pos + e];
-        }
-#pragma unroll
-        for (int i = 0; i < ITEMS; i++) {
-            const uint32_t e = (uint32_t)i * BK_THREADS + tid;
             rb[i] = 0;
-            if (i < n_items && e < n_load && e > 0)
-                rb[i] = bucket_of(keys[pos + e - 1], a.k, a.D);  // bucket of the previous key
-        }
-#pragma unroll
-        for (int i = 0; i < ITEMS; i++) {
             if (i < n_items) {
                 const uint32_t e = (uint32_t)i * BK_THREADS + tid;
-                const bool head = e < n_load && (e == 0 || rb[i] != bucket_of(key[i], a.k, a.D));
+                // previous key: lane - 1 of this wave, or lane 63 of the
+                // previous wave (of the previous item for thread 0)
+                K prev = shift_up_lane(key[i]);
+                if (lane == 0 && e > 0)
+                    prev = wave > 0 ? s_xk[i][wave - 1] : s_xk[i > 0 ? i - 1 : 0][BK_WAVES - 1];
+                const bool head = e < n_load && (e == 0 || bucket_of(prev, a.k, a.D) != bucket_of(key[i], a.k, a.D));
                 hm |= (uint32_t)head << i;
                 const uint64_t hb = __ballot(head);
                 rb[i] = (uint32_t)__popcll(hb & lt) + (uint32_t)head;  // inclusive, within the wave
@@ -307,6 +343,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             }
             __syncthreads();
             pos = s_pos[0];
+            load_group(pos, tid);
             __syncthreads();
             continue;
         }
@@ -314,11 +351,14 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         const uint32_t blocks_cut = r_cut == R ? nb_total : (uint32_t)s_fo[r_cut];
         if (tid == 0)
             s_fo[r_cut] = (uint16_t)blocks_cut;
-        // span of bucket ids in the group -> bits of the bucket part of the sort key
-        const uint32_t d_last = bucket_of(keys[pos + n_sb - 1], a.k, a.D);
-        const uint32_t span = d_last - d0;
-        const int RB = span ? 32 - __clz(span) : 0;
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++)
+            if ((uint32_t)i * BK_THREADS + tid == n_sb - 1)
+                s_b[3] = bucket_of(key[i], a.k, a.D);
         __syncthreads();
+        // span of bucket ids in the group -> bits of the bucket part of the sort key
+        const uint32_t span = s_b[3] - d0;
+        const int RB = span ? 32 - __clz(span) : 0;
 
         // ---- screen and collect, each bucket against its own filter ----
         // In LDS the group's filters are stored as 8 word planes (word q of
@@ -730,15 +770,14 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         uint32_t nh = 0;          // heads (runs) in this wave, wave-uniform
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
-            key[i] = sentinel<K>();
             if (i < n_it) {
                 const uint32_t base = (uint32_t)(wave * n_it + i) * WAVE;
                 const uint32_t e = base + lane;
                 bool h = false, t = false;
                 if (e < n_surv) {
-                    key[i] = s_ex[e];
-                    h = s_ex[(int)e - 1] != key[i];
-                    t = s_ex[e + 1] != key[i];
+                    const K x = s_ex[e];
+                    h = s_ex[(int)e - 1] != x;
+                    t = s_ex[e + 1] != x;
                 }
                 rh |= (uint32_t)h << i;
                 rt |= (uint32_t)t << i;
@@ -785,6 +824,9 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             kbase += w < wave ? s_w[0][w] : 0;
             n_kept += s_w[0][w];
         }
+        // the next group's keys are requested now, so that their latency
+        // overlaps the record writes and the bookkeeping below
+        load_group(pos + n_sb, tid);
         uint32_t *gcnt = a.gap_counts + pos;
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
@@ -793,7 +835,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                 const uint64_t kb = __ballot(keep);
                 if (keep) {
                     const uint32_t o = kbase + (uint32_t)__popcll(kb & lt);
-                    gap_keys[pos + o] = key[i];
+                    gap_keys[pos + o] = s_ex[(uint32_t)(wave * n_it + i) * WAVE + lane];
                     gcnt[o] = cnt[i];
                 }
                 kbase += wave_count(kb);
