@@ -80,6 +80,10 @@ def load_library():
         "tk_count_device": (ctypes.c_int, [_vp, _vp, _u64, _u64, ctypes.c_int, _u32,
                                            P(tk_options), _vp, ctypes.c_size_t, _vp,
                                            P(tk_result)]),
+        "tk_batch_workspace_size": (ctypes.c_int, [_u64, _vp, _vp, ctypes.c_int, _vp, P(tk_options),
+                                                   P(ctypes.c_size_t)]),
+        "tk_count_batch_device": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, ctypes.c_int, _vp,
+                                                 P(tk_options), _vp, ctypes.c_size_t, _vp, _vp]),
         "tk_pattern_table": (ctypes.c_int, [P(tk_options), _vp, _u64]),
         "tk_bloom_blocks": (ctypes.c_int, [_u64, _u64, ctypes.c_int, P(tk_options), P(_u64)]),
         "tk_part_bits": (ctypes.c_int, [_u64, _u64, ctypes.c_int, P(tk_options), P(ctypes.c_int)]),
@@ -103,7 +107,8 @@ def load_library():
 def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["tk_default_options", "tk_strerror", "tk_last_error", "tk_count", "tk_result_free",
-            "tk_workspace_size", "tk_count_device", "tk_pattern_table", "tk_bloom_blocks", "tk_part_bits",
+            "tk_workspace_size", "tk_count_device", "tk_batch_workspace_size", "tk_count_batch_device",
+            "tk_pattern_table", "tk_bloom_blocks", "tk_part_bits",
             "tk_pack_device", "tk_sort_scratch_size", "tk_sort_keys_device",
             "tk_compact_scratch_size", "tk_compact_device"]
 
@@ -272,6 +277,62 @@ def tk_count_device(bases, offsets, k: int, c: int, opts=None, workspace=None, s
     out = Counts(keys, counts, **_stats(r))
     out.workspace = workspace
     return out
+
+
+def _batch_arrays(lib_bases, lib_reads, c):
+    lb = np.ascontiguousarray(np.asarray(lib_bases, dtype=np.uint64))
+    lr = np.ascontiguousarray(np.asarray(lib_reads, dtype=np.uint64))
+    n_libs = lb.size - 1
+    if n_libs < 1 or lr.size != lb.size:
+        raise ValueError("lib_bases and lib_reads need n_libs + 1 entries each")
+    cc = np.full(n_libs, c, np.uint32) if np.isscalar(c) else np.ascontiguousarray(np.asarray(c, dtype=np.uint32))
+    if cc.size != n_libs:
+        raise ValueError("c needs one threshold per library")
+    return n_libs, lb, lr, cc
+
+
+def tk_batch_workspace_size(lib_bases, lib_reads, k: int, c, opts=None) -> int:
+    """Workspace bytes of tk_count_batch_device for these library boundaries."""
+    n_libs, lb, lr, cc = _batch_arrays(lib_bases, lib_reads, c)
+    o = _opts(opts)
+    out = ctypes.c_size_t(0)
+    _check(load_library().tk_batch_workspace_size(n_libs, lb.ctypes.data, lr.ctypes.data, k, cc.ctypes.data,
+                                                  _optp(o), ctypes.byref(out)), "tk_batch_workspace_size")
+    return int(out.value)
+
+
+def tk_count_batch_device(bases, offsets, lib_bases, lib_reads, k: int, c, opts=None, workspace=None,
+                          stream=None) -> list:
+    """Count a batch of libraries held in device memory (one bases/offsets
+    pair; library j owns reads lib_reads[j]..lib_reads[j+1] and bases
+    lib_bases[j]..lib_bases[j+1]).  ``c``: one threshold or one per library.
+    Returns one Counts per library, viewing the workspace."""
+    torch = _torch()
+    lib = load_library()
+    n_libs, lb, lr, cc = _batch_arrays(lib_bases, lib_reads, c)
+    o = _opts(opts)
+    need = tk_batch_workspace_size(lb, lr, k, cc, o)
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=bases.device)
+    res = (tk_result * n_libs)()
+    n_bases = int(bases.numel())
+    _check(lib.tk_count_batch_device(ctypes.c_void_p(bases.data_ptr()) if n_bases else None,
+                                     ctypes.c_void_p(offsets.data_ptr()), n_libs, lb.ctypes.data, lr.ctypes.data,
+                                     k, cc.ctypes.data, _optp(o), ctypes.c_void_p(workspace.data_ptr()),
+                                     workspace.numel(), _stream_handle(stream), res),
+           "tk_count_batch_device")
+    base = workspace.data_ptr()
+    outs = []
+    for r in res:
+        n, kw = int(r.n), int(r.key_words)
+        ko = ctypes.cast(r.keys, ctypes.c_void_p).value - base if n else 0
+        co = ctypes.cast(r.counts, ctypes.c_void_p).value - base if n else 0
+        keys = workspace[ko:ko + n * kw * 8].view(torch.int64).view(n, kw)
+        counts = workspace[co:co + n * 4].view(torch.int32)
+        out = Counts(keys, counts, **_stats(r))
+        out.workspace = workspace
+        outs.append(out)
+    return outs
 
 
 def tk_pack_device(bases, offsets, k: int, stream=None):

@@ -143,36 +143,52 @@ constexpr uint64_t MAX_BUCKET_GRID = 4096;
 
 struct Plan {
     int k, key_words;
-    uint32_t c;
-    bool screen, global;
+    uint32_t c;            // global path
+    bool screen, global;   // screen: some library has c >= 2
     Opts opts;
     uint64_t n_bases, n_reads, n_words, cap, n_blocks;
     size_t key_bytes;
-    // partitioned path
-    int D;  // bucket bits
+    // per-bucket path: the libraries of the batch
+    uint32_t n_libs;
+    std::vector<LibDesc> libs;
     uint64_t n_buckets, fb_cap, fb_nb_max;
+    PartPlan part;
     size_t part_words;
     // workspace offsets
     size_t off_ctr, off_table, off_packed, off_valid, off_starts, off_filter;
     size_t off_keys_a, off_keys_b, off_counts, off_sort, off_compact;
     size_t off_gapc, off_f, off_part, off_rec_start, off_rec_nout, off_rec_off, off_rec_scan;
-    size_t off_wg, off_fb_list, off_fb_ent, off_fbc, off_misc, total;
+    size_t off_fb_list, off_fb_ent, off_fbc, off_misc, total;
+    size_t off_libs, off_lib_keys, off_lib_stats, off_lib_ctr, off_lib_first;
     size_t sort_bytes, compact_bytes;
 };
 
 // small device values of the partitioned path
 struct Misc {
     uint32_t fb_count;
-    uint32_t totals[3];  // [0] windows, [1] records out, [2] keys after pass 2
-    unsigned long long fb_stats[4];
+    uint32_t totals[3];  // [1] records out
     DevCounters fb_ctr;
 };
 
-tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const tk_options *o, Plan *p) {
+// Plan of one call over n_libs libraries: library j owns reads
+// [lib_reads[j], lib_reads[j + 1]) and bases [lib_bases[j], lib_bases[j + 1]).
+tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *lib_reads, int k, const uint32_t *c,
+                    const tk_options *o, Plan *p) {
     if (k < 1 || k > 63)
         return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
-    if (c == 0)
-        return fail(TK_EINVAL, "threshold c must be >= 1");
+    if (n_libs == 0 || !lib_bases || !lib_reads || !c)
+        return fail(TK_EINVAL, "a batch needs at least one library and its boundaries and thresholds");
+    if (n_libs >= (1ull << 24))
+        return fail(TK_EINVAL, "%llu libraries are too many", (unsigned long long)n_libs);
+    if (lib_bases[0] != 0 || lib_reads[0] != 0)
+        return fail(TK_EINVAL, "library boundaries must start at 0");
+    for (uint64_t j = 0; j < n_libs; j++) {
+        if (lib_bases[j + 1] < lib_bases[j] || lib_reads[j + 1] < lib_reads[j])
+            return fail(TK_EINVAL, "library boundaries decrease at library %llu", (unsigned long long)j);
+        if (c[j] == 0)
+            return fail(TK_EINVAL, "threshold c of library %llu must be >= 1", (unsigned long long)j);
+    }
+    const uint64_t n_bases = lib_bases[n_libs], n_reads = lib_reads[n_libs];
     if (n_bases >= (1ull << 32))
         return fail(TK_EOVERFLOW, "n_bases = %llu must be below 2^32", (unsigned long long)n_bases);
     if (n_reads >= (1ull << 40))
@@ -181,11 +197,15 @@ tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const
     if (st != TK_OK)
         return st;
     p->k = k;
-    p->c = c;
+    p->c = c[0];
     p->key_words = k <= 31 ? 1 : 2;
     p->key_bytes = 8 * (size_t)p->key_words;
-    p->screen = c >= 2;
+    p->screen = false;
+    for (uint64_t j = 0; j < n_libs; j++)
+        p->screen = p->screen || c[j] >= 2;
     p->global = p->opts.flags & TK_FLAG_GLOBAL_FILTER;
+    if (p->global && n_libs != 1)
+        return fail(TK_EINVAL, "the global-filter path counts one library per call");
     p->n_bases = n_bases;
     p->n_reads = n_reads;
     p->n_words = ceil_div(n_bases, 32);
@@ -193,13 +213,47 @@ tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const
     p->n_blocks = (p->screen && p->global) ? bloom_blocks_for(n_bases, n_reads, k, p->opts) : 0;
     if (p->n_blocks > (1ull << 40))
         return fail(TK_EINVAL, "filter of %llu blocks is too large", (unsigned long long)p->n_blocks);
-    p->D = p->global ? -1 : part_bits_for(n_bases, n_reads, k, p->opts);
+    p->n_libs = (uint32_t)n_libs;
+    p->libs.clear();
     if (!p->global) {
-        const int D = p->D;
-        p->n_buckets = 1ull << D;
+        const uint64_t chunk = partition_chunk(p->key_words);
+        uint64_t n_ch = 0, n_hist = 0, n_seg = 0, n_bk = 0;
+        int d2max = 0;
+        p->libs.resize(n_libs);
+        for (uint64_t j = 0; j < n_libs; j++) {
+            LibDesc &L = p->libs[j];
+            L.pos0 = lib_bases[j];
+            L.pos1 = lib_bases[j + 1];
+            L.c = c[j];
+            L.D = part_bits_for(L.pos1 - L.pos0, lib_reads[j + 1] - lib_reads[j], k, p->opts);
+            L.D1 = std::min(L.D, 10);
+            L.D2 = L.D - L.D1;
+            L.nch1 = L.pos1 > L.pos0 ? (uint32_t)ceil_div(L.pos1 - (L.pos0 & ~31ull), chunk) : 0u;
+            L.cb1 = (uint32_t)n_ch;
+            L.h1 = n_hist;
+            L.seg0 = (uint32_t)n_seg;
+            L.bucket0 = (uint32_t)n_bk;
+            n_ch += L.nch1;
+            n_hist += (uint64_t)L.nch1 << L.D1;
+            n_seg += 1ull << L.D1;
+            n_bk += 1ull << L.D;
+            d2max = std::max(d2max, L.D2);
+        }
+        if (n_bk >= (1ull << 31) || n_seg >= (1ull << 28) || n_ch >= (1ull << 31))
+            return fail(TK_EINVAL, "the batch needs %llu buckets: too many (lower part_bits or split the batch)",
+                        (unsigned long long)n_bk);
+        p->n_buckets = n_bk;
+        p->part = PartPlan{};
+        p->part.k = k;
+        p->part.n_libs = (uint32_t)n_libs;
+        p->part.nch1 = (uint32_t)n_ch;
+        p->part.n_hist1 = n_hist;
+        p->part.nseg = (uint32_t)n_seg;
+        p->part.D2max = d2max;
+        p->part.cap = p->cap;
         p->fb_cap = p->cap / ((uint64_t)bucket_capacity(p->key_words) + 1) + 1;
         p->fb_nb_max = p->screen ? ceil_div((uint64_t)p->opts.beta * std::max<uint64_t>(p->cap, 1), 256) + p->fb_cap : 0;
-        p->part_words = partition_scratch_words(p->n_words * 32, p->key_words);
+        p->part_words = partition_scratch_words(p->part, p->key_words);
     }
     p->sort_bytes = radix_scratch_bytes(p->cap, p->key_words);
     p->compact_bytes = compact_scratch_bytes(p->cap);
@@ -230,14 +284,25 @@ tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const
         p->off_rec_nout = take(p->n_buckets * sizeof(uint32_t));
         p->off_rec_off = take(p->n_buckets * sizeof(uint32_t));
         p->off_rec_scan = take(scan_scratch_words(p->n_buckets) * sizeof(uint32_t));
-        p->off_wg = take(MAX_BUCKET_GRID * 4 * sizeof(unsigned long long));
         p->off_fb_list = take(p->fb_cap * 3 * sizeof(uint32_t));
         p->off_fb_ent = take(p->fb_cap * sizeof(FbEntry));
         p->off_fbc = take(p->cap * sizeof(uint32_t));
         p->off_misc = take(sizeof(Misc));
+        p->off_libs = take(n_libs * sizeof(LibDesc));
+        p->off_lib_keys = take((n_libs + 1) * sizeof(uint32_t));
+        p->off_lib_stats = take(n_libs * 4 * sizeof(unsigned long long));
+        p->off_lib_ctr = take(n_libs * sizeof(DevCounters));
+        p->off_lib_first = take(n_libs * sizeof(uint32_t));
     }
     p->total = off;
     return TK_OK;
+}
+
+tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const tk_options *o, Plan *p) {
+    const uint64_t lb[2] = {0, n_bases}, lr[2] = {0, n_reads};
+    if (c == 0)
+        return fail(TK_EINVAL, "threshold c must be >= 1");
+    return make_plan(1, lb, lr, k, &c, o, p);
 }
 
 __global__ void zero_vec(uint4 *__restrict__ p, uint64_t n) {
@@ -251,6 +316,8 @@ __global__ void zero_u32(uint32_t *__restrict__ p, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
         p[i] = 0;
 }
+
+}  // namespace
 
 // Clears n bytes (n a multiple of 4, p 4-byte aligned) with kernels rather
 // than memset nodes, so the sequence stays safe under stream capture.
@@ -275,6 +342,8 @@ hipError_t zero_bytes(void *p, size_t n, hipStream_t s) {
     zero_u32<<<dim3((unsigned)g), dim3(256), 0, s>>>(q, words);
     return hipGetLastError();
 }
+
+namespace {
 
 int g_cu_cache[64];
 
@@ -421,9 +490,9 @@ tk_status run_global(const uint8_t *d_bases, const uint64_t *d_offsets, const Pl
     return TK_OK;
 }
 
+// The per-bucket path over the plan's libraries; out[j] receives library j.
 tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, const Plan &p, char *ws,
                           hipStream_t s, tk_result *out) {
-    DevCounters *ctr = reinterpret_cast<DevCounters *>(ws + p.off_ctr);
     uint64_t *table = reinterpret_cast<uint64_t *>(ws + p.off_table);
     uint64_t *packed = reinterpret_cast<uint64_t *>(ws + p.off_packed);
     uint32_t *valid = reinterpret_cast<uint32_t *>(ws + p.off_valid);
@@ -438,20 +507,26 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
     uint32_t *rec_nout = reinterpret_cast<uint32_t *>(ws + p.off_rec_nout);
     uint32_t *rec_off = reinterpret_cast<uint32_t *>(ws + p.off_rec_off);
     uint32_t *rec_scan = reinterpret_cast<uint32_t *>(ws + p.off_rec_scan);
-    unsigned long long *wg = reinterpret_cast<unsigned long long *>(ws + p.off_wg);
     uint32_t *fb_list = reinterpret_cast<uint32_t *>(ws + p.off_fb_list);
     Misc *misc = reinterpret_cast<Misc *>(ws + p.off_misc);
+    LibDesc *d_libs = reinterpret_cast<LibDesc *>(ws + p.off_libs);
+    uint32_t *lib_keys = reinterpret_cast<uint32_t *>(ws + p.off_lib_keys);
+    unsigned long long *lib_stats = reinterpret_cast<unsigned long long *>(ws + p.off_lib_stats);
+    DevCounters *lib_ctr = reinterpret_cast<DevCounters *>(ws + p.off_lib_ctr);
+    uint32_t *lib_first = reinterpret_cast<uint32_t *>(ws + p.off_lib_first);
     const int kw = p.key_words;
+    const uint32_t L = p.n_libs;
 
     Timer tm;
     tk_status st = tm.init(p.opts.flags & TK_FLAG_TIMING);
     if (st != TK_OK)
         return st;
 
-    TK_HIP(zero_bytes(ctr, sizeof(DevCounters), s));
     TK_HIP(zero_bytes(misc, sizeof(Misc), s));
     TK_HIP(zero_bytes(starts, p.n_words * sizeof(uint32_t), s));
     TK_HIP(zero_bytes(rec_nout, p.n_buckets * sizeof(uint32_t), s));
+    TK_HIP(zero_bytes(lib_stats, (size_t)L * 4 * sizeof(unsigned long long), s));
+    TK_HIP(hipMemcpyAsync(d_libs, p.libs.data(), (size_t)L * sizeof(LibDesc), hipMemcpyHostToDevice, s));
     if (p.screen) {
         const auto &tab = pattern_table(p.opts.seed, p.opts.table_bits, p.opts.bits);
         TK_HIP(hipMemcpyAsync(table, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
@@ -463,14 +538,12 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
     if ((st = tm.end(TK_STAGE_PACK, s)) != TK_OK || (st = tm.mark(TK_STAGE_PARTITION, s)) != TK_OK)
         return st;
 
-    // keys ordered by bucket: windows -> A (through B when D > 10)
-    PartArgs pa{};
-    pa.packed = packed;
-    pa.valid = valid;
-    pa.n_elems = p.n_words * 32;
-    pa.k = p.k;
-    pa.bits = p.D;
-    TK_HIP(partition_keys(pa, keys_b, keys_a, part, p.part_words, &misc->totals[0], &misc->totals[2], s));
+    // keys ordered by (library, bucket): windows -> A (through B for D > 10)
+    PartPlan pp = p.part;
+    pp.packed = packed;
+    pp.valid = valid;
+    pp.libs = d_libs;
+    TK_HIP(partition_keys(pp, kw, keys_b, keys_a, part, p.part_words, lib_keys, s));
     uint64_t *sorted = keys_a, *other = keys_b;
     if ((st = tm.end(TK_STAGE_PARTITION, s)) != TK_OK || (st = tm.mark(TK_STAGE_BUCKET, s)) != TK_OK)
         return st;
@@ -478,11 +551,10 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
     const int grid = (int)std::min<uint64_t>((uint64_t)bucket_grid(), MAX_BUCKET_GRID);
     BucketArgs ba{};
     ba.keys = sorted;
-    ba.n_dev = &misc->totals[0];
+    ba.libs = d_libs;
+    ba.n_libs = L;
+    ba.lib_keys = lib_keys;
     ba.k = p.k;
-    ba.D = p.D;
-    ba.c = p.c;
-    ba.screen = p.screen;
     ba.beta = p.opts.beta;
     ba.table = table;
     ba.table_bits = p.opts.table_bits;
@@ -490,7 +562,7 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
     ba.gap_counts = gap_counts;
     ba.rec_start = rec_start;
     ba.rec_nout = rec_nout;
-    ba.wg_stats = wg;
+    ba.lib_stats = lib_stats;
     ba.fb_list = fb_list;
     ba.fb_count = &misc->fb_count;
     ba.fb_cap = (uint32_t)p.fb_cap;
@@ -506,83 +578,136 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
                     (unsigned long long)p.fb_cap);
 
     // buckets too large for LDS: global-memory kernels, same filter rule, all
-    // of them at once
+    // oversized buckets of a library at once
     if ((st = tm.mark(TK_STAGE_FALLBACK, s)) != TK_OK)
         return st;
+    std::vector<uint32_t> fb_per_lib(L, 0);
     if (hm.fb_count) {
         const uint32_t nf = hm.fb_count;
         std::vector<uint32_t> list(3 * (size_t)nf);
         TK_HIP(hipMemcpyAsync(list.data(), fb_list, list.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         TK_HIP(hipStreamSynchronize(s));
+        // (library, entry) in key order
+        std::vector<std::pair<uint32_t, FbEntry>> all(nf);
+        for (uint32_t i = 0; i < nf; i++) {
+            const uint32_t id = list[3 * i];
+            uint32_t lo = 0, hi = L;  // library: largest j with bucket0 <= id
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) / 2;
+                if (p.libs[mid].bucket0 <= id)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            all[i] = {lo, FbEntry{id - p.libs[lo].bucket0, list[3 * i + 1], list[3 * i + 2], 0, 0, 0}};
+        }
+        std::sort(all.begin(), all.end(), [](const std::pair<uint32_t, FbEntry> &x, const std::pair<uint32_t, FbEntry> &y) {
+            return x.first != y.first ? x.first < y.first : x.second.d < y.second.d;
+        });
+        // every library's entries with their windows (wpre: inside the
+        // library) and filter blocks (fpre: over the whole batch)
         std::vector<FbEntry> ent(nf);
-        for (uint32_t i = 0; i < nf; i++)
-            ent[i] = FbEntry{list[3 * i], list[3 * i + 1], list[3 * i + 2], 0, 0, 0};
-        std::sort(ent.begin(), ent.end(), [](const FbEntry &x, const FbEntry &y) { return x.d < y.d; });
-        uint64_t n_win = 0, n_blk = 0;
-        for (auto &e : ent) {
-            e.wpre = (uint32_t)n_win;
-            e.fpre = (uint32_t)n_blk;
-            e.nb = p.screen ? (uint32_t)std::max<uint64_t>(1, ceil_div((uint64_t)p.opts.beta * e.ns, 256)) : 0u;
-            n_win += e.ns;
-            n_blk += e.nb;
+        struct Group {
+            uint32_t lib, e0, ne;
+            uint64_t w0, n_win;  // survivors go to fbuf + w0 (at most n_win of them)
+        };
+        std::vector<Group> groups;
+        uint64_t n_blk = 0, w_all = 0;
+        for (uint32_t i = 0; i < nf;) {
+            const uint32_t j = all[i].first;
+            const bool screen = p.libs[j].c >= 2;
+            Group gr{j, i, 0, w_all, 0};
+            for (; i < nf && all[i].first == j; i++) {
+                FbEntry e = all[i].second;
+                e.wpre = (uint32_t)gr.n_win;
+                e.fpre = (uint32_t)n_blk;
+                e.nb = screen ? (uint32_t)std::max<uint64_t>(1, ceil_div((uint64_t)p.opts.beta * e.ns, 256)) : 0u;
+                gr.n_win += e.ns;
+                n_blk += e.nb;
+                ent[i] = e;
+                gr.ne++;
+            }
+            w_all += gr.n_win;
+            fb_per_lib[j] = gr.ne;
+            groups.push_back(gr);
         }
         if (n_blk > p.fb_nb_max)
             return fail(TK_EDEVICE, "fallback filters of %llu blocks exceed the reserved %llu",
                         (unsigned long long)n_blk, (unsigned long long)p.fb_nb_max);
         FbEntry *d_ent = reinterpret_cast<FbEntry *>(ws + p.off_fb_ent);
-        TK_HIP(hipMemcpyAsync(d_ent, ent.data(), nf * sizeof(FbEntry), hipMemcpyHostToDevice, s));
-        if (p.screen) {
-            TK_HIP(zero_bytes(filter, n_blk * 64, s));
-            TK_HIP(launch_fb_screen(sorted, d_ent, nf, n_win, kw, table, p.opts.table_bits, filter, s));
-        }
-        TK_HIP(zero_bytes(&misc->fb_ctr, sizeof(DevCounters), s));
-        TK_HIP(launch_fb_collect(sorted, d_ent, nf, n_win, kw, table, p.opts.table_bits, filter, p.screen, fbuf,
-                                 &misc->fb_ctr.n_collected, s));
-        unsigned long long n_surv = 0;
-        TK_HIP(hipMemcpyAsync(&n_surv, &misc->fb_ctr.n_collected, sizeof n_surv, hipMemcpyDeviceToHost, s));
-        TK_HIP(hipStreamSynchronize(s));
-        // the partitioned keys are no longer needed: `sorted` is the radix
-        // sort's second buffer
-        uint64_t *srt = nullptr;
-        int passes = 0;
-        TK_HIP(radix_sort(fbuf, sorted, n_surv, kw, 2 * p.k, ws + p.off_sort, p.sort_bytes, s, &srt, &passes));
-        uint64_t *dst = srt == fbuf ? sorted : fbuf;
         uint32_t *fb_counts = reinterpret_cast<uint32_t *>(ws + p.off_fbc);
-        TK_HIP(compact(srt, n_surv, kw, p.c, dst, fb_counts, ws + p.off_compact, p.compact_bytes, &misc->fb_ctr, s));
-        TK_HIP(launch_fb_distribute(dst, fb_counts, &misc->fb_ctr, d_ent, nf, kw, p.k, p.D, other, gap_counts,
-                                    rec_nout, misc->fb_stats, s));
+        TK_HIP(hipMemcpyAsync(d_ent, ent.data(), nf * sizeof(FbEntry), hipMemcpyHostToDevice, s));
+        TK_HIP(zero_bytes(lib_ctr, (size_t)L * sizeof(DevCounters), s));  // per-library fallback counters
+        if (p.screen)
+            TK_HIP(zero_bytes(filter, n_blk * 64, s));
+        // screen and collect every library's oversized buckets (they are read
+        // from `sorted`, which becomes free afterwards)
+        for (const Group &gr : groups) {
+            const bool screen = p.libs[gr.lib].c >= 2;
+            if (screen)
+                TK_HIP(launch_fb_screen(sorted, d_ent + gr.e0, gr.ne, gr.n_win, kw, table, p.opts.table_bits, filter,
+                                        s));
+            TK_HIP(launch_fb_collect(sorted, d_ent + gr.e0, gr.ne, gr.n_win, kw, table, p.opts.table_bits, filter,
+                                     screen, fbuf + gr.w0 * kw, &lib_ctr[gr.lib].n_collected, s));
+        }
+        std::vector<DevCounters> fc(L);
+        TK_HIP(hipMemcpyAsync(fc.data(), lib_ctr, (size_t)L * sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));  // ent, fc
+        // sort the survivors of each library (buckets partition its key
+        // space in order), compact them and file every bucket's records
+        for (const Group &gr : groups) {
+            const LibDesc &lib = p.libs[gr.lib];
+            const uint64_t n_surv = fc[gr.lib].n_collected;
+            uint64_t *src = fbuf + gr.w0 * kw, *alt = sorted + gr.w0 * kw;
+            uint64_t *srt = nullptr;
+            int passes = 0;
+            TK_HIP(radix_sort(src, alt, n_surv, kw, 2 * p.k, ws + p.off_sort, p.sort_bytes, s, &srt, &passes));
+            uint64_t *dst = srt == src ? alt : src;
+            TK_HIP(compact(srt, n_surv, kw, lib.c, dst, fb_counts + gr.w0, ws + p.off_compact, p.compact_bytes,
+                           &lib_ctr[gr.lib], s));
+            TK_HIP(launch_fb_distribute(dst, fb_counts + gr.w0, &lib_ctr[gr.lib], d_ent + gr.e0, gr.ne, kw, p.k,
+                                        lib.D, lib.bucket0, other, gap_counts, rec_nout,
+                                        lib_stats + 4 * (size_t)gr.lib, s));
+        }
     }
     if ((st = tm.end(TK_STAGE_FALLBACK, s)) != TK_OK || (st = tm.mark(TK_STAGE_GATHER, s)) != TK_OK)
         return st;
 
-    // records of every bucket in bucket order: final keys in `sorted`,
-    // final counts in F
+    // records of every bucket in (library, bucket) order: final keys in
+    // `sorted`, final counts in F
     uint32_t *out_counts = reinterpret_cast<uint32_t *>(fbuf);
     TK_HIP(launch_exclusive_scan(rec_nout, rec_off, p.n_buckets, rec_scan, &misc->totals[1], s));
     TK_HIP(launch_gather(rec_start, rec_nout, rec_off, p.n_buckets, other, gap_counts, kw, sorted, out_counts, s));
-    TK_HIP(launch_stats(wg, (uint64_t)grid, misc->fb_stats, misc->totals, ctr, s));
+    TK_HIP(launch_lib_stats(d_libs, L, lib_keys, rec_off, &misc->totals[1], lib_stats, lib_ctr, lib_first, s));
     if ((st = tm.end(TK_STAGE_GATHER, s)) != TK_OK)
         return st;
-    DevCounters h{};
-    TK_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
+    std::vector<DevCounters> h(L);
+    std::vector<uint32_t> first(L);
+    TK_HIP(hipMemcpyAsync(h.data(), lib_ctr, (size_t)L * sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    TK_HIP(hipMemcpyAsync(first.data(), lib_first, (size_t)L * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     TK_HIP(hipStreamSynchronize(s));
 
-    memset(out, 0, sizeof *out);
-    out->n = h.n_out;
-    out->k = (uint32_t)p.k;
-    out->key_words = (uint32_t)kw;
-    out->keys = sorted;
-    out->counts = out_counts;
-    out->n_windows = h.n_windows;
-    out->n_collected = h.n_collected;
-    out->n_distinct = h.n_runs;
-    out->n_singletons = h.n_single;
-    out->n_below_c = h.n_below;
-    out->bloom_blocks = 0;
-    out->sort_passes = 0;
-    out->part_bits = p.D;
-    out->n_fallback = hm.fb_count;
-    tm.read(out->stage_ms);
+    double ms[9] = {0};
+    tm.read(ms);
+    for (uint32_t j = 0; j < L; j++) {
+        tk_result &o = out[j];
+        memset(&o, 0, sizeof o);
+        o.n = h[j].n_out;
+        o.k = (uint32_t)p.k;
+        o.key_words = (uint32_t)kw;
+        o.keys = sorted + (size_t)first[j] * kw;
+        o.counts = out_counts + first[j];
+        o.n_windows = h[j].n_windows;
+        o.n_collected = h[j].n_collected;
+        o.n_distinct = h[j].n_runs;
+        o.n_singletons = h[j].n_single;
+        o.n_below_c = h[j].n_below;
+        o.bloom_blocks = 0;
+        o.sort_passes = 0;
+        o.part_bits = p.libs[j].D;
+        o.n_fallback = fb_per_lib[j];
+        memcpy(o.stage_ms, ms, sizeof ms);
+    }
     return TK_OK;
 }
 
@@ -691,6 +816,42 @@ tk_status tk_count_device(const uint8_t *d_bases, const uint64_t *d_offsets, uin
     tk_status st = make_plan(n_bases, n_reads, k, c, opts, &p);
     if (st != TK_OK)
         return st;
+    if (ws_bytes < p.total)
+        return fail(TK_EINVAL, "workspace of %zu bytes is below the %zu needed", ws_bytes, p.total);
+    return run_count(d_bases, d_offsets, p, static_cast<char *>(d_workspace), static_cast<hipStream_t>(stream),
+                     out);
+}
+
+tk_status tk_batch_workspace_size(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *lib_reads, int k,
+                                  const uint32_t *c, const tk_options *opts, size_t *bytes) {
+    if (!bytes)
+        return fail(TK_EINVAL, "bytes is NULL");
+    Plan p;
+    tk_status st = make_plan(n_libs, lib_bases, lib_reads, k, c, opts, &p);
+    if (st != TK_OK)
+        return st;
+    *bytes = p.total;
+    return TK_OK;
+}
+
+tk_status tk_count_batch_device(const uint8_t *d_bases, const uint64_t *d_offsets, uint64_t n_libs,
+                                const uint64_t *lib_bases, const uint64_t *lib_reads, int k, const uint32_t *c,
+                                const tk_options *opts, void *d_workspace, size_t ws_bytes, void *stream,
+                                tk_result *out) {
+    if (!out)
+        return fail(TK_EINVAL, "out is NULL");
+    if (!d_offsets)
+        return fail(TK_EINVAL, "offsets is NULL");
+    if (!d_workspace)
+        return fail(TK_EINVAL, "workspace is NULL");
+    if ((uintptr_t)d_workspace & 255u)
+        return fail(TK_EINVAL, "workspace must be 256-byte aligned");
+    Plan p;
+    tk_status st = make_plan(n_libs, lib_bases, lib_reads, k, c, opts, &p);
+    if (st != TK_OK)
+        return st;
+    if (p.n_bases && !d_bases)
+        return fail(TK_EINVAL, "bases is NULL");
     if (ws_bytes < p.total)
         return fail(TK_EINVAL, "workspace of %zu bytes is below the %zu needed", ws_bytes, p.total);
     return run_count(d_bases, d_offsets, p, static_cast<char *>(d_workspace), static_cast<hipStream_t>(stream),

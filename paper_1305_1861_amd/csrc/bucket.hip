@@ -52,17 +52,37 @@ __device__ __forceinline__ uint32_t bucket_of(const K &key, int k, int D) {
     return digit_of(key, 2 * k - D, (1u << D) - 1u);
 }
 
-// First index in [p, n) whose bucket is greater than the bucket of key p-1
-// (p itself when p == 0, n when p >= n).  Buckets are non-decreasing.
+// Library holding key index p: the largest j with lib_keys[j] <= p (the
+// last library for p past the keys).
+__device__ __forceinline__ uint32_t library_of(const BucketArgs &a, uint64_t p) {
+    uint32_t lo = 0, hi = a.n_libs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (a.lib_keys[mid] <= p)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// First group start at or after p: p itself at a library's first key, else
+// the first index in [p, end of the library) whose bucket is greater than
+// the bucket of key p-1 (buckets are non-decreasing inside a library).
 template <typename K>
-__device__ uint64_t next_bucket_start(const K *__restrict__ keys, uint64_t n, uint64_t p, int k, int D) {
+__device__ uint64_t group_start(const BucketArgs &a, const K *__restrict__ keys, uint64_t p) {
+    const uint64_t n = a.lib_keys[a.n_libs];
     if (p == 0 || p >= n)
-        return p >= n ? n : 0;
-    const uint32_t d = bucket_of(keys[p - 1], k, D);
-    uint64_t lo = p, hi = n;
+        return p < n ? p : n;
+    const uint32_t j = library_of(a, p);
+    if (p == a.lib_keys[j])
+        return p;
+    const int D = a.libs[j].D;
+    const uint32_t d = bucket_of(keys[p - 1], a.k, D);
+    uint64_t lo = p, hi = a.lib_keys[j + 1];
     while (lo < hi) {
         const uint64_t mid = lo + (hi - lo) / 2;
-        if (bucket_of(keys[mid], k, D) > d)
+        if (bucket_of(keys[mid], a.k, D) > d)
             hi = mid;
         else
             lo = mid + 1;
@@ -180,40 +200,57 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     K *__restrict__ gap_keys = static_cast<K *>(a.gap_keys);
     const uint32_t n_tab = 1u << a.table_bits;
     const uint32_t tmask = n_tab - 1;
-    if (a.screen)
-        for (uint32_t i = tid0; i < n_tab; i += BK_THREADS)
-            s_table[i] = a.table[i];
+    for (uint32_t i = tid0; i < n_tab; i += BK_THREADS)
+        s_table[i] = a.table[i];
     if (tid0 < 3 * BK_WAVES)
         (&s_acc[0][0])[tid0] = 0;
     if (tid0 == 0)
         s_tot[0] = 0;
 
     const uint64_t G = gridDim.x, g = blockIdx.x;
-    const uint64_t n = *a.n_dev;
+    const uint64_t n = a.lib_keys[a.n_libs];
     if (tid0 == 0) {
-        s_pos[0] = next_bucket_start(keys, n, n * g / G, a.k, a.D);
-        s_pos[1] = next_bucket_start(keys, n, n * (g + 1) / G, a.k, a.D);
+        s_pos[0] = group_start(a, keys, n * g / G);
+        s_pos[1] = group_start(a, keys, n * (g + 1) / G);
     }
     __syncthreads();
     uint64_t pos = s_pos[0];
     const uint64_t end = s_pos[1];
-    const int SB = 2 * a.k - a.D;  // key bits below the bucket digit
+    uint32_t jl = library_of(a, pos);  // library of the groups being processed
+    // statistics of library jl gathered so far go to its counters (thread 0;
+    // the counters it reads were written before a barrier)
+    auto flush_stats = [&](uint32_t j) {
+        unsigned long long t[3] = {0, 0, 0};
+        for (int w = 0; w < BK_WAVES; w++)
+            for (int q = 0; q < 3; q++) {
+                t[q] += s_acc[w][q];
+                s_acc[w][q] = 0;
+            }
+        unsigned long long *o = a.lib_stats + 4 * (uint64_t)j;
+        atomicAdd(o + 0, (unsigned long long)s_tot[0]);
+        atomicAdd(o + 1, t[2]);
+        atomicAdd(o + 2, t[0]);
+        atomicAdd(o + 3, t[1]);
+        s_tot[0] = 0;
+    };
     // keys of the group starting at p (item-major, sentinel past the group)
-    // and, in thread 0, the first key past it; every element is assigned so
-    // that no value is carried from one group to the next
+    // and, in thread 0, the first key past it inside its library; every
+    // element is assigned so that no value is carried from one group to the
+    // next
     K key[ITEMS];
     K beyond = sentinel<K>();
     auto load_group = [&](uint64_t p, int t) {
-        const uint32_t nl = (uint32_t)min<uint64_t>(CAP, end - p);
+        const uint64_t le = min(end, (uint64_t)a.lib_keys[library_of(a, p) + 1]);
+        const uint32_t nl = p < le ? (uint32_t)min<uint64_t>(CAP, le - p) : 0u;
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             const uint32_t e = (uint32_t)i * BK_THREADS + t;
             key[i] = sentinel<K>();
-            if (p < end && e < nl)
+            if (e < nl)
                 key[i] = keys[p + e];
         }
         beyond = sentinel<K>();
-        if (t == 0 && p + nl < end)
+        if (t == 0 && p + nl < le)
             beyond = keys[p + nl];
     };
     load_group(pos, tid0);
@@ -228,9 +265,25 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         const uint32_t lane = (uint32_t)tid % WAVE;
         const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
 
+        // ---- the group's library ----
+        {
+            const uint32_t jn = library_of(a, pos);
+            if (jn != jl) {
+                if (tid == 0)
+                    flush_stats(jl);
+                jl = jn;
+            }
+        }
+        const int D = a.libs[jl].D;            // bucket bits of the library
+        const uint32_t c = a.libs[jl].c;       // its threshold
+        const bool screen = c >= 2;
+        const uint32_t bucket0 = a.libs[jl].bucket0;
+        const uint64_t lend = min(end, (uint64_t)a.lib_keys[jl + 1]);
+        const int SB = 2 * a.k - D;  // key bits below the bucket digit
+
         // ---- a group of whole buckets: up to CAP keys, loaded by the
         // previous iteration (item-major) ----
-        const uint32_t n_load = (uint32_t)min<uint64_t>(CAP, end - pos);
+        const uint32_t n_load = (uint32_t)min<uint64_t>(CAP, lend - pos);
         const int n_items = (int)((n_load + BK_THREADS - 1) / BK_THREADS);
         // publish what other lanes need: lane 63's keys (the previous key of
         // the next wave's lane 0), the first key's bucket, the buckets of the
@@ -242,13 +295,13 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                     s_xk[i][wave] = key[i];
         }
         if (tid == 0) {
-            s_b[0] = bucket_of(key[0], a.k, a.D);
-            s_b[1] = pos + n_load < end ? bucket_of(beyond, a.k, a.D) : ~0u;
+            s_b[0] = bucket_of(key[0], a.k, D);
+            s_b[1] = pos + n_load < lend ? bucket_of(beyond, a.k, D) : ~0u;
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; i++)
             if ((uint32_t)i * BK_THREADS + tid == n_load - 1)
-                s_b[2] = bucket_of(key[i], a.k, a.D);
+                s_b[2] = bucket_of(key[i], a.k, D);
         __syncthreads();
         const uint32_t d0 = s_b[0];
         // does the last loaded bucket continue past the loaded keys?
@@ -265,7 +318,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                 K prev = shift_up_lane(key[i]);
                 if (lane == 0 && e > 0)
                     prev = wave > 0 ? s_xk[i][wave - 1] : s_xk[i > 0 ? i - 1 : 0][BK_WAVES - 1];
-                const bool head = e < n_load && (e == 0 || bucket_of(prev, a.k, a.D) != bucket_of(key[i], a.k, a.D));
+                const bool head = e < n_load && (e == 0 || bucket_of(prev, a.k, D) != bucket_of(key[i], a.k, D));
                 hm |= (uint32_t)head << i;
                 const uint64_t hb = __ballot(head);
                 rb[i] = (uint32_t)__popcll(hb & lt) + (uint32_t)head;  // inclusive, within the wave
@@ -308,7 +361,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             const uint32_t r = tid * rpt + j;
             if (r < R) {
                 const uint32_t ns = (uint32_t)s_start[r + 1] - s_start[r];
-                nb_sum += a.screen ? max(1u, (a.beta * ns + 255) / 256) : 0u;
+                nb_sum += screen ? max(1u, (a.beta * ns + 255) / 256) : 0u;
             }
         }
         uint32_t nb_total;
@@ -318,7 +371,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             const uint32_t r = tid * rpt + j;
             if (r < R) {
                 const uint32_t ns = (uint32_t)s_start[r + 1] - s_start[r];
-                const uint32_t nb = a.screen ? max(1u, (a.beta * ns + 255) / 256) : 0u;
+                const uint32_t nb = screen ? max(1u, (a.beta * ns + 255) / 256) : 0u;
                 s_fo[r] = (uint16_t)min(fo, 0xFFFFu);
                 const bool whole = !(incomplete && r + 1 == R_all);
                 fits += (whole && fo + nb <= FMAX) ? 1u : 0u;
@@ -330,16 +383,16 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         if (r_cut == 0) {
             // the first bucket alone exceeds the registers: fallback path
             if (tid == 0) {
-                const uint64_t e = bucket_end(keys, end, pos + n_load, d0, a.k, a.D);
+                const uint64_t e = bucket_end(keys, lend, pos + n_load, d0, a.k, D);
                 const uint64_t ns = e - pos;
                 s_pos[0] = e;
                 const uint32_t slot = atomicAdd(a.fb_count, 1u);
                 if (slot < a.fb_cap) {
-                    a.fb_list[3 * slot + 0] = d0;
+                    a.fb_list[3 * slot + 0] = bucket0 + d0;
                     a.fb_list[3 * slot + 1] = (uint32_t)pos;
                     a.fb_list[3 * slot + 2] = (uint32_t)ns;
                 }
-                a.rec_start[d0] = (uint32_t)pos;
+                a.rec_start[bucket0 + d0] = (uint32_t)pos;
             }
             __syncthreads();
             pos = s_pos[0];
@@ -354,7 +407,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
 #pragma unroll
         for (int i = 0; i < ITEMS; i++)
             if ((uint32_t)i * BK_THREADS + tid == n_sb - 1)
-                s_b[3] = bucket_of(key[i], a.k, a.D);
+                s_b[3] = bucket_of(key[i], a.k, D);
         __syncthreads();
         // span of bucket ids in the group -> bits of the bucket part of the sort key
         const uint32_t span = s_b[3] - d0;
@@ -365,7 +418,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         // block x at q * blocks_cut + x) so that the lanes of a wave touching
         // the same word of different blocks fall in different banks.
         uint32_t sv = 0;  // bit i: item i survives
-        if (a.screen) {
+        if (screen) {
             for (uint32_t i = tid; i < blocks_cut * 8; i += BK_THREADS)
                 s_filter[i] = 0;
             __syncthreads();
@@ -434,7 +487,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         for (int i = 0; i < ITEMS; i++) {
             rd[i] = 0;
             if (i < n_items && ((sv >> i) & 1u)) {
-                const uint32_t d = vdigit(key[i], mshift, MB, SB, a.k, a.D, d0);
+                const uint32_t d = vdigit(key[i], mshift, MB, SB, a.k, D, d0);
                 const uint32_t sh = (d & 1u) * 16u;
                 const uint32_t old = atomicAdd(&s_c32[d >> 1], 1u << sh);
                 rd[i] = (((old >> sh) & 0xFFFFu) << BK_MSD_BITS) | d;
@@ -471,8 +524,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             if (i < n_ch && e > 0 && e < n_surv) {
                 const K x = s_ex[e], y = s_ex[e - 1];
                 if (x != y) {
-                    const uint32_t dx = vdigit(x, mshift, MB, SB, a.k, a.D, d0);
-                    if (dx == vdigit(y, mshift, MB, SB, a.k, a.D, d0))
+                    const uint32_t dx = vdigit(x, mshift, MB, SB, a.k, D, d0);
+                    if (dx == vdigit(y, mshift, MB, SB, a.k, D, d0))
                         atomicOr(&s_mix[dx >> 5], 1u << (dx & 31u));
                 }
             }
@@ -613,7 +666,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                     const uint32_t e = (uint32_t)i * BK_THREADS + tid;
                     bool f = false;
                     if (e < n_surv) {
-                        const uint32_t d = vdigit(s_ex[e], mshift, MB, SB, a.k, a.D, d0);
+                        const uint32_t d = vdigit(s_ex[e], mshift, MB, SB, a.k, D, d0);
                         f = (s_mix[d >> 5] >> (d & 31u)) & 1u;
                     }
                     fm |= (uint32_t)f << i;
@@ -674,7 +727,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                         for (int j = 0; j < IL; j++) {
                             const int i = i0 + j;
                             act[j] = i < ITEMS && ((sv >> i) & 1u);
-                            dg[j] = act[j] ? vdigit(key[i], shift, BK_SORT_BITS, SB, a.k, a.D, d0) : 0u;
+                            dg[j] = act[j] ? vdigit(key[i], shift, BK_SORT_BITS, SB, a.k, D, d0) : 0u;
                             peers[j] = __ballot(act[j]);
                         }
 #pragma unroll
@@ -812,8 +865,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                 if (hb)
                     carry = base + 63u - (uint32_t)__clzll(hb);
                 single += wave_count(__ballot(cnt[i] == 1));
-                below += wave_count(__ballot(cnt[i] >= 2 && cnt[i] < a.c));
-                nk += wave_count(__ballot(cnt[i] >= a.c));
+                below += wave_count(__ballot(cnt[i] >= 2 && cnt[i] < c));
+                nk += wave_count(__ballot(cnt[i] >= c));
             }
         }
         if (lane == 0)
@@ -831,7 +884,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             if (i < n_it) {
-                const bool keep = cnt[i] >= a.c;
+                const bool keep = cnt[i] >= c;
                 const uint64_t kb = __ballot(keep);
                 if (keep) {
                     const uint32_t o = kbase + (uint32_t)__popcll(kb & lt);
@@ -848,28 +901,17 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         }
         if (tid == 0) {
             // the group's records are filed under its first bucket
-            a.rec_start[d0] = (uint32_t)pos;
-            a.rec_nout[d0] = n_kept;
+            a.rec_start[bucket0 + d0] = (uint32_t)pos;
+            a.rec_nout[bucket0 + d0] = n_kept;
             s_tot[0] += n_surv;
         }
         pos += n_sb;
         __syncthreads();  // shared buffers are reused by the next group
     }
-    // per-workgroup statistics (no contended atomics)
+    // statistics of the last library of this workgroup
     __syncthreads();
-    if (tid0 == 0) {
-        unsigned long long s1 = 0, s2 = 0, s3 = 0;
-        for (int w = 0; w < BK_WAVES; w++) {
-            s1 += s_acc[w][0];
-            s2 += s_acc[w][1];
-            s3 += s_acc[w][2];
-        }
-        unsigned long long *o = a.wg_stats + 4 * g;
-        o[0] = s_tot[0];
-        o[1] = s3;
-        o[2] = s1;
-        o[3] = s2;
-    }
+    if (tid0 == 0)
+        flush_stats(jl);
 }
 
 // ---- fallback: oversized buckets, all at once, with global-memory kernels --
@@ -953,7 +995,7 @@ __global__ __launch_bounds__(256) void fb_collect(const K *__restrict__ keys, co
 template <typename K>
 __global__ __launch_bounds__(256) void fb_distribute(const K *__restrict__ rec_keys, const uint32_t *__restrict__ rec_counts,
                                                      const DevCounters *__restrict__ c, const FbEntry *__restrict__ ent,
-                                                     int k, int D, K *__restrict__ gap_keys,
+                                                     int k, int D, uint32_t bucket0, K *__restrict__ gap_keys,
                                                      uint32_t *__restrict__ gap_counts, uint32_t *__restrict__ rec_nout) {
     __shared__ uint64_t s_r[2];
     const FbEntry e = ent[blockIdx.x];
@@ -978,15 +1020,15 @@ __global__ __launch_bounds__(256) void fb_distribute(const K *__restrict__ rec_k
         gap_counts[e.start + i] = rec_counts[r0 + i];
     }
     if (threadIdx.x == 0)
-        rec_nout[e.d] = (uint32_t)m;
+        rec_nout[bucket0 + e.d] = (uint32_t)m;
 }
 
-// Folds the fallback's compaction counters into the fallback statistics.
-__global__ void fb_fold(const DevCounters *__restrict__ c, unsigned long long *__restrict__ fb_stats) {
-    fb_stats[0] += c->n_collected;
-    fb_stats[1] += c->n_runs;
-    fb_stats[2] += c->n_single;
-    fb_stats[3] += c->n_below;
+// Folds the fallback's compaction counters into the library's statistics.
+__global__ void fb_fold(const DevCounters *__restrict__ c, unsigned long long *__restrict__ stats) {
+    stats[0] += c->n_collected;
+    stats[1] += c->n_runs;
+    stats[2] += c->n_single;
+    stats[3] += c->n_below;
 }
 
 // ---- gather: records of every bucket, in bucket order, into place ---------
@@ -1015,30 +1057,27 @@ __global__ __launch_bounds__(256) void gather_kernel(const uint32_t *__restrict_
     }
 }
 
-__global__ void stats_kernel(const unsigned long long *__restrict__ wg_stats, uint64_t n_wg,
-                             const unsigned long long *__restrict__ fb_stats, const uint32_t *__restrict__ totals,
-                             DevCounters *__restrict__ ctr) {
-    // one block: totals[0] = windows, totals[1] = records out
-    __shared__ unsigned long long s[4][256];
-    unsigned long long v[4] = {0, 0, 0, 0};
-    for (uint64_t i = threadIdx.x; i < n_wg; i += blockDim.x)
-        for (int j = 0; j < 4; j++)
-            v[j] += wg_stats[4 * i + j];
-    for (int j = 0; j < 4; j++)
-        s[j][threadIdx.x] = v[j];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t[4] = {0, 0, 0, 0};
-        for (int i = 0; i < (int)blockDim.x; i++)
-            for (int j = 0; j < 4; j++)
-                t[j] += s[j][i];
-        ctr->n_windows = totals[0];
-        ctr->n_out = totals[1];
-        ctr->n_collected = t[0] + fb_stats[0];
-        ctr->n_runs = t[1] + fb_stats[1];
-        ctr->n_single = t[2] + fb_stats[2];
-        ctr->n_below = t[3] + fb_stats[3];
-    }
+// Per-library counters; one thread per library.
+__global__ __launch_bounds__(256) void lib_stats_kernel(const LibDesc *__restrict__ libs, uint32_t n_libs,
+                                                        const uint32_t *__restrict__ lib_keys,
+                                                        const uint32_t *__restrict__ rec_off,
+                                                        const uint32_t *__restrict__ rec_total,
+                                                        const unsigned long long *__restrict__ stats,
+                                                        DevCounters *__restrict__ ctr, uint32_t *__restrict__ out_first) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_libs)
+        return;
+    const uint32_t first = rec_off[libs[j].bucket0];
+    const uint32_t next = j + 1 < n_libs ? rec_off[libs[j + 1].bucket0] : *rec_total;
+    DevCounters c{};
+    c.n_windows = lib_keys[j + 1] - lib_keys[j];
+    c.n_out = next - first;
+    c.n_collected = stats[4 * (uint64_t)j + 0];
+    c.n_runs = stats[4 * (uint64_t)j + 1];
+    c.n_single = stats[4 * (uint64_t)j + 2];
+    c.n_below = stats[4 * (uint64_t)j + 3];
+    ctr[j] = c;
+    out_first[j] = first;
 }
 
 }  // namespace
@@ -1083,22 +1122,23 @@ hipError_t launch_fb_collect(const void *keys, const FbEntry *ent, uint32_t n_en
 }
 
 hipError_t launch_fb_distribute(const void *rec_keys, const uint32_t *rec_counts, const DevCounters *c,
-                                const FbEntry *ent, uint32_t n_ent, int key_words, int k, int D, void *gap_keys,
-                                uint32_t *gap_counts, uint32_t *rec_nout, unsigned long long *fb_stats,
-                                hipStream_t stream) {
+                                const FbEntry *ent, uint32_t n_ent, int key_words, int k, int D, uint32_t bucket0,
+                                void *gap_keys, uint32_t *gap_counts, uint32_t *rec_nout,
+                                unsigned long long *lib_stats, hipStream_t stream) {
     if (n_ent) {
         if (key_words == 2)
             fb_distribute<Key2><<<n_ent, 256, 0, stream>>>(static_cast<const Key2 *>(rec_keys), rec_counts, c, ent, k,
-                                                           D, static_cast<Key2 *>(gap_keys), gap_counts, rec_nout);
+                                                           D, bucket0, static_cast<Key2 *>(gap_keys), gap_counts,
+                                                           rec_nout);
         else
             fb_distribute<uint64_t><<<n_ent, 256, 0, stream>>>(static_cast<const uint64_t *>(rec_keys), rec_counts, c,
-                                                               ent, k, D, static_cast<uint64_t *>(gap_keys),
+                                                               ent, k, D, bucket0, static_cast<uint64_t *>(gap_keys),
                                                                gap_counts, rec_nout);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
     }
-    fb_fold<<<1, 1, 0, stream>>>(c, fb_stats);
+    fb_fold<<<1, 1, 0, stream>>>(c, lib_stats);
     return hipGetLastError();
 }
 
@@ -1114,9 +1154,13 @@ hipError_t launch_gather(const uint32_t *rec_start, const uint32_t *rec_nout, co
     return hipGetLastError();
 }
 
-hipError_t launch_stats(const unsigned long long *wg_stats, uint64_t n_wg, const unsigned long long *fb_stats,
-                        const uint32_t *totals, DevCounters *ctr, hipStream_t stream) {
-    stats_kernel<<<1, 256, 0, stream>>>(wg_stats, n_wg, fb_stats, totals, ctr);
+hipError_t launch_lib_stats(const LibDesc *libs, uint32_t n_libs, const uint32_t *lib_keys, const uint32_t *rec_off,
+                            const uint32_t *rec_total, const unsigned long long *lib_stats, DevCounters *ctr,
+                            uint32_t *out_first, hipStream_t stream) {
+    if (!n_libs)
+        return hipSuccess;
+    lib_stats_kernel<<<dim3((unsigned)ceil_div(n_libs, 256)), dim3(256), 0, stream>>>(
+        libs, n_libs, lib_keys, rec_off, rec_total, lib_stats, ctr, out_first);
     return hipGetLastError();
 }
 

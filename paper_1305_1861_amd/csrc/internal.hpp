@@ -25,6 +25,9 @@ struct DevCounters {
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Clears n bytes (n a multiple of 4, p 4-byte aligned) with fill kernels.
+hipError_t zero_bytes(void *p, size_t n, hipStream_t stream);
+
 // ---- pack.hip -------------------------------------------------------------
 // starts: n_words uint32, must be zero on entry.  n_windows may be null.
 hipError_t launch_pack(const uint8_t *bases, const uint64_t *offsets, uint64_t n_bases,
@@ -47,54 +50,73 @@ hipError_t launch_screen(const BloomArgs &a, int grid, hipStream_t stream);
 hipError_t launch_collect(const BloomArgs &a, bool screen, void *keys, uint64_t capacity,
                           unsigned long long *n_collected, int grid, hipStream_t stream);
 
+// ---- libraries of a batch --------------------------------------------------
+// Device table, one entry per library.  The libraries' reads are consecutive
+// in the bases/offsets arrays; a window belongs to the library holding its
+// last base, and window positions are base positions.
+struct LibDesc {
+    uint64_t pos0, pos1;  // window positions [pos0, pos1)
+    uint64_t h1;          // partition pass 1: first count entry of the library
+    uint32_t cb1, nch1;   // pass 1: first chunk, number of chunks
+    uint32_t seg0;        // pass 2: first segment (2^D1 segments per library)
+    uint32_t bucket0;     // first bucket id (2^D buckets per library)
+    uint32_t c;           // threshold
+    int D, D1, D2;        // bucket bits D = D1 (pass 1) + D2 (pass 2)
+};
+
 // ---- partition.hip --------------------------------------------------------
-// Keys of every valid window ordered by their top D = bits bits (D <= 20),
-// in one pass (D <= 10) or two; the order inside a bucket is unspecified.
-// Input: the packed reads (n_elems = n_words * 32 window positions).  tmp
-// (pass-1 output when D > 10) and out hold n_elems keys each; out receives
-// the result and *total (device) the number of keys; *total2 (device) the
-// number moved by pass 2.
-struct PartArgs {
+// Keys of every valid window, ordered by (library, top D bits): every bucket
+// is one contiguous range.  Pass 1 extracts the canonical keys from the
+// packed reads and orders them by (library, top D1 bits); pass 2, run when
+// some library has D2 > 0, orders every (library, top-digit) segment by the
+// next D2 bits (D2 = 0: a copy).  The order inside a bucket is unspecified.
+// Pass-1 chunks are per library: chunk i of library j covers window
+// positions [floor32(pos0) + i * chunk, ...) inside [pos0, pos1).
+uint64_t partition_chunk(int key_words);  // window positions (pass 1) or keys (pass 2) per chunk
+struct PartPlan {
     const uint64_t *packed;
     const uint32_t *valid;
-    const void *keys_in;  // pass 2: the pass-1 output
-    uint64_t n_elems;
     int k;
-    int shift, bits;
-    uint64_t n_chunks;    // pass 1: chunks
-    const uint32_t *seg;  // pass 2: segment starts (nseg + 1)
-    const uint32_t *cb;   // pass 2: first chunk of each segment (nseg + 1)
-    uint32_t nseg;
+    const LibDesc *libs;  // device
+    uint32_t n_libs;
+    uint32_t nch1;        // pass-1 chunks of all libraries
+    uint64_t n_hist1;     // pass-1 count entries of all libraries
+    uint32_t nseg;        // pass-2 segments of all libraries
+    int D2max;            // largest pass-2 digit; 0: no second pass
+    uint64_t cap;         // key capacity of tmp and out
 };
-size_t partition_scratch_words(uint64_t n_pos, int key_words);
-hipError_t partition_keys(const PartArgs &a, void *tmp, void *out, uint32_t *scratch, size_t scratch_words,
-                          uint32_t *total, uint32_t *total2, hipStream_t stream);
+size_t partition_scratch_words(const PartPlan &p, int key_words);
+// out receives the keys; lib_keys (device, n_libs + 1) the first key of
+// every library and the number of keys.
+hipError_t partition_keys(const PartPlan &p, int key_words, void *tmp, void *out, uint32_t *scratch,
+                          size_t scratch_words, uint32_t *lib_keys, hipStream_t stream);
 
 // ---- bucket.hip -----------------------------------------------------------
 struct BucketArgs {
-    const void *keys;         // keys ordered by bucket (top D bits)
-    const uint32_t *n_dev;    // number of keys (device)
-    int k, D;
-    uint32_t c;
-    int screen;
+    const void *keys;         // keys ordered by (library, bucket)
+    const LibDesc *libs;      // device
+    uint32_t n_libs;
+    const uint32_t *lib_keys; // first key of every library, number of keys (device)
+    int k;
     uint32_t beta;
     const uint64_t *table;
     uint32_t table_bits;
-    void *gap_keys;        // records of a bucket start at the bucket's first index
+    void *gap_keys;        // records of a group start at the group's first index
     uint32_t *gap_counts;
-    uint32_t *rec_start;   // per bucket: first index, number of records
+    uint32_t *rec_start;   // per bucket id: first index, number of records
     uint32_t *rec_nout;
-    unsigned long long *wg_stats;  // per workgroup: collected, runs, singletons, below c
-    uint32_t *fb_list;     // oversized buckets: (bucket, start, size)
+    unsigned long long *lib_stats;  // per library: collected, runs, singletons, below c
+    uint32_t *fb_list;     // oversized buckets: (bucket id, start, size)
     uint32_t *fb_count;
     uint32_t fb_cap;
 };
 int bucket_grid();
 int bucket_capacity(int key_words);
 hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream);
-// Oversized buckets (more keys than a workgroup holds), in key order.
+// Oversized buckets (more keys than a workgroup holds) of one library, in
+// key order.
 struct FbEntry {
-    uint32_t d, start, ns;  // bucket, first key, number of keys
+    uint32_t d, start, ns;  // bucket within the library, first key, number of keys
     uint32_t wpre, fpre;    // keys and filter blocks of the entries before
     uint32_t nb;            // filter blocks of this bucket
 };
@@ -104,16 +126,21 @@ hipError_t launch_fb_collect(const void *keys, const FbEntry *ent, uint32_t n_en
                              const uint64_t *table, uint32_t table_bits, const uint64_t *filter, bool screen,
                              void *out, unsigned long long *n_out, hipStream_t stream);
 // Copies each bucket's records (sorted records of all entries, c->n_out of
-// them) to its slot, sets rec_nout, and adds the counters to fb_stats.
+// them) to its slot, sets rec_nout[bucket0 + d], and adds the counters to
+// the library's statistics.
 hipError_t launch_fb_distribute(const void *rec_keys, const uint32_t *rec_counts, const DevCounters *c,
-                                const FbEntry *ent, uint32_t n_ent, int key_words, int k, int D, void *gap_keys,
-                                uint32_t *gap_counts, uint32_t *rec_nout, unsigned long long *fb_stats,
-                                hipStream_t stream);
+                                const FbEntry *ent, uint32_t n_ent, int key_words, int k, int D, uint32_t bucket0,
+                                void *gap_keys, uint32_t *gap_counts, uint32_t *rec_nout,
+                                unsigned long long *lib_stats, hipStream_t stream);
 hipError_t launch_gather(const uint32_t *rec_start, const uint32_t *rec_nout, const uint32_t *rec_off,
                          uint64_t n_buckets, const uint64_t *gap_keys, const uint32_t *gap_counts, int key_words,
                          uint64_t *out_keys, uint32_t *out_counts, hipStream_t stream);
-hipError_t launch_stats(const unsigned long long *wg_stats, uint64_t n_wg, const unsigned long long *fb_stats,
-                        const uint32_t *totals, DevCounters *ctr, hipStream_t stream);
+// Per-library counters: windows from lib_keys, records and their first
+// index from the scanned record counts (rec_off, total), the rest from
+// lib_stats.  out_first[j]: first output record of library j.
+hipError_t launch_lib_stats(const LibDesc *libs, uint32_t n_libs, const uint32_t *lib_keys, const uint32_t *rec_off,
+                            const uint32_t *rec_total, const unsigned long long *lib_stats, DevCounters *ctr,
+                            uint32_t *out_first, hipStream_t stream);
 
 // ---- scan.hip -------------------------------------------------------------
 // Exclusive prefix sum of n uint32 values (in may equal out).  *total (device)

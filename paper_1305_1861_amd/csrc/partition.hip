@@ -1,23 +1,23 @@
-// Partitioning of the window keys by their top D bits (D <= 20) -- the GPU
-// counterpart of routing every k-mer to the consumer that owns its filter
-// (paper §2.1, parallelization): afterwards every bucket (keys sharing their
-// top D bits) is one contiguous range and the buckets are in key order, so
-// per-bucket sort-and-compact results concatenate into the sorted answer.
+// Partitioning of the window keys by (library, top D bits), D <= 20 -- the
+// GPU counterpart of routing every k-mer to the consumer that owns its filter
+// (paper §2.1, parallelization): afterwards every bucket (keys of one library
+// sharing their top D bits) is one contiguous range, libraries follow each
+// other and buckets are in key order inside a library, so per-bucket
+// sort-and-compact results concatenate into each library's sorted answer.
 //
 // Pass 1 extracts the canonical keys straight from the packed reads (§2.1,
-// k-mer extraction) and orders them by their top D1 = min(D, 10) bits
-// ("segments").  When D > 10, pass 2 orders every segment by the next
-// D2 = D - 10 bits.  The order of keys inside a bucket is not kept -- the
-// bucket kernel sorts each bucket -- so both passes rank keys with LDS atomic
-// counters instead of a stable ranking.
+// k-mer extraction) and orders them by (library, top D1 = min(D, 10) bits):
+// the "segments".  Pass 2 orders every segment by the next D2 = D - D1 bits
+// (a plain copy for libraries with D2 = 0).  The order of keys inside a
+// bucket is not kept -- the bucket kernel sorts each bucket -- so both passes
+// rank keys with LDS atomic counters instead of a stable ranking.
 //
-// Work unit: a chunk of up to PT_CH tiles, one workgroup each.  hist counts
-// the chunk's digits; the counts are laid out so that one exclusive scan
-// gives every (chunk, digit) its write position.  scatter, per tile: rank
-// every key within its digit (LDS atomics), stage the tile in LDS in digit
-// order, write each digit's run contiguously at the chunk's cursor for that
-// digit.  Pass-2 chunks never straddle a segment: chunk j of segment s covers
-// keys [seg[s] + j * CHUNK, min(seg[s] + (j + 1) * CHUNK, seg[s + 1])).
+// Work unit: a chunk of up to PT_CH tiles, one workgroup each; chunks never
+// straddle a library (pass 1) or a segment (pass 2).  hist counts the chunk's
+// digits; the counts are laid out (library or segment, digit, chunk) so that
+// one exclusive scan gives every (chunk, digit) its write position.  scatter,
+// per tile: rank every key within its digit (LDS atomics), stage the tile in
+// LDS in digit order, write each digit's run contiguously at its cursor.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -30,7 +30,7 @@ constexpr int PT_MAX_BITS = 10;
 constexpr int PT_MAX_BINS = 1 << PT_MAX_BITS;
 constexpr int PT_BPT = PT_MAX_BINS / PT_THREADS;  // digit bins per thread
 constexpr int PT_CH = 8;                          // tiles per chunk
-constexpr int SEG_THREADS = 1024;                 // one thread per segment
+constexpr int SEG_THREADS = 256;
 static_assert(PT_BPT * PT_THREADS == PT_MAX_BINS, "bins spread evenly over the threads");
 
 template <typename K>
@@ -53,47 +53,105 @@ constexpr uint64_t pt_chunk() {
     return pt_tile<K>() * PT_CH;
 }
 
-// Segment s and chunk index j of pass-2 workgroup b; false for workgroups
-// beyond the last chunk.  cb[s] is the first chunk of segment s, cb[nseg]
-// the number of chunks.
-__device__ __forceinline__ bool seg_chunk(const uint32_t *__restrict__ cb, uint32_t nseg, uint32_t b, uint32_t &s,
-                                          uint32_t &j) {
-    if (b >= cb[nseg])
-        return false;
-    uint32_t lo = 0, hi = nseg;  // largest s with cb[s] <= b
+// Largest i in [0, n) with at(i) <= v, for a non-decreasing at(); 0 if none.
+template <typename F>
+__device__ __forceinline__ uint32_t last_le(uint32_t n, uint64_t v, F at) {
+    uint32_t lo = 0, hi = n;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) / 2;
-        if (cb[mid] <= b)
+        if (at(mid) <= v)
             lo = mid;
         else
             hi = mid;
     }
-    s = lo;
-    j = b - cb[lo];
+    return lo;
+}
+
+struct PassArgs {
+    const uint64_t *packed;
+    const uint32_t *valid;
+    const void *keys_in;     // pass 2: the pass-1 output
+    int k;
+    const LibDesc *libs;
+    uint32_t n_libs;
+    const uint32_t *seg;     // pass 2: start of every segment (nseg + 1)
+    const uint32_t *cb;      // pass 2: first chunk of every segment (nseg + 1)
+    const uint32_t *eb;      // pass 2: first count entry of every segment (nseg + 1)
+    uint32_t nseg;
+};
+
+// The chunk of this workgroup: elements [c0, c1) (window positions of pass
+// 1, below which `lo` masks positions of the previous library; keys of pass
+// 2), its count entries hidx + d * hstride, and its digit (shift, bits).
+struct Chunk {
+    uint64_t c0, c1, lo, hidx;
+    uint32_t hstride;
+    int shift, bits;
+};
+
+template <typename K, bool FROM_WIN>
+__device__ __forceinline__ bool chunk_of(const PassArgs &a, Chunk &ch) {
+    const uint32_t b = blockIdx.x;
+    if (FROM_WIN) {
+        const uint32_t j = last_le(a.n_libs, b, [&](uint32_t i) { return (uint64_t)a.libs[i].cb1; });
+        const LibDesc L = a.libs[j];
+        if (b < L.cb1 || b >= L.cb1 + L.nch1)
+            return false;
+        const uint32_t i = b - L.cb1;
+        ch.c0 = (L.pos0 & ~31ull) + (uint64_t)i * pt_chunk<K>();
+        ch.c1 = min(ch.c0 + pt_chunk<K>(), L.pos1);
+        ch.lo = L.pos0;
+        ch.hidx = L.h1 + i;
+        ch.hstride = L.nch1;
+        ch.shift = 2 * a.k - L.D1;
+        ch.bits = L.D1;
+        return true;
+    }
+    if (b >= a.cb[a.nseg])
+        return false;
+    const uint32_t s = last_le(a.nseg, b, [&](uint32_t i) { return (uint64_t)a.cb[i]; });
+    const uint32_t j = last_le(a.n_libs, s, [&](uint32_t i) { return (uint64_t)a.libs[i].seg0; });
+    const uint32_t i = b - a.cb[s];
+    ch.c0 = a.seg[s] + (uint64_t)i * pt_chunk<K>();
+    ch.c1 = min(ch.c0 + pt_chunk<K>(), (uint64_t)a.seg[s + 1]);
+    ch.lo = ch.c0;
+    ch.hidx = a.eb[s] + i;
+    ch.hstride = a.cb[s + 1] - a.cb[s];
+    ch.shift = 2 * a.k - a.libs[j].D;
+    ch.bits = a.libs[j].D2;
     return true;
 }
 
 // Keys of one tile into registers.  Pass 1: the tile is PT_TILE window
-// positions; thread t takes ITEMS consecutive windows of one packed word.
-// Pass 2: keys [k0, k1) of the pass-1 output, item-major.  Bit i of the
+// positions starting at a word boundary; thread t takes ITEMS consecutive
+// windows of one packed word; positions outside [lo, t1) are skipped.
+// Pass 2: keys [t0, t1) of the pass-1 output, item-major.  Bit i of the
 // result: item i holds a key.
 template <typename K, bool FROM_WIN>
-__device__ __forceinline__ uint32_t load_tile(const PartArgs &a, uint64_t t0, uint64_t t1, K (&key)[PtItems<K>::value]) {
+__device__ __forceinline__ uint32_t load_tile(const PassArgs &a, uint64_t t0, uint64_t t1, uint64_t lo,
+                                              K (&key)[PtItems<K>::value]) {
     constexpr int ITEMS = PtItems<K>::value;
     const int tid = threadIdx.x;
     uint32_t vm = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++)
+        key[i] = K{};
     if (FROM_WIN) {
         constexpr int PER_WORD = 32 / ITEMS;  // threads per packed word
         const uint64_t w = t0 / 32 + (uint64_t)(tid / PER_WORD);
         const uint32_t first = (uint32_t)(tid % PER_WORD) * ITEMS;
-        if (w * 32 + first < t1) {
+        const uint64_t p0 = w * 32 + first;  // position of item 0
+        if (p0 < t1 && p0 + ITEMS > lo) {
             const uint64_t w0 = a.packed[w];
             const uint64_t w1 = w ? a.packed[w - 1] : 0;
             const uint64_t w2 = (std::is_same<K, Key2>::value && w > 1) ? a.packed[w - 2] : 0;
-            const uint32_t ok = (a.valid[w] >> first) & (ITEMS == 32 ? ~0u : (1u << (ITEMS & 31)) - 1u);
+            uint32_t ok = (a.valid[w] >> first) & (ITEMS == 32 ? ~0u : (1u << (ITEMS & 31)) - 1u);
+            if (p0 < lo)
+                ok &= ~0u << (uint32_t)(lo - p0);  // lo - p0 < ITEMS
+            if (p0 + ITEMS > t1)
+                ok &= (1u << (uint32_t)(t1 - p0)) - 1u;  // t1 - p0 < ITEMS
 #pragma unroll
             for (int i = 0; i < ITEMS; i++) {
-                key[i] = K{};
                 if ((ok >> i) & 1u) {
                     key[i] = KeyOf<std::is_same<K, Key2>::value>::get(w0, w1, w2, first + i, a.k);
                     vm |= 1u << i;
@@ -105,7 +163,6 @@ __device__ __forceinline__ uint32_t load_tile(const PartArgs &a, uint64_t t0, ui
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             const uint64_t e = t0 + (uint64_t)i * PT_THREADS + tid;
-            key[i] = K{};
             if (e < t1) {
                 key[i] = in[e];
                 vm |= 1u << i;
@@ -115,66 +172,33 @@ __device__ __forceinline__ uint32_t load_tile(const PartArgs &a, uint64_t t0, ui
     return vm;
 }
 
-// Element range of the chunk this workgroup owns: [c0, c1).
 template <typename K, bool FROM_WIN>
-__device__ __forceinline__ bool chunk_range(const PartArgs &a, uint64_t &c0, uint64_t &c1, uint64_t &hidx,
-                                            uint32_t &hstride) {
-    const uint32_t b = blockIdx.x;
-    if (FROM_WIN) {
-        c0 = (uint64_t)b * pt_chunk<K>();
-        c1 = min(c0 + pt_chunk<K>(), a.n_elems);
-        hidx = b;                        // entry of digit d: d * n_chunks + b
-        hstride = (uint32_t)a.n_chunks;  // chunks of pass 1
-        return c0 < c1;
-    }
-    uint32_t s, j;
-    if (!seg_chunk(a.cb, a.nseg, b, s, j))
-        return false;
-    const uint64_t s0 = a.seg[s], s1 = a.seg[s + 1];
-    c0 = s0 + (uint64_t)j * pt_chunk<K>();
-    c1 = min(c0 + pt_chunk<K>(), s1);
-    const uint32_t nch = a.cb[s + 1] - a.cb[s];
-    hidx = (uint64_t)a.cb[s] * (1u << a.bits) + j;  // entry of digit d: cb[s] * bins + d * nch + j
-    hstride = nch;
-    return true;
-}
-
-template <typename K, bool FROM_WIN>
-__global__ __launch_bounds__(PT_THREADS) void pt_hist(PartArgs a, uint32_t *__restrict__ hist) {
+__global__ __launch_bounds__(PT_THREADS) void pt_hist(PassArgs a, uint32_t *__restrict__ hist) {
     constexpr int ITEMS = PtItems<K>::value;
     __shared__ uint32_t s_h[PT_MAX_BINS];
     const int tid = threadIdx.x;
-    const uint32_t bins = 1u << a.bits, mask = bins - 1;
-    uint64_t c0, c1, hidx;
-    uint32_t hstride;
-    if (!chunk_range<K, FROM_WIN>(a, c0, c1, hidx, hstride)) {
-        if (!FROM_WIN) {
-            // beyond the last pass-2 chunk: clear this block's share of the
-            // unused tail of the count array
-            const uint64_t z = (uint64_t)blockIdx.x * bins;
-            for (uint32_t d = tid; d < bins; d += PT_THREADS)
-                hist[z + d] = 0;
-        }
-        return;
-    }
+    Chunk ch;
+    if (!chunk_of<K, FROM_WIN>(a, ch))
+        return;  // uniform over the block
+    const uint32_t bins = 1u << ch.bits, mask = bins - 1;
     for (int d = tid; d < PT_MAX_BINS; d += PT_THREADS)
         s_h[d] = 0;
     __syncthreads();
-    for (uint64_t t0 = c0; t0 < c1; t0 += pt_tile<K>()) {
+    for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += pt_tile<K>()) {
         K key[ITEMS];
-        const uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + pt_tile<K>(), c1), key);
+        const uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + pt_tile<K>(), ch.c1), ch.lo, key);
 #pragma unroll
         for (int i = 0; i < ITEMS; i++)
             if ((vm >> i) & 1u)
-                atomicAdd(&s_h[digit_of(key[i], a.shift, mask)], 1u);
+                atomicAdd(&s_h[digit_of(key[i], ch.shift, mask)], 1u);
     }
     __syncthreads();
     for (uint32_t d = tid; d < bins; d += PT_THREADS)
-        hist[hidx + (uint64_t)d * hstride] = s_h[d];
+        hist[ch.hidx + (uint64_t)d * ch.hstride] = s_h[d];
 }
 
 template <typename K, bool FROM_WIN>
-__global__ __launch_bounds__(PT_THREADS) void pt_scatter(PartArgs a, const uint32_t *__restrict__ offs,
+__global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint32_t *__restrict__ offs,
                                                          K *__restrict__ out) {
     constexpr int ITEMS = PtItems<K>::value;
     constexpr int TILE = PT_THREADS * ITEMS;
@@ -185,29 +209,28 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PartArgs a, const uint3
     const int tid = threadIdx.x;
     const int wave = tid / WAVE;
     const uint32_t lane = lane_id();
-    const uint32_t bins = 1u << a.bits, mask = bins - 1;
-    uint64_t c0, c1, hidx;
-    uint32_t hstride;
-    if (!chunk_range<K, FROM_WIN>(a, c0, c1, hidx, hstride))
+    Chunk ch;
+    if (!chunk_of<K, FROM_WIN>(a, ch))
         return;  // uniform over the block
+    const uint32_t bins = 1u << ch.bits, mask = bins - 1;
     // thread t owns digits t * PT_BPT .. t * PT_BPT + PT_BPT - 1
     const uint32_t d0 = (uint32_t)tid * PT_BPT;
 #pragma unroll
     for (int j = 0; j < PT_BPT; j++) {
         if (d0 + j < bins)
-            s_cur[d0 + j] = offs[hidx + (uint64_t)(d0 + j) * hstride];
+            s_cur[d0 + j] = offs[ch.hidx + (uint64_t)(d0 + j) * ch.hstride];
         s_cnt[d0 + j] = 0;
     }
     __syncthreads();
-    for (uint64_t t0 = c0; t0 < c1; t0 += TILE) {
+    for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += TILE) {
         K key[ITEMS];
-        const uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + (uint64_t)TILE, c1), key);
+        const uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + (uint64_t)TILE, ch.c1), ch.lo, key);
         uint32_t rd[ITEMS];  // (rank << 10) | digit
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             rd[i] = 0;
             if ((vm >> i) & 1u) {
-                const uint32_t d = digit_of(key[i], a.shift, mask);
+                const uint32_t d = digit_of(key[i], ch.shift, mask);
                 rd[i] = (atomicAdd(&s_cnt[d], 1u) << PT_MAX_BITS) | d;
             }
         }
@@ -247,7 +270,7 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PartArgs a, const uint3
         // consecutive positions of a run
         for (uint32_t j = tid; j < n_tile; j += PT_THREADS) {
             const K x = s_stage[j];
-            const uint32_t d = digit_of(x, a.shift, mask);
+            const uint32_t d = digit_of(x, ch.shift, mask);
             out[(uint64_t)s_cur[d] + (j - s_cnt[d])] = x;
         }
         __syncthreads();
@@ -261,115 +284,133 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PartArgs a, const uint3
     }
 }
 
-// Segment starts and the first pass-2 chunk of each segment, from the
-// scanned pass-1 counts (entry d * n_chunks of the scan is the start of
-// digit d).  One block.
+// Start of segment s (library j, top digit d) from the scanned pass-1
+// counts (n_hist1 entries, total1 keys).  Count entry h1 + d * nch1 of a
+// library is the first chunk of digit d; an empty library has no entries and
+// reads the start of what follows it.
+__device__ __forceinline__ uint32_t segment_start(const PassArgs &a, const uint32_t *__restrict__ scan1,
+                                                  uint64_t n_hist1, uint32_t total1, uint32_t s) {
+    if (s >= a.nseg)
+        return total1;
+    const uint32_t j = last_le(a.n_libs, s, [&](uint32_t i) { return (uint64_t)a.libs[i].seg0; });
+    const LibDesc &L = a.libs[j];
+    const uint64_t e = L.h1 + (uint64_t)(s - L.seg0) * L.nch1;
+    return e < n_hist1 ? scan1[e] : total1;
+}
+
+// Per segment: its start, its number of pass-2 chunks and of pass-2 count
+// entries; the first key of every library.
 template <typename K>
-__global__ __launch_bounds__(SEG_THREADS) void pt_segments(const uint32_t *__restrict__ offs1, uint64_t n_chunks1,
-                                                          uint32_t nseg, const uint32_t *__restrict__ total,
-                                                          uint32_t *__restrict__ seg, uint32_t *__restrict__ cb) {
-    const uint32_t s = threadIdx.x;
-    const uint32_t n = *total;
-    uint32_t start = n, end = n;
-    if (s < nseg)
-        start = offs1[(uint64_t)s * n_chunks1];
-    if (s + 1 < nseg)
-        end = offs1[(uint64_t)(s + 1) * n_chunks1];
-    const uint32_t ch = s < nseg ? (uint32_t)(((uint64_t)(end - start) + pt_chunk<K>() - 1) / pt_chunk<K>()) : 0u;
-    uint32_t n_ch;
-    const uint32_t first = block_exclusive_sum<SEG_THREADS>(ch, &n_ch);
-    if (s < nseg) {
+__global__ __launch_bounds__(SEG_THREADS) void pt_segments(PassArgs a, const uint32_t *__restrict__ scan1,
+                                                           uint64_t n_hist1, const uint32_t *__restrict__ total1p,
+                                                           uint32_t *__restrict__ seg, uint32_t *__restrict__ chs,
+                                                           uint32_t *__restrict__ ent, uint32_t *__restrict__ lib_keys) {
+    const uint32_t total1 = *total1p;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= a.nseg; t += stride) {
+        const uint32_t s = (uint32_t)t;
+        const uint32_t start = segment_start(a, scan1, n_hist1, total1, s);
         seg[s] = start;
-        cb[s] = first;
+        if (s < a.nseg) {
+            const uint32_t end = segment_start(a, scan1, n_hist1, total1, s + 1);
+            const uint32_t j = last_le(a.n_libs, s, [&](uint32_t i) { return (uint64_t)a.libs[i].seg0; });
+            const uint32_t n_ch = (uint32_t)(((uint64_t)(end - start) + pt_chunk<K>() - 1) / pt_chunk<K>());
+            chs[s] = n_ch;
+            ent[s] = n_ch << a.libs[j].D2;
+        }
     }
-    if (s == 0) {
-        seg[nseg] = n;
-        cb[nseg] = n_ch;
+    // first key of every library: the start of its first segment
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= a.n_libs; t += stride) {
+        const uint32_t j = (uint32_t)t;
+        lib_keys[j] = j < a.n_libs ? segment_start(a, scan1, n_hist1, total1, a.libs[j].seg0) : total1;
     }
 }
 
 template <typename K>
-hipError_t run_partition(const PartArgs &a0, void *tmp, void *out, uint32_t *scratch, size_t scratch_words,
-                         uint32_t *total, uint32_t *total2, hipStream_t stream) {
-    const int D = a0.bits;
-    const int D1 = D < PT_MAX_BITS ? D : PT_MAX_BITS;
-    const int D2 = D - D1;
-    if (D < 0 || D2 > PT_MAX_BITS || 2 * a0.k < D)
+hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scratch, size_t scratch_words,
+                         uint32_t *lib_keys, hipStream_t stream) {
+    if (p.D2max < 0 || p.D2max > PT_MAX_BITS)
         return hipErrorInvalidValue;
-    const uint64_t n_pos = a0.n_elems;  // window positions
-    uint32_t *seg = scratch;
-    uint32_t *cb = scratch + (PT_MAX_BINS + 1);
-    uint32_t *hist = scratch + 2 * (PT_MAX_BINS + 1);
-    const size_t hist_words = scratch_words - 2 * (PT_MAX_BINS + 1);
+    const uint64_t n1 = p.n_hist1;
+    const uint64_t grid2 = ceil_div(p.cap, pt_chunk<K>()) + p.nseg;  // bound on pass-2 chunks
+    const uint64_t n2 = grid2 << p.D2max;
+    const uint64_t H = std::max(n1 + scan_scratch_words(n1), n2 + scan_scratch_words(n2));
+    const uint64_t need = H + 3 * ((uint64_t)p.nseg + 1) + scan_scratch_words(p.nseg) + 4;
+    if (need > scratch_words)
+        return hipErrorInvalidValue;
+    uint32_t *hist = scratch;
+    uint32_t *seg = scratch + H;
+    uint32_t *cb = seg + (p.nseg + 1);
+    uint32_t *eb = cb + (p.nseg + 1);
+    uint32_t *sscan = eb + (p.nseg + 1);
+    uint32_t *total1 = sscan + scan_scratch_words(p.nseg);
     const dim3 block(PT_THREADS);
 
-    // pass 1: windows -> (D2 ? tmp : out), by the top D1 bits
-    PartArgs a = a0;
-    a.shift = 2 * a0.k - D1;
-    a.bits = D1;
-    a.n_chunks = ceil_div(n_pos ? n_pos : 1, pt_chunk<K>());
-    const uint64_t n_hist1 = a.n_chunks << D1;
-    if (n_hist1 + scan_scratch_words(n_hist1) > hist_words)
-        return hipErrorInvalidValue;
-    void *out1 = D2 ? tmp : out;
-    if (n_pos) {
-        pt_hist<K, true><<<dim3((unsigned)a.n_chunks), block, 0, stream>>>(a, hist);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
+    PassArgs a{};
+    a.packed = p.packed;
+    a.valid = p.valid;
+    a.k = p.k;
+    a.libs = p.libs;
+    a.n_libs = p.n_libs;
+    a.seg = seg;
+    a.cb = cb;
+    a.eb = eb;
+    a.nseg = p.nseg;
+
+    // pass 1: windows -> (second pass ? tmp : out), by (library, top D1 bits)
+    void *out1 = p.D2max ? tmp : out;
+    hipError_t e;
+    if (p.nch1) {
+        pt_hist<K, true><<<dim3(p.nch1), block, 0, stream>>>(a, hist);
+        if ((e = hipGetLastError()) != hipSuccess)
             return e;
-    } else {
-        a.n_chunks = 0;
     }
-    hipError_t e = launch_exclusive_scan(hist, hist, a.n_chunks << D1, hist + n_hist1, total, stream);
-    if (e != hipSuccess)
+    if ((e = launch_exclusive_scan(hist, hist, n1, hist + n1, total1, stream)) != hipSuccess)
         return e;
-    if (!n_pos)
-        return hipSuccess;  // no key: nothing to move
-    pt_scatter<K, true><<<dim3((unsigned)a.n_chunks), block, 0, stream>>>(a, hist, static_cast<K *>(out1));
+    if (p.nch1) {
+        pt_scatter<K, true><<<dim3(p.nch1), block, 0, stream>>>(a, hist, static_cast<K *>(out1));
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    const unsigned sgrid = (unsigned)std::min<uint64_t>(ceil_div((uint64_t)p.nseg + 1, SEG_THREADS), 4096);
+    pt_segments<K><<<dim3(sgrid), dim3(SEG_THREADS), 0, stream>>>(a, hist, n1, total1, seg, cb, eb, lib_keys);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    if (!D2)
+    if (!p.D2max)
         return hipSuccess;
 
-    // pass 2: tmp -> out, each segment by the next D2 bits
-    const uint32_t nseg = 1u << D1;
-    pt_segments<K><<<dim3(1), dim3(SEG_THREADS), 0, stream>>>(hist, a.n_chunks, nseg, total, seg, cb);
+    // pass 2: tmp -> out, every segment by its library's next D2 bits
+    if ((e = launch_exclusive_scan(cb, cb, p.nseg, sscan, cb + p.nseg, stream)) != hipSuccess ||
+        (e = launch_exclusive_scan(eb, eb, p.nseg, sscan, eb + p.nseg, stream)) != hipSuccess)
+        return e;
+    a.keys_in = tmp;
+    if ((e = zero_bytes(hist, n2 * sizeof(uint32_t), stream)) != hipSuccess)
+        return e;
+    pt_hist<K, false><<<dim3((unsigned)grid2), block, 0, stream>>>(a, hist);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    PartArgs b = a0;
-    b.keys_in = tmp;
-    b.shift = 2 * a0.k - D;
-    b.bits = D2;
-    b.seg = seg;
-    b.cb = cb;
-    b.nseg = nseg;
-    const uint64_t grid2 = ceil_div(n_pos, pt_chunk<K>()) + nseg;  // bound on the number of chunks
-    const uint64_t n_hist2 = grid2 << D2;
-    if (n_hist2 + scan_scratch_words(n_hist2) > hist_words)
-        return hipErrorInvalidValue;
-    pt_hist<K, false><<<dim3((unsigned)grid2), block, 0, stream>>>(b, hist);
-    if ((e = hipGetLastError()) != hipSuccess)
+    if ((e = launch_exclusive_scan(hist, hist, n2, hist + n2, total1 + 1, stream)) != hipSuccess)
         return e;
-    if ((e = launch_exclusive_scan(hist, hist, n_hist2, hist + n_hist2, total2, stream)) != hipSuccess)
-        return e;
-    pt_scatter<K, false><<<dim3((unsigned)grid2), block, 0, stream>>>(b, hist, static_cast<K *>(out));
+    pt_scatter<K, false><<<dim3((unsigned)grid2), block, 0, stream>>>(a, hist, static_cast<K *>(out));
     return hipGetLastError();
 }
 
 }  // namespace
 
-size_t partition_scratch_words(uint64_t n_pos, int key_words) {
-    const uint64_t chunk = key_words == 2 ? pt_chunk<Key2>() : pt_chunk<uint64_t>();
-    const uint64_t n1 = ceil_div(n_pos ? n_pos : 1, chunk) << PT_MAX_BITS;
-    const uint64_t n2 = (ceil_div(n_pos, chunk) + PT_MAX_BINS) << PT_MAX_BITS;
-    const uint64_t h = std::max(n1 + scan_scratch_words(n1), n2 + scan_scratch_words(n2));
-    return 2 * (PT_MAX_BINS + 1) + h;
+uint64_t partition_chunk(int key_words) { return key_words == 2 ? pt_chunk<Key2>() : pt_chunk<uint64_t>(); }
+
+size_t partition_scratch_words(const PartPlan &p, int key_words) {
+    const uint64_t n1 = p.n_hist1;
+    const uint64_t grid2 = ceil_div(p.cap, partition_chunk(key_words)) + p.nseg;
+    const uint64_t n2 = grid2 << p.D2max;
+    const uint64_t H = std::max(n1 + scan_scratch_words(n1), n2 + scan_scratch_words(n2));
+    return H + 3 * ((uint64_t)p.nseg + 1) + scan_scratch_words(p.nseg) + 4;
 }
 
-hipError_t partition_keys(const PartArgs &a, void *tmp, void *out, uint32_t *scratch, size_t scratch_words,
-                          uint32_t *total, uint32_t *total2, hipStream_t stream) {
-    return a.k > 31 ? run_partition<Key2>(a, tmp, out, scratch, scratch_words, total, total2, stream)
-                    : run_partition<uint64_t>(a, tmp, out, scratch, scratch_words, total, total2, stream);
+hipError_t partition_keys(const PartPlan &p, int key_words, void *tmp, void *out, uint32_t *scratch,
+                          size_t scratch_words, uint32_t *lib_keys, hipStream_t stream) {
+    return key_words == 2 ? run_partition<Key2>(p, tmp, out, scratch, scratch_words, lib_keys, stream)
+                          : run_partition<uint64_t>(p, tmp, out, scratch, scratch_words, lib_keys, stream);
 }
 
 }  // namespace tk

@@ -138,3 +138,42 @@ def test_last_error_message(lib):
     with pytest.raises(tk.TurtleError):
         tk.tk_workspace_size(100, 1, 99, 2)
     assert "k = 99" in tk.tk_last_error()
+
+
+def test_batch_workspace_of_one_library_equals_single(lib):
+    for n_bases, n_reads, k, c in [(100_000, 1000, 31, 2), (10_000_000, 100_000, 63, 2), (0, 0, 5, 1)]:
+        assert tk.tk_batch_workspace_size([0, n_bases], [0, n_reads], k, [c]) == \
+            tk.tk_workspace_size(n_bases, n_reads, k, c)
+
+
+@pytest.mark.parametrize("n_libs", [2, 7, 100])
+def test_batch_workspace_bounded_by_its_libraries(lib, n_libs):
+    """A batch needs at least its largest library's workspace and at most
+    the sum of its libraries' workspaces."""
+    rng = np.random.default_rng(n_libs)
+    nb = rng.integers(0, 400_000, n_libs)
+    nr = nb // 100
+    lb = np.concatenate([[0], np.cumsum(nb)])
+    lr = np.concatenate([[0], np.cumsum(nr)])
+    singles = [tk.tk_workspace_size(int(b), int(r), 31, 2) for b, r in zip(nb, nr)]
+    batch = tk.tk_batch_workspace_size(lb, lr, 31, 2)
+    assert max(singles) <= batch <= sum(singles)
+
+
+@pytest.mark.parametrize("lb,lr,c,opts,what", [
+    ([0, 10, 5], [0, 1, 2], [2, 2], None, "decrease"),
+    ([0, 10, 20], [0, 2, 1], [2, 2], None, "decrease"),
+    ([1, 10], [0, 1], [2], None, "start at 0"),
+    ([0, 10, 20], [0, 1, 2], [2, 0], None, "threshold"),
+    ([0, 10, 20], [0, 1, 2], [2, 2], dict(flags=2), "one library"),
+    ([0, 10, 20], [0, 1, 2], [2, 2], dict(part_bits=20), "buckets"),
+])
+def test_batch_bad_arguments_rejected(lib, lb, lr, c, opts, what):
+    if what == "buckets":
+        # 2^20 buckets per library: too many over 2048 libraries
+        lb = list(range(0, 20 * 2049, 20))
+        lr = list(range(0, 2049))
+        c = [2] * 2048
+    with pytest.raises(tk.TurtleError) as e:
+        tk.tk_batch_workspace_size(lb, lr, 31, c, opts)
+    assert e.value.status == tk.TK_EINVAL and what in str(e.value)

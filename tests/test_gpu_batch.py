@@ -1,0 +1,137 @@
+"""GPU parity of batched counting: several libraries in one call, each
+compared bit-exactly with the oracle run on that library alone (keys,
+counts, windows, and the screen statistics of the library's own per-bucket
+filters), and with the single-library entry point."""
+import sys
+
+import numpy as np
+import pytest
+
+import readsim
+
+pytestmark = pytest.mark.gpu
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1305_1861_amd as tk
+    tk.load_library()
+    return tk
+
+
+def concat(libs):
+    """One bases/offsets pair for a list of (bases, offsets) libraries, with
+    the library boundaries in bases and in reads."""
+    bases = np.concatenate([b for b, _ in libs]) if libs else np.zeros(0, np.uint8)
+    offs = [np.zeros(1, np.uint64)]
+    lib_bases, lib_reads = [0], [0]
+    for b, o in libs:
+        offs.append(o[1:].astype(np.uint64) + np.uint64(lib_bases[-1]))
+        lib_bases.append(lib_bases[-1] + int(b.size))
+        lib_reads.append(lib_reads[-1] + int(o.size - 1))
+    return bases, np.concatenate(offs), lib_bases, lib_reads
+
+
+def run_batch(tk, libs, k, c, opts=None):
+    import torch
+    bases, offsets, lb, lr = concat(libs)
+    db = torch.from_numpy(bases).cuda() if bases.size else torch.zeros(1, dtype=torch.uint8).cuda()[:0]
+    do = torch.from_numpy(offsets.view(np.int64)).cuda()
+    res = tk.tk_count_batch_device(db, do, lb, lr, k, c, opts)
+    torch.cuda.synchronize()
+    out = []
+    for r in res:
+        keys = r.keys.cpu().numpy().view(np.uint64).reshape(r.n, r.key_words)
+        counts = r.counts.cpu().numpy().view(np.uint32)
+        out.append((keys, counts, r))
+    return out
+
+
+def check_library(oracle_lib, bases, offsets, k, c, keys, counts, r, opts=None):
+    ora = oracle_lib.kmer_count(bases, offsets, k, c)
+    if k <= 31:
+        assert keys.shape[1] == 1 and keys.shape[0] == ora.lo.size, (keys.shape, ora.lo.size)
+        assert (keys[:, 0] == ora.lo).all()
+    else:
+        assert keys.shape[0] == ora.lo.size
+        assert (keys[:, 0] == ora.hi).all() and (keys[:, 1] == ora.lo).all()
+    assert (counts.astype(np.uint64) == ora.count).all()
+    assert r.n_windows == ora.n_windows
+    D = oracle_lib.partition_bits(bases.size, offsets.size - 1, k, (opts or {}).get("part_bits", -1))
+    assert r.part_bits == D
+    if c == 1:
+        assert r.n_collected == ora.n_windows and r.n_distinct == ora.n_distinct
+    else:
+        m = oracle_lib.bloom_model_buckets(bases, offsets, k, D, 4, 1024, 2, 1305)
+        assert (r.n_collected, r.n_distinct, r.n_singletons) == (m.n_cand_occ, m.n_cand, m.n_cand_single)
+
+
+def mixed_libraries(seed, k):
+    rng = np.random.default_rng(seed)
+    libs = []
+    libs.append(readsim.random_reads(seed, 300, 0, 2 * k + 80, n_rate=0.01, lower_rate=0.02, junk_rate=0.002))
+    libs.append((np.zeros(0, np.uint8), np.zeros(1, np.uint64)))  # empty library
+    lib = readsim.small_library(scale=0.05, seed=seed + 1)
+    libs.append((lib.bases, lib.offsets))
+    libs.append(readsim.from_strings(["A" * (k + 40), "ACGT" * 30, ""]))
+    libs.append(readsim.random_reads(seed + 2, 40, k - 1, k + 3))
+    dup = readsim.random_reads(seed + 3, 200, k, 3 * k)
+    libs.append(readsim.from_strings(readsim.to_strings(*dup) * 3))
+    return libs
+
+
+@pytest.mark.parametrize("k", [21, 31, 63])
+def test_batch_matches_each_library_alone(tk, oracle_lib, k):
+    libs = mixed_libraries(500 + k, k)
+    cs = [2, 3, 2, 1, 2, 2][: len(libs)]
+    case(f"batch of {len(libs)} libraries k={k} c={cs}")
+    out = run_batch(tk, libs, k, cs)
+    assert len(out) == len(libs)
+    for (b, o), c, (keys, counts, r) in zip(libs, cs, out):
+        check_library(oracle_lib, b, o, k, c, keys, counts, r)
+
+
+def test_batch_of_one_equals_single_call(tk, oracle_lib):
+    import torch
+    lib = readsim.small_library(scale=0.2)
+    case("batch of one vs single call")
+    (keys, counts, r), = run_batch(tk, [(lib.bases, lib.offsets)], lib.k, lib.c)
+    db = torch.from_numpy(lib.bases).cuda()
+    do = torch.from_numpy(lib.offsets.view(np.int64)).cuda()
+    s = tk.tk_count_device(db, do, lib.k, lib.c)
+    torch.cuda.synchronize()
+    assert np.array_equal(keys, s.keys.cpu().numpy().view(np.uint64).reshape(s.n, s.key_words))
+    assert np.array_equal(counts, s.counts.cpu().numpy().view(np.uint32))
+    assert (r.n_windows, r.n_collected, r.n_distinct, r.n_singletons) == \
+        (s.n_windows, s.n_collected, s.n_distinct, s.n_singletons)
+
+
+def test_many_small_libraries(tk, oracle_lib):
+    libs = [readsim.random_reads(9000 + j, 20 + 7 * j, 0, 140, n_rate=0.005) for j in range(64)]
+    case("64 small libraries k=31 c=2")
+    out = run_batch(tk, libs, 31, 2)
+    for (b, o), (keys, counts, r) in zip(libs, out):
+        check_library(oracle_lib, b, o, 31, 2, keys, counts, r)
+
+
+@pytest.mark.parametrize("part_bits", [2, 6])
+def test_batch_oversized_buckets(tk, oracle_lib, part_bits):
+    """Oversized buckets in several libraries at once go through the
+    fallback library by library."""
+    libs = [(l.bases, l.offsets) for l in (readsim.small_library(scale=0.05, seed=s) for s in (11, 12, 13))]
+    libs.insert(1, readsim.random_reads(77, 100, 0, 120))
+    case(f"batch with oversized buckets part_bits={part_bits}")
+    out = run_batch(tk, libs, 31, 2, dict(part_bits=part_bits))
+    n_fb = 0
+    for (b, o), (keys, counts, r) in zip(libs, out):
+        check_library(oracle_lib, b, o, 31, 2, keys, counts, r, dict(part_bits=part_bits))
+        n_fb += r.n_fallback
+    assert n_fb >= 3
