@@ -35,6 +35,7 @@ STAGE_SOURCES = {
 }
 
 WORKLOAD_INFO = {
+    "batched": dict(libraries="log-uniform genomes 1e5..2e7 bp (times --batch-scale), coverage U[5, 60]"),
     "small": dict(genome_bp=1_000_000, coverage=10, read_len=100, sub_rate=0.01, n_rate=0.0, repeats=None),
     "large": dict(genome_bp=50_000_000, coverage=30, read_len=100, sub_rate=0.01, n_rate=0.0,
                   repeats="20% as 5 kbp copies, 2-10 per family, 2% divergence"),
@@ -128,6 +129,95 @@ def cpu_baseline(lib, target_s: float = 12.0) -> dict:
                       f"single-threaded on 1 of {os.cpu_count()} host cores ({cpu})"}
 
 
+def bench_batched(args, tk, readsim, torch, np, dev) -> int:
+    """Many libraries of uneven size: one batch call per wave against one
+    single-library call per library, on the same resident data."""
+    t0 = time.perf_counter()
+    libs = readsim.batched_libraries(n_libs=args.batch_libs, scale=args.batch_scale)
+    sizes = np.array([l.n_bases for l in libs], np.uint64)
+    print(f"[bench] generated {len(libs)} libraries, {int(sizes.sum())} bases in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    # waves: consecutive libraries up to wave_bases bases each
+    waves, cur, acc = [], [], 0
+    for j, l in enumerate(libs):
+        if cur and acc + l.n_bases > args.wave_bases:
+            waves.append(cur)
+            cur, acc = [], 0
+        cur.append(j)
+        acc += l.n_bases
+    if cur:
+        waves.append(cur)
+    k, c = libs[0].k, libs[0].c
+    opts = tk.tk_default_options()
+    opts.flags = tk.TK_FLAG_TIMING
+    wave_data = []
+    for w in waves:
+        bases = np.concatenate([libs[j].bases for j in w])
+        lb, lr, offs = [0], [0], [np.zeros(1, np.uint64)]
+        for j in w:
+            offs.append(libs[j].offsets[1:] + np.uint64(lb[-1]))
+            lb.append(lb[-1] + libs[j].n_bases)
+            lr.append(lr[-1] + libs[j].n_reads)
+        offsets = np.concatenate(offs)
+        db = torch.from_numpy(bases).to(dev)
+        do = torch.from_numpy(offsets.view(np.int64)).to(dev)
+        # each library on its own (for the single-library calls): views of the
+        # same bases and offsets re-based to the library's first base
+        single = [(db[lb[q]:lb[q + 1]], do[lr[q]:lr[q + 1] + 1] - lb[q]) for q in range(len(w))]
+        wave_data.append(dict(db=db, do=do, lb=lb, lr=lr, libs=w, single=single))
+    ws_bytes = max(tk.tk_batch_workspace_size(wd["lb"], wd["lr"], k, c, opts) for wd in wave_data)
+    ws_bytes = max(ws_bytes, max(tk.tk_workspace_size(l.n_bases, l.n_reads, k, c, opts) for l in libs))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def batched():
+        n_win = n_out = 0
+        for wd in wave_data:
+            for r in tk.tk_count_batch_device(wd["db"], wd["do"], wd["lb"], wd["lr"], k, c, opts, workspace=ws,
+                                              stream=stream):
+                n_win += r.n_windows
+                n_out += r.n
+        return n_win, n_out
+
+    def sequential():
+        n_win = n_out = 0
+        for wd in wave_data:
+            for b, o in wd["single"]:
+                r = tk.tk_count_device(b, o, k, c, opts, workspace=ws, stream=stream)
+                n_win += r.n_windows
+                n_out += r.n
+        return n_win, n_out
+
+    results = {}
+    for name, fn in (("batched", batched), ("sequential", sequential)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            n_win, n_out = fn()
+        torch.cuda.synchronize()
+        results[name] = ((time.perf_counter() - t) / args.steps, n_win, n_out)
+        print(f"[bench] {name}: {1e3 * results[name][0]:.2f} ms per pass", file=sys.stderr, flush=True)
+    tb, n_win, n_out = results["batched"]
+    ts = results["sequential"][0]
+    assert results["sequential"][1:] == (n_win, n_out)
+    out = {
+        "metric": METRIC, "value": n_win / tb, "unit": "k-mer windows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * tb, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"batched-{len(libs)}-libraries-scale-{args.batch_scale:g}",
+                   "genome_bp": "log-uniform 1e5..2e7 times scale", "coverage": "U[5, 60]", "read_len": 100,
+                   "sub_rate": 0.01, "k": k, "c": c, "n_bases": int(sizes.sum()), "waves": len(waves)},
+        "result": {"n_windows": n_win, "n_frequent": n_out},
+        "sequential": {"ms_per_step": 1e3 * ts, "value": n_win / ts, "calls": len(libs)},
+        "speedup_vs_sequential": ts / tb,
+        "host": platform.node(),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +231,11 @@ def main() -> int:
                     help="bucket bits D of the per-bucket plan (-1: the library's size rule)")
     ap.add_argument("--traffic", default=TRAFFIC_FILE,
                     help="JSON record of measured HBM bytes per launch of the dominant kernel")
+    ap.add_argument("--batch-libs", type=int, default=256, help="batched workload: number of libraries")
+    ap.add_argument("--batch-scale", type=float, default=1.0 / 16,
+                    help="batched workload: factor on every library's genome size")
+    ap.add_argument("--wave-bases", type=float, default=3.0e9,
+                    help="batched workload: bases per batch call (waves sized to HBM)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain "
                          "device copy kernel (reference for HBM byte counters)")
@@ -161,6 +256,8 @@ def main() -> int:
     tk.load_library()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "batched":
+        return bench_batched(args, tk, readsim, torch, np, dev)
 
     t0 = time.perf_counter()
     lib = readsim.WORKLOADS[args.workload]()
