@@ -35,6 +35,7 @@ STAGE_SOURCES = {
 }
 
 WORKLOAD_INFO = {
+    "served": dict(jobs="Poisson arrivals, mean 50/s; batched-style libraries, k in {21, 31, 55}"),
     "batched": dict(libraries="log-uniform genomes 1e5..2e7 bp (times --batch-scale), coverage U[5, 60]"),
     "small": dict(genome_bp=1_000_000, coverage=10, read_len=100, sub_rate=0.01, n_rate=0.0, repeats=None),
     "large": dict(genome_bp=50_000_000, coverage=30, read_len=100, sub_rate=0.01, n_rate=0.0,
@@ -218,6 +219,60 @@ def bench_batched(args, tk, readsim, torch, np, dev) -> int:
     return 0
 
 
+def bench_served(args, tk, readsim, torch, np, dev) -> int:
+    """Jobs arriving as a Poisson process, served by continuous batching;
+    latency per job from arrival to result on the host."""
+    from paper_1305_1861_amd.serve import Job, Server
+    pool_n = args.pool
+    t0 = time.perf_counter()
+    pool = readsim.batched_libraries(n_libs=pool_n, scale=args.batch_scale, base_seed=5_000_000)
+    print(f"[bench] generated a pool of {pool_n} libraries in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    rng = np.random.Generator(np.random.PCG64(5))
+    gaps = rng.exponential(1.0 / args.rate, args.jobs)
+    ks = rng.choice([21, 31, 55], args.jobs)
+    arrivals = np.cumsum(gaps)
+    biggest = max(l.n_bases for l in pool)
+    budget = max(1 << 28, 1 << (biggest - 1).bit_length())
+    srv = Server(max_batch_bases=budget, max_batch_reads=budget // 64, max_batch_libs=64, workers=2,
+                 device="cuda:0")
+    try:
+        # warm-up: one job of each k
+        for k in (21, 31, 55):
+            srv.submit(Job(pool[0].bases, pool[0].offsets, int(k), 2)).result()
+        futs = []
+        start = time.perf_counter()
+        for j in range(args.jobs):
+            wait = start + arrivals[j] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            lib = pool[j % pool_n]
+            futs.append(srv.submit(Job(lib.bases, lib.offsets, int(ks[j]), 2, t_submit=time.perf_counter())))
+        res = [f.result() for f in futs]
+        end = max(r.t_done for r in res)
+    finally:
+        srv.close()
+    lat = np.array([r.latency_s for r in res]) * 1e3
+    n_win = sum(r.n_windows for r in res)
+    span = end - start
+    batches = len({(r.t_start, r.t_done) for r in res})
+    out = {
+        "metric": METRIC, "value": n_win / span, "unit": "k-mer windows/s", "n_gpus": 1, "steps": args.jobs,
+        "warmup": 3, "ms_per_step": 1e3 * span / args.jobs, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64/u128", "data": "synthetic",
+        "config": {"workload": f"served-{args.jobs}-jobs-{args.rate:g}-per-s-scale-{args.batch_scale:g}",
+                   "jobs": args.jobs, "rate_per_s": args.rate, "k": "U{21, 31, 55}", "c": 2,
+                   "library_pool": pool_n, "workers": 2, "batch_budget_bases": budget},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max())},
+        "result": {"n_windows": n_win, "n_frequent": sum(int(r.counts.size) for r in res), "batches": batches,
+                   "offered_windows_per_s": n_win / arrivals[-1]},
+        "host": platform.node(),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +291,9 @@ def main() -> int:
                     help="batched workload: factor on every library's genome size")
     ap.add_argument("--wave-bases", type=float, default=3.0e9,
                     help="batched workload: bases per batch call (waves sized to HBM)")
+    ap.add_argument("--jobs", type=int, default=1000, help="served workload: number of jobs")
+    ap.add_argument("--rate", type=float, default=50.0, help="served workload: mean arrivals per second")
+    ap.add_argument("--pool", type=int, default=48, help="served workload: distinct libraries the jobs cycle over")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain "
                          "device copy kernel (reference for HBM byte counters)")
@@ -258,6 +316,8 @@ def main() -> int:
     torch.cuda.set_device(dev)
     if args.workload == "batched":
         return bench_batched(args, tk, readsim, torch, np, dev)
+    if args.workload == "served":
+        return bench_served(args, tk, readsim, torch, np, dev)
 
     t0 = time.perf_counter()
     lib = readsim.WORKLOADS[args.workload]()
