@@ -182,20 +182,25 @@ class Server:
         for j in jobs:
             lb.append(lb[-1] + int(j.bases.size))
             lr.append(lr[-1] + int(j.offsets.size - 1))
-        bases = np.concatenate([j.bases for j in jobs]) if lb[-1] else np.zeros(0, np.uint8)
-        offs = np.concatenate([np.zeros(1, np.uint64)] +
-                              [j.offsets[1:].astype(np.uint64) + np.uint64(lb[q]) for q, j in enumerate(jobs)])
         stream = w["stream"]
         with torch.cuda.stream(stream):
             db = w["bases"][:lb[-1]]
             do = w["offsets"][:lr[-1] + 1]
-            if lb[-1]:
-                db.copy_(torch.from_numpy(bases))
-            do.copy_(torch.from_numpy(offs.view(np.int64)))
+            # every job straight into its slice of the resident buffers; its
+            # offsets rebased to its first base on the device
+            do[:1].zero_()
+            for q, j in enumerate(jobs):
+                if j.bases.size:
+                    db[lb[q]:lb[q + 1]].copy_(torch.from_numpy(j.bases))
+                if lr[q + 1] > lr[q]:
+                    seg = do[lr[q] + 1:lr[q + 1] + 1]
+                    seg.copy_(torch.from_numpy(j.offsets[1:].astype(np.uint64, copy=False).view(np.int64)))
+                    if lb[q]:
+                        seg.add_(lb[q])
             res = tk_count_batch_device(db, do, lb, lr, jobs[0].k, [j.c for j in jobs], self.opts,
                                         workspace=w["ws"], stream=stream)
-            host = [(r.keys.cpu().numpy().view(np.uint64).reshape(r.n, r.key_words).copy(),
-                     r.counts.cpu().numpy().view(np.uint32).copy(), r) for r in res]
+            host = [(r.keys.cpu().numpy().view(np.uint64).reshape(r.n, r.key_words),
+                     r.counts.cpu().numpy().view(np.uint32), r) for r in res]
         t_done = time.perf_counter()
         for (keys, counts, r), (job, fut) in zip(host, batch):
             fut.set_result(JobResult(keys, counts, r.n_windows, r.n_collected, r.n_distinct, r.n_singletons,
