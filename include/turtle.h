@@ -235,6 +235,29 @@ TK_API tk_status tk_count_batch_device(const uint8_t *d_bases, const uint64_t *d
                                        size_t ws_bytes, void *stream, tk_result *out);
 
 /*
+ * Phased sort-and-compact (§2.1, "Counting frequencies with sorting and
+ * compaction", Fig. 1): a library in HOST memory (as tk_count) is streamed to
+ * the device in chunks of consecutive reads of at most chunk_bases bases (a
+ * longer read forms a chunk alone).  Pass 1 screens every window of every
+ * chunk into one filter of the global-filter size rule; pass 2 collects each
+ * chunk's candidates, sorts and compacts them into (key, count) records and
+ * merges those into a resident sorted-and-compacted array (SAC) of at most
+ * sac_capacity records (0: as many as bases), adding the counts of keys
+ * present in both.  The answer keeps the SAC records with count >= c.
+ * Device memory is bounded by the chunk size and the SAC capacity, not by
+ * the library size; the result does not depend on chunk_bases and equals
+ * tk_count's with TK_FLAG_GLOBAL_FILTER (same filter, same statistics).
+ * *out is allocated as in tk_count (free with tk_result_free);
+ * *device_bytes (may be NULL) receives the device memory used.
+ * Errors: as tk_count; TK_ENOMEM also when the SAC outgrows sac_capacity.
+ */
+TK_API tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets,
+                                 uint64_t n_reads, int k, uint32_t c,
+                                 uint64_t chunk_bases, uint64_t sac_capacity,
+                                 const tk_options *opts, tk_result **out,
+                                 size_t *device_bytes);
+
+/*
  * The pattern table the screen uses for these options: 2^bloom_table_bits
  * 64-bit masks written to host array `masks` of `capacity` entries.
  */

@@ -84,6 +84,8 @@ def load_library():
                                                    P(ctypes.c_size_t)]),
         "tk_count_batch_device": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, ctypes.c_int, _vp,
                                                  P(tk_options), _vp, ctypes.c_size_t, _vp, _vp]),
+        "tk_count_phased": (ctypes.c_int, [_vp, _vp, _u64, ctypes.c_int, _u32, _u64, _u64, P(tk_options),
+                                           P(P(tk_result)), P(ctypes.c_size_t)]),
         "tk_pattern_table": (ctypes.c_int, [P(tk_options), _vp, _u64]),
         "tk_bloom_blocks": (ctypes.c_int, [_u64, _u64, ctypes.c_int, P(tk_options), P(_u64)]),
         "tk_part_bits": (ctypes.c_int, [_u64, _u64, ctypes.c_int, P(tk_options), P(ctypes.c_int)]),
@@ -108,7 +110,7 @@ def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["tk_default_options", "tk_strerror", "tk_last_error", "tk_count", "tk_result_free",
             "tk_workspace_size", "tk_count_device", "tk_batch_workspace_size", "tk_count_batch_device",
-            "tk_pattern_table", "tk_bloom_blocks", "tk_part_bits",
+            "tk_count_phased", "tk_pattern_table", "tk_bloom_blocks", "tk_part_bits",
             "tk_pack_device", "tk_sort_scratch_size", "tk_sort_keys_device",
             "tk_compact_scratch_size", "tk_compact_device"]
 
@@ -230,6 +232,33 @@ def tk_count(bases: np.ndarray, offsets: np.ndarray, k: int, c: int, opts=None) 
         keys = np.ctypeslib.as_array(r.keys, shape=(max(n, 1) * kw,))[:n * kw].copy().reshape(n, kw)
         counts = np.ctypeslib.as_array(r.counts, shape=(max(n, 1),))[:n].copy()
         return Counts(keys, counts, **_stats(r))
+    finally:
+        lib.tk_result_free(res)
+
+
+def tk_count_phased(bases: np.ndarray, offsets: np.ndarray, k: int, c: int, chunk_bases: int,
+                    sac_capacity: int = 0, opts=None) -> Counts:
+    """Phased sort-and-compact over a library in host memory, streamed in
+    chunks of at most ``chunk_bases`` bases; ``sac_capacity`` bounds the
+    resident (key, count) array (0: no bound).  The result's
+    ``device_bytes`` is the device memory the call used."""
+    lib = load_library()
+    b = np.ascontiguousarray(bases, dtype=np.uint8)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    o = _opts(opts)
+    res = ctypes.POINTER(tk_result)()
+    used = ctypes.c_size_t(0)
+    _check(lib.tk_count_phased(b.ctypes.data if b.size else None, off.ctypes.data, off.size - 1, k, c,
+                               chunk_bases, sac_capacity, _optp(o), ctypes.byref(res), ctypes.byref(used)),
+           "tk_count_phased")
+    try:
+        r = res.contents
+        n, kw = int(r.n), int(r.key_words)
+        keys = np.ctypeslib.as_array(r.keys, shape=(max(n, 1) * kw,))[:n * kw].copy().reshape(n, kw)
+        counts = np.ctypeslib.as_array(r.counts, shape=(max(n, 1),))[:n].copy()
+        out = Counts(keys, counts, **_stats(r))
+        out.device_bytes = int(used.value)
+        return out
     finally:
         lib.tk_result_free(res)
 

@@ -950,6 +950,230 @@ tk_status tk_count(const uint8_t *bases, const uint64_t *offsets, uint64_t n_rea
     return TK_OK;
 }
 
+tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_t n_reads, int k, uint32_t c,
+                          uint64_t chunk_bases, uint64_t sac_capacity, const tk_options *opts, tk_result **out,
+                          size_t *device_bytes) {
+    if (!out)
+        return fail(TK_EINVAL, "out is NULL");
+    if (!offsets)
+        return fail(TK_EINVAL, "offsets is NULL");
+    if (offsets[0] != 0)
+        return fail(TK_EINVAL, "offsets[0] must be 0");
+    for (uint64_t r = 0; r < n_reads; r++)
+        if (offsets[r + 1] < offsets[r])
+            return fail(TK_EINVAL, "offsets decrease at read %llu", (unsigned long long)r);
+    if (k < 1 || k > 63)
+        return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
+    if (c == 0)
+        return fail(TK_EINVAL, "threshold c must be >= 1");
+    if (chunk_bases == 0)
+        return fail(TK_EINVAL, "chunk_bases must be >= 1");
+    const uint64_t n_bases = offsets[n_reads];
+    if (n_bases && !bases)
+        return fail(TK_EINVAL, "bases is NULL");
+    if (n_bases >= (1ull << 32))
+        return fail(TK_EOVERFLOW, "n_bases = %llu must be below 2^32", (unsigned long long)n_bases);
+    Opts o;
+    tk_status st = resolve(opts, &o);
+    if (st != TK_OK)
+        return st;
+    const int kw = k <= 31 ? 1 : 2;
+    const size_t kb = 8 * (size_t)kw;
+    const bool screen = c >= 2;
+    // chunks: consecutive reads of at most chunk_bases bases (a longer read
+    // alone)
+    std::vector<uint64_t> cuts{0};
+    uint64_t cb_max = 0, cr_max = 0;
+    for (uint64_t r0 = 0; r0 < n_reads;) {
+        uint64_t r1 = r0 + 1;
+        while (r1 < n_reads && offsets[r1 + 1] - offsets[r0] <= chunk_bases)
+            r1++;
+        cb_max = std::max(cb_max, offsets[r1] - offsets[r0]);
+        cr_max = std::max(cr_max, r1 - r0);
+        cuts.push_back(r1);
+        r0 = r1;
+    }
+    const uint64_t n_chunks = cuts.size() - 1;
+    const uint64_t CB = std::max<uint64_t>(cb_max, 1), CW = ceil_div(CB, 32);
+    const uint64_t sac_cap = sac_capacity ? sac_capacity : std::max<uint64_t>(n_bases, 1);
+    const uint64_t n_blocks = screen ? bloom_blocks_for(n_bases, n_reads, k, o) : 0;
+    const uint64_t merged = sac_cap + CB;  // records of one merge
+    // device memory
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = off;
+        off = align_up(off + bytes, 256);
+        return r;
+    };
+    const size_t o_ctr = take(2 * sizeof(DevCounters)), o_misc = take(64), o_table = take(sizeof(uint64_t) << o.table_bits);
+    const size_t o_filter = take(n_blocks * 64), o_bases = take(CB), o_offs = take((cr_max + 1) * sizeof(uint64_t));
+    const size_t o_packed = take(CW * 8), o_valid = take(CW * 4), o_starts = take(CW * 4);
+    const size_t o_ka = take(CB * kb), o_kb = take(CB * kb), o_rk = take(CB * kb), o_rc = take(CB * 4);
+    const size_t sort_bytes = radix_scratch_bytes(CB, kw), cmp_bytes = compact_scratch_bytes(CB);
+    const size_t o_sort = take(sort_bytes), o_cmp = take(cmp_bytes);
+    const size_t o_sk[2] = {take(merged * kb), take(merged * kb)}, o_sc[2] = {take(merged * 4), take(merged * 4)};
+    const size_t o_tk = take(merged * kb), o_tc = take(merged * 4), o_flag = take(2 * merged * 4);
+    const size_t o_scan = take(scan_scratch_words(2 * merged) * 4);
+    const size_t total = off;
+    if (device_bytes)
+        *device_bytes = total;
+
+    char *ws = nullptr;
+    hipStream_t s = nullptr;
+    tk_result *res = nullptr;
+    auto cleanup = [&]() {
+        if (ws) (void)hipFree(ws);
+        if (s) (void)hipStreamDestroy(s);
+    };
+    auto dev_fail = [&](const char *what, hipError_t e) {
+        cleanup();
+        if (res) {
+            free(res->keys);
+            free(res->counts);
+            free(res);
+        }
+        if (e == hipErrorOutOfMemory)
+            return fail(TK_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+        return fail(TK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    };
+#define TK_PH(call, what)                   \
+    do {                                    \
+        hipError_t e_ = (call);             \
+        if (e_ != hipSuccess)               \
+            return dev_fail(what, e_);      \
+    } while (0)
+    TK_PH(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+    TK_PH(hipMalloc(&ws, total), "hipMalloc(workspace)");
+    DevCounters *ctr = reinterpret_cast<DevCounters *>(ws + o_ctr);  // [0] windows, collected; [1] chunk compaction
+    uint32_t *misc = reinterpret_cast<uint32_t *>(ws + o_misc);        // [0] SAC size, [1] selected
+    unsigned long long *stats = reinterpret_cast<unsigned long long *>(ws + o_misc + 16);
+    uint64_t *table = reinterpret_cast<uint64_t *>(ws + o_table);
+    uint64_t *filter = reinterpret_cast<uint64_t *>(ws + o_filter);
+    uint8_t *d_bases = reinterpret_cast<uint8_t *>(ws + o_bases);
+    uint64_t *d_offs = reinterpret_cast<uint64_t *>(ws + o_offs);
+    uint64_t *packed = reinterpret_cast<uint64_t *>(ws + o_packed);
+    uint32_t *valid = reinterpret_cast<uint32_t *>(ws + o_valid), *starts = reinterpret_cast<uint32_t *>(ws + o_starts);
+    uint64_t *keys_a = reinterpret_cast<uint64_t *>(ws + o_ka), *keys_b = reinterpret_cast<uint64_t *>(ws + o_kb);
+    uint64_t *run_k = reinterpret_cast<uint64_t *>(ws + o_rk);
+    uint32_t *run_c = reinterpret_cast<uint32_t *>(ws + o_rc);
+    uint64_t *sac_k[2] = {reinterpret_cast<uint64_t *>(ws + o_sk[0]), reinterpret_cast<uint64_t *>(ws + o_sk[1])};
+    uint32_t *sac_c[2] = {reinterpret_cast<uint32_t *>(ws + o_sc[0]), reinterpret_cast<uint32_t *>(ws + o_sc[1])};
+    uint64_t *tmp_k = reinterpret_cast<uint64_t *>(ws + o_tk);
+    uint32_t *tmp_c = reinterpret_cast<uint32_t *>(ws + o_tc), *flag = reinterpret_cast<uint32_t *>(ws + o_flag);
+    uint32_t *scan_tmp = reinterpret_cast<uint32_t *>(ws + o_scan);
+    TK_PH(zero_bytes(ws, o_table, s), "zero");  // counters and misc
+    if (screen) {
+        const auto &tab = pattern_table(o.seed, o.table_bits, o.bits);
+        TK_PH(hipMemcpyAsync(table, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s), "table");
+        TK_PH(zero_bytes(filter, n_blocks * 64, s), "zero filter");
+    }
+    BloomArgs ba{};
+    ba.packed = packed;
+    ba.valid = valid;
+    ba.k = k;
+    ba.table = table;
+    ba.table_bits = o.table_bits;
+    ba.n_blocks = n_blocks;
+    ba.filter = filter;
+    std::vector<uint64_t> roff(cr_max + 1);
+    // one chunk to the device and packed; count windows on the first pass
+    auto load_chunk = [&](uint64_t q, bool count) -> hipError_t {
+        const uint64_t r0 = cuts[q], r1 = cuts[q + 1], b0 = offsets[r0], nb = offsets[r1] - b0;
+        for (uint64_t r = r0; r <= r1; r++)
+            roff[r - r0] = offsets[r] - b0;
+        hipError_t e;
+        if (nb && (e = hipMemcpyAsync(d_bases, bases + b0, nb, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync(d_offs, roff.data(), (r1 - r0 + 1) * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return e;
+        if ((e = zero_bytes(starts, CW * 4, s)) != hipSuccess)
+            return e;
+        ba.n_words = ceil_div(nb, 32);
+        e = launch_pack(d_bases, d_offs, nb, r1 - r0, k, packed, valid, starts, count ? &ctr[0].n_windows : nullptr,
+                        s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);  // roff is reused by the next chunk
+        return e;
+    };
+    // pass 1: every window of every chunk into the filter
+    if (screen) {
+        for (uint64_t q = 0; q < n_chunks; q++) {
+            TK_PH(load_chunk(q, true), "pass 1");
+            TK_PH(launch_screen(ba, persistent_grid(ba.n_words * 32), s), "screen");
+        }
+    }
+    // pass 2: per chunk, collect, sort, compact, merge into the SAC
+    uint64_t n_sac = 0, n_coll = 0;
+    int cur = 0;
+    for (uint64_t q = 0; q < n_chunks; q++) {
+        TK_PH(load_chunk(q, !screen), "pass 2");
+        TK_PH(zero_bytes(&ctr[1], sizeof(DevCounters), s), "zero");
+        TK_PH(launch_collect(ba, screen, keys_a, CB, &ctr[1].n_collected, persistent_grid(ba.n_words * 32), s),
+              "collect");
+        unsigned long long n_surv = 0;
+        TK_PH(hipMemcpyAsync(&n_surv, &ctr[1].n_collected, 8, hipMemcpyDeviceToHost, s), "read");
+        TK_PH(hipStreamSynchronize(s), "sync");
+        n_coll += n_surv;
+        uint64_t *srt = nullptr;
+        int passes = 0;
+        TK_PH(radix_sort(keys_a, keys_b, n_surv, kw, 2 * k, ws + o_sort, sort_bytes, s, &srt, &passes), "sort");
+        TK_PH(compact(srt, n_surv, kw, 1, run_k, run_c, ws + o_cmp, cmp_bytes, &ctr[1], s), "compact");
+        unsigned long long n_runs = 0;
+        TK_PH(hipMemcpyAsync(&n_runs, &ctr[1].n_out, 8, hipMemcpyDeviceToHost, s), "read");
+        TK_PH(hipStreamSynchronize(s), "sync");
+        TK_PH(merge_compact(sac_k[cur], sac_c[cur], n_sac, run_k, run_c, n_runs, kw, tmp_k, tmp_c, flag, scan_tmp,
+                            sac_k[1 - cur], sac_c[1 - cur], &misc[0], s),
+              "merge");
+        uint32_t ns = 0;
+        TK_PH(hipMemcpyAsync(&ns, &misc[0], 4, hipMemcpyDeviceToHost, s), "read");
+        TK_PH(hipStreamSynchronize(s), "sync");
+        n_sac = ns;
+        cur = 1 - cur;
+        if (n_sac > sac_cap) {
+            cleanup();
+            return fail(TK_ENOMEM, "%llu counted k-mers exceed the sorted-and-compacted array of %llu",
+                        (unsigned long long)n_sac, (unsigned long long)sac_cap);
+        }
+    }
+    // the answer: records with count >= c
+    TK_PH(select_records(sac_k[cur], sac_c[cur], n_sac, kw, c, flag, scan_tmp, tmp_k, tmp_c, &misc[1], stats, s),
+          "select");
+    uint32_t n_out = 0;
+    unsigned long long st2[2] = {0, 0}, n_win = 0;
+    TK_PH(hipMemcpyAsync(&n_out, &misc[1], 4, hipMemcpyDeviceToHost, s), "read");
+    TK_PH(hipMemcpyAsync(st2, stats, 16, hipMemcpyDeviceToHost, s), "read");
+    TK_PH(hipMemcpyAsync(&n_win, &ctr[0].n_windows, 8, hipMemcpyDeviceToHost, s), "read");
+    TK_PH(hipStreamSynchronize(s), "sync");
+    res = static_cast<tk_result *>(calloc(1, sizeof(tk_result)));
+    if (!res) {
+        cleanup();
+        return fail(TK_ENOMEM, "result allocation failed");
+    }
+    res->n = n_out;
+    res->k = (uint32_t)k;
+    res->key_words = (uint32_t)kw;
+    res->n_windows = n_win;
+    res->n_collected = n_coll;
+    res->n_distinct = n_sac;
+    res->n_singletons = st2[0];
+    res->n_below_c = st2[1];
+    res->bloom_blocks = n_blocks;
+    res->part_bits = -1;
+    res->keys = static_cast<uint64_t *>(malloc((n_out ? n_out : 1) * kb));
+    res->counts = static_cast<uint32_t *>(malloc((n_out ? n_out : 1) * sizeof(uint32_t)));
+    if (!res->keys || !res->counts)
+        return dev_fail("result allocation", hipErrorOutOfMemory);
+    if (n_out) {
+        TK_PH(hipMemcpyAsync(res->keys, tmp_k, n_out * kb, hipMemcpyDeviceToHost, s), "copy keys");
+        TK_PH(hipMemcpyAsync(res->counts, tmp_c, n_out * 4, hipMemcpyDeviceToHost, s), "copy counts");
+    }
+    TK_PH(hipStreamSynchronize(s), "sync");
+#undef TK_PH
+    cleanup();
+    *out = res;
+    return TK_OK;
+}
+
 void tk_result_free(tk_result *res) {
     if (!res)
         return;

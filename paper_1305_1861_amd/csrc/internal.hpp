@@ -165,6 +165,20 @@ hipError_t compact(const uint64_t *keys, uint64_t n, int key_words, uint32_t c, 
                    uint32_t *out_counts, void *scratch, size_t scratch_bytes, DevCounters *ctr,
                    hipStream_t stream);
 
+// ---- phased.hip -----------------------------------------------------------
+// Merge of two sorted (key, count) lists with unique keys into one list with
+// unique keys, counts of equal keys added (*n_out, device).  tmp_k/tmp_c and
+// flag hold na + nb entries, scan_tmp scan_scratch_words(na + nb); out holds
+// na + nb records.
+hipError_t merge_compact(const uint64_t *ak, const uint32_t *ac, uint64_t na, const uint64_t *bk, const uint32_t *bc,
+                         uint64_t nb, int key_words, uint64_t *tmp_k, uint32_t *tmp_c, uint32_t *flag,
+                         uint32_t *scan_tmp, uint64_t *out_k, uint32_t *out_c, uint32_t *n_out, hipStream_t stream);
+// Records with count >= c, in order (*n_out, device); stats[0] += records of
+// count 1, stats[1] += records of count in [2, c).  flag holds 2n entries.
+hipError_t select_records(const uint64_t *keys, const uint32_t *cnt, uint64_t n, int key_words, uint32_t c,
+                          uint32_t *flag, uint32_t *scan_tmp, uint64_t *out_k, uint32_t *out_c, uint32_t *n_out,
+                          unsigned long long *stats, hipStream_t stream);
+
 // Number of compute units of the current device (cached).
 int device_cu_count();
 
