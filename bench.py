@@ -302,6 +302,56 @@ def bench_phased(args, tk, readsim, torch, np, dev) -> int:
     return 0
 
 
+def bench_approx(args, tk, readsim, torch, np, dev) -> int:
+    """An approximate variant (cTurtle or the single pass with "+1") on a
+    resident workload: throughput, and false positives / negatives / count
+    errors against the exact per-bucket path on the same input."""
+    lib = readsim.WORKLOADS[args.workload]()
+    bases = torch.from_numpy(lib.bases).to(dev)
+    offsets = torch.from_numpy(lib.offsets.view(np.int64)).to(dev)
+    flag = 4 if args.approx == "cturtle" else 8
+    opts = tk.tk_default_options()
+    opts.flags = tk.TK_FLAG_TIMING | flag
+    opts.bloom_beta = args.approx_beta
+    ws = torch.empty(tk.tk_workspace_size(lib.n_bases, lib.n_reads, lib.k, lib.c, opts), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        tk.tk_count_device(bases, offsets, lib.k, lib.c, opts, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        r = tk.tk_count_device(bases, offsets, lib.k, lib.c, opts, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    got_k = r.keys[:, -1].clone()
+    got_c = r.counts.clone()
+    ex = tk.tk_count_device(bases, offsets, lib.k, lib.c)
+    ex_k, ex_c = ex.keys[:, -1], ex.counts
+    if lib.k > 31:  # two-word keys: compare (hi, lo) pairs through their rank in the union
+        raise SystemExit("approximate bench compares one-word keys")
+    fn = int((~torch.isin(ex_k, got_k)).sum())
+    fp = int((~torch.isin(got_k, ex_k)).sum())
+    over = None
+    if args.approx == "single_pass":
+        idx = torch.searchsorted(ex_k, got_k).clamp(max=ex_k.numel() - 1)
+        hit = ex_k[idx] == got_k
+        over = int((got_c[hit] != ex_c[idx[hit]]).sum())
+    n_ex = int(ex_k.numel())
+    out = {
+        "metric": METRIC, "value": r.n_windows / dt, "unit": "k-mer windows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{args.approx}-{lib.name}", "bits_per_window": args.approx_beta,
+                   "filter_words": int(r.bloom_blocks) * 8},
+        "result": {"n_windows": r.n_windows, "n_reported": int(got_k.numel()), "n_frequent_exact": n_ex,
+                   "false_negative_rate": fn / n_ex, "false_positive_rate": fp / n_ex,
+                   "count_one_over_rate": (over / n_ex) if over is not None else None},
+        "host": platform.node(),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +376,9 @@ def main() -> int:
     ap.add_argument("--chunk-bases", type=float, default=1.0e8, help="phased workload: bases per chunk")
     ap.add_argument("--sac-capacity", type=float, default=6.0e7,
                     help="phased workload: records of the resident sorted-and-compacted array")
+    ap.add_argument("--approx", choices=["cturtle", "single_pass"], default=None,
+                    help="time an approximate variant on the workload and report its errors against the exact path")
+    ap.add_argument("--approx-beta", type=int, default=16, help="approximate variants: filter bits per window")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain "
                          "device copy kernel (reference for HBM byte counters)")
@@ -352,6 +405,8 @@ def main() -> int:
         return bench_served(args, tk, readsim, torch, np, dev)
     if args.workload == "phased":
         return bench_phased(args, tk, readsim, torch, np, dev)
+    if args.approx:
+        return bench_approx(args, tk, readsim, torch, np, dev)
 
     t0 = time.perf_counter()
     lib = readsim.WORKLOADS[args.workload]()

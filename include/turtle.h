@@ -106,10 +106,29 @@ enum {
 };
 
 #define TK_FLAG_TIMING 1u         /* record HIP events around each stage     */
+#define TK_FLAG_CTURTLE 4u        /* approximate: cTurtle (§2.2), see below   */
+#define TK_FLAG_SINGLE_PASS 8u    /* approximate: single pass with "+1" (§2.1)
+                                     see below                               */
 #define TK_FLAG_GLOBAL_FILTER 2u  /* one filter for the whole library in HBM
                                      (device-scope atomics) instead of one
                                      filter per bucket                       */
 
+/*
+ * Approximate variants (one library per call; tk_count / tk_count_device):
+ *   TK_FLAG_CTURTLE: the counting Bloom filter of cTurtle (§2.2).  A k-mer's
+ *     first pattern (two table entries ORed, in 64-bit word
+ *     floor(h * W / 2^64) of a filter of W words) is set at its first
+ *     sighting; a sighting that finds it set tries its second pattern (two
+ *     more entries, in the next word): if not all set, it sets them and the
+ *     k-mer is reported.  Result: the reported k-mers, ascending, counts 0;
+ *     c must be 2.  False positives and negatives come from collisions.
+ *   TK_FLAG_SINGLE_PASS: the single pass of Algorithm 1 as printed: a
+ *     sighting that finds its first pattern set is stored; counts are the
+ *     stored sightings plus one; records with count >= c are kept.
+ * W = max(1, ceil(bloom_beta * windows_estimate / 64)) (bloom_beta up to
+ * 1024 here), or 8 * bloom_blocks when set.  n_collected = stored or
+ * reported sightings.  Not combinable with each other or with batches.
+ */
 typedef struct {
     uint32_t bloom_beta;        /* first-plane bits per window (4); the
                                    partitioned path accepts 1..32          */

@@ -84,6 +84,10 @@ def _load():
                                                    ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32,
                                                    ctypes.c_uint32, ctypes.c_uint64,
                                                    _u64p, _u64p, _u64p]
+        lib.oracle_approx.restype = ctypes.c_int
+        lib.oracle_approx.argtypes = [_u8p, _u64p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_uint64, _u64p, _u64p, _u64p, ctypes.c_uint64, _u64p, _u64p]
         lib.oracle_bloom_model.restype = ctypes.c_int
         lib.oracle_bloom_model.argtypes = [_u8p, _u64p, ctypes.c_uint64, ctypes.c_int,
                                            ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
@@ -138,6 +142,33 @@ def kmer_count(bases, offsets, k: int, c: int) -> Counted:
     if r < 0:
         raise ValueError(f"oracle_kmer_count: status {r}")
     return Counted(hi[:r].copy(), lo[:r].copy(), cnt[:r].copy(), int(nw.value), int(nd.value))
+
+
+def approx_words(n_bases: int, n_reads: int, k: int, beta: int) -> int:
+    """Filter words of the approximate variants: max(1, ceil(beta * W / 64))
+    with W = max(n_bases - n_reads * (k - 1), 1) estimated windows."""
+    w = max(n_bases - n_reads * (k - 1), 1)
+    return max(1, -(-beta * w // 64))
+
+
+def approx_count(bases, offsets, k: int, mode: str, c: int, n_words: int,
+                 n_patterns: int = 1024, n_bits: int = 2, seed: int = 1305):
+    """The approximate variants run sequentially in read order: mode
+    "cturtle" (reported keys, count 0) or "single_pass" (stored sightings
+    compacted, count = run + 1, kept when >= c).  Returns (Counted, number
+    of reported or stored sightings)."""
+    b, o, n = _reads(bases, offsets)
+    cap = max(1, int(b.size))
+    hi, lo, cnt = np.empty(cap, np.uint64), np.empty(cap, np.uint64), np.empty(cap, np.uint64)
+    n_out, n_rep = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    m = {"cturtle": 1, "single_pass": 2}[mode]
+    r = _load().oracle_approx(_p(b, _u8p), _p(o, _u64p), n, k, m, c, n_words, n_patterns, n_bits, seed,
+                              _p(hi, _u64p), _p(lo, _u64p), _p(cnt, _u64p), cap,
+                              ctypes.byref(n_out), ctypes.byref(n_rep))
+    if r != 0:
+        raise ValueError(f"oracle_approx: status {r}")
+    q = int(n_out.value)
+    return Counted(hi[:q].copy(), lo[:q].copy(), cnt[:q].copy(), 0, q), int(n_rep.value)
 
 
 def sort_compact(hi, lo):

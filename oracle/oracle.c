@@ -624,3 +624,102 @@ int oracle_bloom_model_buckets(const uint8_t *bases, const uint64_t *offsets,
     free(keys); free(hi); free(lo);
     return st;
 }
+
+/*
+ * Approximate variants, run sequentially over the windows in read order.
+ * The filter is n_words 64-bit words; a key's first pattern is the OR of
+ * table entries e0 and e1 (e_w = (h >> (w * lg)) mod P, h the key hash) in
+ * word floor(h * n_words / 2^64), its second pattern the OR of e2 and e3 in
+ * the next word (word 0 after the last).
+ *   mode 1, cTurtle (§2.2): if the first pattern is not all set, set it;
+ *     otherwise, if the second pattern is not all set, set it and report the
+ *     key.  Output: the reported keys in ascending order, count 0.
+ *   mode 2, the single pass of Algorithm 1 as printed (§2.1): if the first
+ *     pattern is all set, store the key, else set it.  Output: the stored
+ *     keys sorted and compacted, count = run length + 1 (the "+1"), kept
+ *     when >= c.
+ * *n_reported receives the number of reported (mode 1) or stored (mode 2)
+ * sightings.  Returns OR_ECAP when more than `capacity` records result.
+ */
+int oracle_approx(const uint8_t *bases, const uint64_t *offsets,
+                  uint64_t n_reads, int k, int mode, uint32_t c,
+                  uint64_t n_words, uint32_t n_patterns, uint32_t n_bits,
+                  uint64_t seed, uint64_t *out_hi, uint64_t *out_lo,
+                  uint64_t *out_count, uint64_t capacity, uint64_t *n_out,
+                  uint64_t *n_reported)
+{
+    int st = check_args(offsets, n_reads, k);
+    int lg = log2_exact(n_patterns);
+    if (st != OR_OK || (mode != 1 && mode != 2) || n_words == 0 || lg < 0 ||
+        lg * BLOCK_WORDS > 64 || n_bits == 0 || n_bits > 64 || c == 0)
+        return OR_EINVAL;
+    uint8_t *pos = (uint8_t *)malloc((size_t)n_patterns * n_bits);
+    uint64_t *mask = (uint64_t *)calloc(n_patterns, sizeof(uint64_t));
+    uint64_t *filter = (uint64_t *)calloc(n_words, sizeof(uint64_t));
+    u128 *keys = NULL;
+    uint64_t n = 0;
+    if (!pos || !mask || !filter) {
+        free(pos); free(mask); free(filter);
+        return OR_ENOMEM;
+    }
+    oracle_pattern_positions(seed, n_patterns, n_bits, pos);
+    for (uint32_t e = 0; e < n_patterns; e++)
+        for (uint32_t j = 0; j < n_bits; j++)
+            mask[e] |= 1ull << pos[(size_t)e * n_bits + j];
+    free(pos);
+    st = enumerate_keys(bases, offsets, n_reads, k, &keys, &n);
+    if (st != OR_OK) {
+        free(mask); free(filter);
+        return st;
+    }
+    const int two = k > 31;
+    uint64_t kept = 0;  /* keys[0..kept) are the reported or stored sightings */
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t h = key_hash(keys[i], two);
+        uint64_t w1 = (uint64_t)(((u128)h * n_words) >> 64);
+        uint64_t m1 = mask[h & (n_patterns - 1)] | mask[(h >> lg) & (n_patterns - 1)];
+        int seen = (filter[w1] & m1) == m1;
+        filter[w1] |= m1;
+        if (!seen)
+            continue;
+        if (mode == 2) {
+            keys[kept++] = keys[i];
+            continue;
+        }
+        uint64_t w2 = w1 + 1 < n_words ? w1 + 1 : 0;
+        uint64_t m2 = mask[(h >> (2 * lg)) & (n_patterns - 1)] |
+                      mask[(h >> (3 * lg)) & (n_patterns - 1)];
+        int done = (filter[w2] & m2) == m2;
+        filter[w2] |= m2;
+        if (!done)
+            keys[kept++] = keys[i];
+    }
+    *n_reported = kept;
+    free(mask);
+    free(filter);
+    uint64_t *runs = kept ? (uint64_t *)malloc(kept * sizeof(uint64_t)) : NULL;
+    if (kept && !runs) {
+        free(keys);
+        return OR_ENOMEM;
+    }
+    uint64_t n_runs = 0;
+    sort_and_compact(keys, kept, runs, &n_runs);
+    uint64_t o = 0;
+    for (uint64_t r = 0; r < n_runs; r++) {
+        uint64_t cnt = mode == 1 ? 0 : runs[r] + 1;
+        if (mode == 2 && cnt < c)
+            continue;
+        if (o >= capacity) {
+            free(keys); free(runs);
+            return OR_ECAP;
+        }
+        out_hi[o] = (uint64_t)(keys[r] >> 64);
+        out_lo[o] = (uint64_t)keys[r];
+        out_count[o] = cnt;
+        o++;
+    }
+    *n_out = o;
+    free(keys);
+    free(runs);
+    return OR_OK;
+}

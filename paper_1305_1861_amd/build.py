@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libturtle.so")
 ARCH = "gfx950"
 
 SOURCES = ["pack.hip", "bloom.hip", "scan.hip", "radix.hip", "compact.hip", "partition.hip", "bucket.hip",
-           "phased.hip", "api.hip"]
+           "phased.hip", "approx.hip", "api.hip"]
 
 CXXFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",

@@ -69,7 +69,11 @@ tk_status resolve(const tk_options *o, Opts *r) {
         r->seed = o->bloom_seed ? o->bloom_seed : DEF_SEED;
         r->part_bits = o->part_bits;
     }
-    const bool global = r->flags & TK_FLAG_GLOBAL_FILTER;
+    const bool global = r->flags & (TK_FLAG_GLOBAL_FILTER | TK_FLAG_CTURTLE | TK_FLAG_SINGLE_PASS);
+    if ((r->flags & TK_FLAG_CTURTLE) && (r->flags & (TK_FLAG_SINGLE_PASS | TK_FLAG_GLOBAL_FILTER)))
+        return fail(TK_EINVAL, "TK_FLAG_CTURTLE combines with no other path flag");
+    if ((r->flags & TK_FLAG_SINGLE_PASS) && (r->flags & TK_FLAG_GLOBAL_FILTER))
+        return fail(TK_EINVAL, "TK_FLAG_SINGLE_PASS combines with no other path flag");
     if (r->beta > (global ? 1024u : 32u))
         return fail(TK_EINVAL, "bloom_beta %u out of range [1, %u]", r->beta, global ? 1024u : 32u);
     if (r->table_bits < 1 || r->table_bits > 10)
@@ -142,6 +146,8 @@ int part_bits_for(uint64_t n_bases, uint64_t n_reads, int k, const Opts &o) {
 constexpr uint64_t MAX_BUCKET_GRID = 4096;
 
 struct Plan {
+    int approx;            // 0 exact; 1 cTurtle; 2 single pass with "+1"
+    uint64_t approx_words; // filter words of the approximate variants
     int k, key_words;
     uint32_t c;            // global path
     bool screen, global;   // screen: some library has c >= 2
@@ -203,14 +209,26 @@ tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *
     p->screen = false;
     for (uint64_t j = 0; j < n_libs; j++)
         p->screen = p->screen || c[j] >= 2;
-    p->global = p->opts.flags & TK_FLAG_GLOBAL_FILTER;
+    p->approx = (p->opts.flags & TK_FLAG_CTURTLE) ? 1 : (p->opts.flags & TK_FLAG_SINGLE_PASS) ? 2 : 0;
+    p->global = (p->opts.flags & TK_FLAG_GLOBAL_FILTER) || p->approx;
     if (p->global && n_libs != 1)
-        return fail(TK_EINVAL, "the global-filter path counts one library per call");
+        return fail(TK_EINVAL, "the global-filter path and the approximate variants count one library per call");
+    if (p->approx == 1 && c[0] != 2)
+        return fail(TK_EINVAL, "cTurtle reports k-mers seen more than once: c must be 2");
+    if (p->approx)
+        p->screen = true;
     p->n_bases = n_bases;
     p->n_reads = n_reads;
     p->n_words = ceil_div(n_bases, 32);
     p->cap = n_bases;  // windows <= bases
     p->n_blocks = (p->screen && p->global) ? bloom_blocks_for(n_bases, n_reads, k, p->opts) : 0;
+    p->approx_words = 0;
+    if (p->approx) {
+        const uint64_t cut = n_reads * (uint64_t)(k - 1);
+        const uint64_t est = n_bases > cut ? n_bases - cut : 1;
+        p->approx_words = p->opts.blocks ? 8 * p->opts.blocks : std::max<uint64_t>(1, ceil_div(p->opts.beta * est, 64));
+        p->n_blocks = ceil_div(p->approx_words, 8);
+    }
     if (p->n_blocks > (1ull << 40))
         return fail(TK_EINVAL, "filter of %llu blocks is too large", (unsigned long long)p->n_blocks);
     p->n_libs = (uint32_t)n_libs;
@@ -442,11 +460,15 @@ tk_status run_global(const uint8_t *d_bases, const uint64_t *d_offsets, const Pl
         return st;
     BloomArgs a{packed, valid, p.n_words, p.k, table, p.opts.table_bits, p.n_blocks, filter};
     const int grid = persistent_grid(p.n_words * 32);
-    if (p.screen)
+    if (p.screen && !p.approx)
         TK_HIP(launch_screen(a, grid, s));
     if ((st = tm.end(TK_STAGE_SCREEN, s)) != TK_OK || (st = tm.mark(TK_STAGE_COLLECT, s)) != TK_OK)
         return st;
-    TK_HIP(launch_collect(a, p.screen, keys_a, p.cap, &ctr->n_collected, grid, s));
+    if (p.approx)
+        TK_HIP(launch_approx(packed, valid, p.n_words, p.k, table, p.opts.table_bits, filter, p.approx_words,
+                             p.approx == 1, keys_a, p.cap, &ctr->n_collected, grid, s));
+    else
+        TK_HIP(launch_collect(a, p.screen, keys_a, p.cap, &ctr->n_collected, grid, s));
     if ((st = tm.end(TK_STAGE_COLLECT, s)) != TK_OK)
         return st;
 
@@ -466,7 +488,12 @@ tk_status run_global(const uint8_t *d_bases, const uint64_t *d_offsets, const Pl
     uint64_t *out_keys = sorted == keys_a ? keys_b : keys_a;
     if ((st = tm.end(TK_STAGE_SORT, s)) != TK_OK || (st = tm.mark(TK_STAGE_COMPACT, s)) != TK_OK)
         return st;
-    TK_HIP(compact(sorted, n, p.key_words, p.c, out_keys, counts, ws + p.off_compact, p.compact_bytes, ctr, s));
+    // cTurtle reports every key once (kept, counts cleared); the single pass
+    // counts stored sightings, one short of the count
+    const uint32_t c_eff = p.approx == 1 ? 1u : p.approx == 2 ? std::max(1u, p.c - 1) : p.c;
+    TK_HIP(compact(sorted, n, p.key_words, c_eff, out_keys, counts, ws + p.off_compact, p.compact_bytes, ctr, s));
+    if (p.approx)
+        TK_HIP(launch_adjust_counts(counts, ctr, p.approx == 1 ? 0u : 1u, s));
     if ((st = tm.end(TK_STAGE_COMPACT, s)) != TK_OK)
         return st;
     TK_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));

@@ -179,6 +179,17 @@ hipError_t select_records(const uint64_t *keys, const uint32_t *cnt, uint64_t n,
                           uint32_t *flag, uint32_t *scan_tmp, uint64_t *out_k, uint32_t *out_c, uint32_t *n_out,
                           unsigned long long *stats, hipStream_t stream);
 
+// ---- approx.hip -----------------------------------------------------------
+// One pass of cTurtle (cturtle) or of the single-pass "+1" variant over the
+// packed windows: reported keys appended to out (at most capacity; *n_out
+// counts every report).
+hipError_t launch_approx(const uint64_t *packed, const uint32_t *valid, uint64_t n_words, int k,
+                         const uint64_t *table, uint32_t table_bits, uint64_t *filter, uint64_t n_filter_words,
+                         bool cturtle, void *out, uint64_t capacity, unsigned long long *n_out, int grid,
+                         hipStream_t stream);
+// counts[0, c->n_out) += add, or = 0 when add is 0.
+hipError_t launch_adjust_counts(uint32_t *counts, const DevCounters *c, uint32_t add, hipStream_t stream);
+
 // Number of compute units of the current device (cached).
 int device_cu_count();
 
