@@ -640,6 +640,11 @@ int oracle_bloom_model_buckets(const uint8_t *bases, const uint64_t *offsets,
  *     when >= c.
  * *n_reported receives the number of reported (mode 1) or stored (mode 2)
  * sightings.  Returns OR_ECAP when more than `capacity` records result.
+ * Pinned: with a filter large enough to have no collisions both modes equal
+ * the exact counting above; whatever the collisions, mode 2 counts are the
+ * true count or one more and miss no k-mer seen twice, mode 1 reports every
+ * key once.  Which keys a colliding filter misreports is parity unpinned:
+ * the paper fixes none of the filter's constants.
  */
 int oracle_approx(const uint8_t *bases, const uint64_t *offsets,
                   uint64_t n_reads, int k, int mode, uint32_t c,
