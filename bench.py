@@ -352,6 +352,74 @@ def bench_approx(args, tk, readsim, torch, np, dev) -> int:
     return 0
 
 
+def bench_shards(args, tk, readsim, torch, np, dev) -> int:
+    """Key-range shards of one library on one device: each shard's call is
+    the work one of G devices would do on its share (all windows extracted,
+    only the shard's keys partitioned, screened, sorted and compacted).
+    Reports every shard's device time; the step of G devices would take the
+    slowest shard plus the broadcast of the packed reads, which one device
+    cannot show."""
+    G = args.shards
+    lib = readsim.WORKLOADS[args.workload]()
+    bases = torch.from_numpy(lib.bases).to(dev)
+    offsets = torch.from_numpy(lib.offsets.view(np.int64)).to(dev)
+    stream = torch.cuda.current_stream()
+    full_o = tk.tk_default_options()
+    full_o.flags = tk.TK_FLAG_TIMING
+    opts = []
+    for g in range(G):
+        o = tk.tk_default_options()
+        o.flags = tk.TK_FLAG_TIMING
+        o.shard_count, o.shard_index = G, g
+        opts.append(o)
+    need = max(tk.tk_workspace_size(lib.n_bases, lib.n_reads, lib.k, lib.c, o) for o in opts + [full_o])
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    full = tk.tk_count_device(bases, offsets, lib.k, lib.c, full_o, workspace=ws, stream=stream)
+    full_keys, full_counts = full.keys.clone(), full.counts.clone()
+    full_ms = sum(full.stage_ms.values())
+    # parity of the concatenation with the unsharded result
+    got_k, got_c, wins = [], [], []
+    for o in opts:
+        r = tk.tk_count_device(bases, offsets, lib.k, lib.c, o, workspace=ws, stream=stream)
+        got_k.append(r.keys.clone())
+        got_c.append(r.counts.clone())
+        wins.append(r.n_windows)
+    same = bool(torch.equal(torch.cat(got_k), full_keys) and torch.equal(torch.cat(got_c), full_counts))
+    del got_k, got_c
+    for _ in range(args.warmup):
+        for o in opts:
+            tk.tk_count_device(bases, offsets, lib.k, lib.c, o, workspace=ws, stream=stream)
+    ms = np.zeros((args.steps, G))
+    stages = {s: np.zeros(G) for s in tk.STAGES}
+    for i in range(args.steps):
+        for g, o in enumerate(opts):
+            r = tk.tk_count_device(bases, offsets, lib.k, lib.c, o, workspace=ws, stream=stream)
+            ms[i, g] = sum(r.stage_ms.values())
+            for s in tk.STAGES:
+                stages[s][g] += r.stage_ms[s] / args.steps
+    torch.cuda.synchronize()
+    per = ms.mean(axis=0)
+    total = float(per.sum())
+    out = {
+        "metric": METRIC, "value": full.n_windows / (total * 1e-3), "unit": "k-mer windows/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": total,
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "u64" if lib.k <= 31 else "u128",
+        "data": "synthetic",
+        "config": {"workload": f"{lib.name}-shard-of-{G}", "shards": G, "k": lib.k, "c": lib.c},
+        "note": "one device runs the G shards one after the other; value: the library's windows over "
+                "their summed device time.  slowest_shard_ms is what each of G devices would spend on its "
+                "share, before the broadcast of the packed reads",
+        "result": {"concatenation_equals_unsharded": same, "unsharded_ms": full_ms,
+                   "slowest_shard_ms": round(float(per.max()), 3),
+                   "shard_ms": [round(float(x), 3) for x in per],
+                   "shard_windows": wins,
+                   "shard_stage_ms_mean": {s: round(float(v.mean()), 3) for s, v in stages.items() if v.any()}},
+        "host": platform.node(),
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if same else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,6 +447,9 @@ def main() -> int:
     ap.add_argument("--approx", choices=["cturtle", "single_pass"], default=None,
                     help="time an approximate variant on the workload and report its errors against the exact path")
     ap.add_argument("--approx-beta", type=int, default=16, help="approximate variants: filter bits per window")
+    ap.add_argument("--shards", type=int, default=1,
+                    help="time every key-range shard of the workload in turn (the share of one of this many "
+                         "devices) and check that their results concatenate to the unsharded one")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain "
                          "device copy kernel (reference for HBM byte counters)")
@@ -407,6 +478,8 @@ def main() -> int:
         return bench_phased(args, tk, readsim, torch, np, dev)
     if args.approx:
         return bench_approx(args, tk, readsim, torch, np, dev)
+    if args.shards > 1:
+        return bench_shards(args, tk, readsim, torch, np, dev)
 
     t0 = time.perf_counter()
     lib = readsim.WORKLOADS[args.workload]()

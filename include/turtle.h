@@ -140,8 +140,31 @@ typedef struct {
     uint64_t bloom_seed;        /* SplitMix64 seed of the table (1305)       */
     int32_t part_bits;          /* partitioned path: bucket bits D, 0..20;
                                    -1 (default) = size rule                 */
-    uint32_t reserved;
+    uint32_t shard_count;       /* key-range shards, 0 or 1 = none; <= 1024  */
+    uint32_t shard_index;       /* the shard this call counts, < shard_count */
+    uint32_t reserved;          /* 0 */
 } tk_options;
+
+/*
+ * Key-range shards (partitioned path, one library per call): the share of
+ * the work one of G devices does when the library is split among G devices
+ * that each hold all of its reads -- the counterpart of the paper's routing
+ * of every k-mer to the one consumer that owns its filter (§2.1,
+ * parallelization), with key ranges as owners.  Every window is extracted,
+ * and the first partition pass counts the library's top-digit histogram
+ * (top D1 = min(D, 10) bits of the canonical key).  Digit d goes to shard
+ * min(G - 1, floor(G * (below(d) + n(d) / 2) / M)), where n(d) is its
+ * window count, below(d) that of the digits before it, and M the library's
+ * window count.  The owners are contiguous and the shares even to within one
+ * digit's mass.  A call with shard_index = g keeps only the keys of its
+ * digits from then on: the rest of the partition, the per-bucket filters, the
+ * sort and the compaction see only the shard.  Every
+ * bucket lies in one shard and meets exactly the filter it meets unsharded.
+ * So the results of g = 0..G-1, concatenated in order, are the unsharded
+ * result record for record, and every statistic (n_windows: the shard's
+ * windows) adds up to the unsharded one.  Not combinable with the global
+ * filter, the approximate variants, batches or the phased call.
+ */
 
 typedef struct {
     uint64_t n;             /* records in keys/counts (count >= c)           */

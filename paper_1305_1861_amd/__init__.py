@@ -37,7 +37,8 @@ _vp = ctypes.c_void_p
 class tk_options(ctypes.Structure):
     _fields_ = [("bloom_beta", _u32), ("bloom_table_bits", _u32), ("bloom_bits", _u32),
                 ("flags", _u32), ("bloom_blocks", _u64), ("bloom_seed", _u64),
-                ("part_bits", ctypes.c_int32), ("reserved", _u32)]
+                ("part_bits", ctypes.c_int32), ("shard_count", _u32), ("shard_index", _u32),
+                ("reserved", _u32)]
 
 
 class tk_result(ctypes.Structure):

@@ -47,6 +47,7 @@ struct Opts {
     uint32_t beta, table_bits, bits, flags;
     uint64_t blocks, seed;
     int part_bits;
+    uint32_t shard_count, shard_index;
 };
 
 tk_status resolve(const tk_options *o, Opts *r) {
@@ -57,6 +58,8 @@ tk_status resolve(const tk_options *o, Opts *r) {
     r->blocks = 0;
     r->seed = DEF_SEED;
     r->part_bits = -1;
+    r->shard_count = 1;
+    r->shard_index = 0;
     if (o) {
         if (o->bloom_beta)
             r->beta = o->bloom_beta;
@@ -68,6 +71,8 @@ tk_status resolve(const tk_options *o, Opts *r) {
         r->blocks = o->bloom_blocks;
         r->seed = o->bloom_seed ? o->bloom_seed : DEF_SEED;
         r->part_bits = o->part_bits;
+        r->shard_count = o->shard_count ? o->shard_count : 1;
+        r->shard_index = o->shard_index;
     }
     const bool global = r->flags & (TK_FLAG_GLOBAL_FILTER | TK_FLAG_CTURTLE | TK_FLAG_SINGLE_PASS);
     if ((r->flags & TK_FLAG_CTURTLE) && (r->flags & (TK_FLAG_SINGLE_PASS | TK_FLAG_GLOBAL_FILTER)))
@@ -82,6 +87,11 @@ tk_status resolve(const tk_options *o, Opts *r) {
         return fail(TK_EINVAL, "part_bits %d out of range [-1, 20]", r->part_bits);
     if (r->bits < 1 || r->bits > 16)
         return fail(TK_EINVAL, "bloom_bits %u out of range [1, 16]", r->bits);
+    if (r->shard_count > 1024 || r->shard_index >= r->shard_count)
+        return fail(TK_EINVAL, "shard %u of %u: need shard_index < shard_count <= 1024", r->shard_index,
+                    r->shard_count);
+    if (r->shard_count > 1 && global)
+        return fail(TK_EINVAL, "key-range shards need the partitioned path");
     return TK_OK;
 }
 
@@ -213,6 +223,8 @@ tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *
     p->global = (p->opts.flags & TK_FLAG_GLOBAL_FILTER) || p->approx;
     if (p->global && n_libs != 1)
         return fail(TK_EINVAL, "the global-filter path and the approximate variants count one library per call");
+    if (p->opts.shard_count > 1 && n_libs != 1)
+        return fail(TK_EINVAL, "key-range shards split one library per call");
     if (p->approx == 1 && c[0] != 2)
         return fail(TK_EINVAL, "cTurtle reports k-mers seen more than once: c must be 2");
     if (p->approx)
@@ -269,6 +281,8 @@ tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *
         p->part.nseg = (uint32_t)n_seg;
         p->part.D2max = d2max;
         p->part.cap = p->cap;
+        p->part.shard_count = p->opts.shard_count;
+        p->part.shard_index = p->opts.shard_index;
         p->fb_cap = p->cap / ((uint64_t)bucket_capacity(p->key_words) + 1) + 1;
         p->fb_nb_max = p->screen ? ceil_div((uint64_t)p->opts.beta * std::max<uint64_t>(p->cap, 1), 256) + p->fb_cap : 0;
         p->part_words = partition_scratch_words(p->part, p->key_words);
@@ -1004,6 +1018,8 @@ tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_
     tk_status st = resolve(opts, &o);
     if (st != TK_OK)
         return st;
+    if (o.shard_count > 1)
+        return fail(TK_EINVAL, "key-range shards need the partitioned path");
     const int kw = k <= 31 ? 1 : 2;
     const size_t kb = 8 * (size_t)kw;
     const bool screen = c >= 2;

@@ -84,6 +84,8 @@ struct PartPlan {
     uint32_t nseg;        // pass-2 segments of all libraries
     int D2max;            // largest pass-2 digit; 0: no second pass
     uint64_t cap;         // key capacity of tmp and out
+    uint32_t shard_count; // key-range shards (one library): 1 = none
+    uint32_t shard_index; // the shard whose keys are kept
 };
 size_t partition_scratch_words(const PartPlan &p, int key_words);
 // out receives the keys; lib_keys (device, n_libs + 1) the first key of

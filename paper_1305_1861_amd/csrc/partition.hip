@@ -78,6 +78,8 @@ struct PassArgs {
     const uint32_t *cb;      // pass 2: first chunk of every segment (nseg + 1)
     const uint32_t *eb;      // pass 2: first count entry of every segment (nseg + 1)
     uint32_t nseg;
+    const uint32_t *own;     // pass 1 of a key-range shard: its digits
+                             // [own[0], own[1]); nullptr: every digit
 };
 
 // The chunk of this workgroup: elements [c0, c1) (window positions of pass
@@ -213,6 +215,12 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint3
     if (!chunk_of<K, FROM_WIN>(a, ch))
         return;  // uniform over the block
     const uint32_t bins = 1u << ch.bits, mask = bins - 1;
+    // a shard keeps the keys of its digits only (pass 1, one library)
+    uint32_t own_lo = 0, own_hi = bins;
+    if (FROM_WIN && a.own) {
+        own_lo = a.own[0];
+        own_hi = a.own[1];
+    }
     // thread t owns digits t * PT_BPT .. t * PT_BPT + PT_BPT - 1
     const uint32_t d0 = (uint32_t)tid * PT_BPT;
 #pragma unroll
@@ -224,14 +232,17 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint3
     __syncthreads();
     for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += TILE) {
         K key[ITEMS];
-        const uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + (uint64_t)TILE, ch.c1), ch.lo, key);
+        uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + (uint64_t)TILE, ch.c1), ch.lo, key);
         uint32_t rd[ITEMS];  // (rank << 10) | digit
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             rd[i] = 0;
             if ((vm >> i) & 1u) {
                 const uint32_t d = digit_of(key[i], ch.shift, mask);
-                rd[i] = (atomicAdd(&s_cnt[d], 1u) << PT_MAX_BITS) | d;
+                if (d >= own_lo && d < own_hi)
+                    rd[i] = (atomicAdd(&s_cnt[d], 1u) << PT_MAX_BITS) | d;
+                else
+                    vm &= ~(1u << i);
             }
         }
         __syncthreads();
@@ -282,6 +293,67 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint3
         }
         __syncthreads();
     }
+}
+
+// Key-range shards of one library (pass 1, before the scan).  Window count
+// of every digit d: the sum of its n_ch chunk counts hist[d * n_ch + i].
+__global__ __launch_bounds__(256) void shard_totals(const uint32_t *__restrict__ hist, uint32_t n_ch,
+                                                    uint32_t *__restrict__ tot) {
+    __shared__ uint32_t s_w[256 / WAVE];
+    const uint32_t d = blockIdx.x;
+    uint32_t sum = 0;
+    for (uint32_t i = threadIdx.x; i < n_ch; i += 256)
+        sum += hist[(uint64_t)d * n_ch + i];
+    sum = wave_inclusive_sum(sum);
+    if (lane_id() == WAVE - 1)
+        s_w[threadIdx.x / WAVE] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < 256 / WAVE; w++)
+            t += s_w[w];
+        tot[d] = t;
+    }
+}
+
+// Owner of digit d (one workgroup, n_dig <= SH_THREADS digits):
+// min(G - 1, floor(G * (below(d) + tot(d) / 2) / M)), non-decreasing in d, so
+// shard g owns the digits [own[0], own[1]) = [#{owner < g}, #{owner <= g}).
+constexpr int SH_THREADS = 1024;
+__global__ __launch_bounds__(SH_THREADS) void shard_select(const uint32_t *__restrict__ tot, uint32_t n_dig,
+                                                            uint32_t G, uint32_t g, uint32_t *__restrict__ own) {
+    __shared__ uint32_t s_w[SH_THREADS / WAVE];
+    const uint32_t d = threadIdx.x;
+    const uint32_t t = d < n_dig ? tot[d] : 0u;
+    const uint32_t inc = wave_inclusive_sum(t);
+    if (lane_id() == WAVE - 1)
+        s_w[d / WAVE] = inc;
+    __syncthreads();
+    uint64_t before = inc - t, M = 0;
+    for (int w = 0; w < SH_THREADS / WAVE; w++) {
+        before += (uint32_t)w < d / WAVE ? s_w[w] : 0u;
+        M += s_w[w];
+    }
+    uint32_t owner = 0;
+    if (M)
+        owner = (uint32_t)min<uint64_t>(G - 1, (uint64_t)G * (2 * before + t) / (2 * M));
+    const int below = __syncthreads_count(d < n_dig && owner < g);
+    const int upto = __syncthreads_count(d < n_dig && owner <= g);
+    if (d == 0) {
+        own[0] = (uint32_t)below;
+        own[1] = (uint32_t)upto;
+    }
+}
+
+// Counts of the digits a shard does not own become 0, so that the scan
+// places only its keys.
+__global__ __launch_bounds__(256) void shard_clear(uint32_t *__restrict__ hist, uint32_t n_ch,
+                                                   const uint32_t *__restrict__ own) {
+    const uint32_t d = blockIdx.x;
+    if (d >= own[0] && d < own[1])
+        return;
+    for (uint32_t i = threadIdx.x; i < n_ch; i += 256)
+        hist[(uint64_t)d * n_ch + i] = 0;
 }
 
 // Start of segment s (library j, top digit d) from the scanned pass-1
@@ -335,8 +407,9 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
     const uint64_t grid2 = ceil_div(p.cap, pt_chunk<K>()) + p.nseg;  // bound on pass-2 chunks
     const uint64_t n2 = grid2 << p.D2max;
     const uint64_t H = std::max(n1 + scan_scratch_words(n1), n2 + scan_scratch_words(n2));
-    const uint64_t need = H + 3 * ((uint64_t)p.nseg + 1) + scan_scratch_words(p.nseg) + 4;
-    if (need > scratch_words)
+    const bool shard = p.shard_count > 1;
+    const uint64_t need = H + 3 * ((uint64_t)p.nseg + 1) + scan_scratch_words(p.nseg) + 4 + (shard ? p.nseg + 2 : 0);
+    if (need > scratch_words || (shard && (p.n_libs != 1 || p.nseg > SH_THREADS)))
         return hipErrorInvalidValue;
     uint32_t *hist = scratch;
     uint32_t *seg = scratch + H;
@@ -344,6 +417,8 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
     uint32_t *eb = cb + (p.nseg + 1);
     uint32_t *sscan = eb + (p.nseg + 1);
     uint32_t *total1 = sscan + scan_scratch_words(p.nseg);
+    uint32_t *own = total1 + 4;    // shards: owned digits, then the digit totals
+    uint32_t *dig_tot = own + 2;
     const dim3 block(PT_THREADS);
 
     PassArgs a{};
@@ -364,6 +439,15 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
         pt_hist<K, true><<<dim3(p.nch1), block, 0, stream>>>(a, hist);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
+        if (shard) {  // one library: nseg digits of nch1 counts each
+            shard_totals<<<dim3(p.nseg), dim3(256), 0, stream>>>(hist, p.nch1, dig_tot);
+            shard_select<<<dim3(1), dim3(SH_THREADS), 0, stream>>>(dig_tot, p.nseg, p.shard_count, p.shard_index,
+                                                                   own);
+            shard_clear<<<dim3(p.nseg), dim3(256), 0, stream>>>(hist, p.nch1, own);
+            if ((e = hipGetLastError()) != hipSuccess)
+                return e;
+            a.own = own;
+        }
     }
     if ((e = launch_exclusive_scan(hist, hist, n1, hist + n1, total1, stream)) != hipSuccess)
         return e;
@@ -404,7 +488,7 @@ size_t partition_scratch_words(const PartPlan &p, int key_words) {
     const uint64_t grid2 = ceil_div(p.cap, partition_chunk(key_words)) + p.nseg;
     const uint64_t n2 = grid2 << p.D2max;
     const uint64_t H = std::max(n1 + scan_scratch_words(n1), n2 + scan_scratch_words(n2));
-    return H + 3 * ((uint64_t)p.nseg + 1) + scan_scratch_words(p.nseg) + 4;
+    return H + 3 * ((uint64_t)p.nseg + 1) + scan_scratch_words(p.nseg) + 4 + (p.shard_count > 1 ? p.nseg + 2 : 0);
 }
 
 hipError_t partition_keys(const PartPlan &p, int key_words, void *tmp, void *out, uint32_t *scratch,

@@ -177,3 +177,26 @@ def test_batch_bad_arguments_rejected(lib, lb, lr, c, opts, what):
     with pytest.raises(tk.TurtleError) as e:
         tk.tk_batch_workspace_size(lb, lr, 31, c, opts)
     assert e.value.status == tk.TK_EINVAL and what in str(e.value)
+
+
+@pytest.mark.parametrize("opts,what", [
+    (dict(shard_count=4, shard_index=4), "shard"),
+    (dict(shard_count=2000, shard_index=0), "shard"),
+    (dict(shard_count=0, shard_index=1), "shard"),
+    (dict(shard_count=2, shard_index=0, flags=2), "partitioned"),
+    (dict(shard_count=2, shard_index=1, flags=4), "partitioned"),
+])
+def test_bad_shards_rejected(lib, opts, what):
+    with pytest.raises(tk.TurtleError) as e:
+        tk.tk_workspace_size(100_000, 1000, 31, 2, opts)
+    assert e.value.status == tk.TK_EINVAL and what in str(e.value)
+
+
+def test_shards_split_one_library_per_call(lib):
+    with pytest.raises(tk.TurtleError) as e:
+        tk.tk_batch_workspace_size([0, 500, 1000], [0, 5, 10], 31, [2, 2], dict(shard_count=2, shard_index=0))
+    assert e.value.status == tk.TK_EINVAL and "shard" in str(e.value)
+    # one shard of one library: the same buffers plus the digit table
+    one = tk.tk_workspace_size(10_000_000, 100_000, 31, 2)
+    sh = tk.tk_workspace_size(10_000_000, 100_000, 31, 2, dict(shard_count=8, shard_index=3))
+    assert one <= sh <= one + 8192
