@@ -26,7 +26,8 @@ constexpr int BK_THREADS = 512;
 constexpr int BK_WAVES = BK_THREADS / WAVE;
 constexpr int BK_SORT_BITS = 9;
 constexpr int BK_BINS = 1 << BK_SORT_BITS;  // == BK_THREADS: one bin per thread
-constexpr int BK_TABLE = 1024;              // pattern table entries held in LDS (max)
+constexpr int BK_TABLE_BITS = 10;         // log2 of the largest pattern table (the default)
+constexpr int BK_TABLE = 1 << BK_TABLE_BITS;  // pattern table entries held in LDS (max)
 
 template <typename K>
 struct BkItems;
@@ -111,18 +112,32 @@ __device__ __forceinline__ uint64_t sentinel<uint64_t>() { return ~0ull; }
 template <>
 __device__ __forceinline__ Key2 sentinel<Key2>() { return Key2{~0ull, ~0ull}; }
 
-// Bits [shift, shift + nbits) of a group's virtual sort key
-// V = ((bucket - d0) << SB) | (key bits below the bucket digit), nbits <= 12.
+// A group's virtual sort key V = ((bucket - d0) << SB) | (key bits below
+// the bucket digit) is key - (d0 << SB): the group's keys belong to one
+// library and their buckets are at least d0.  vbase = d0 << SB.
 template <typename K>
-__device__ __forceinline__ uint32_t vdigit(const K &key, int shift, int nbits, int SB, int k, int D, uint32_t d0) {
-    const int lowbits = shift < SB ? min(nbits, SB - shift) : 0;
-    const int hshift = shift > SB ? shift - SB : 0;
-    uint32_t d = 0;
-    if (lowbits)
-        d = digit_of(key, shift, (1u << lowbits) - 1u);
-    if (lowbits < nbits)
-        d |= (((bucket_of(key, k, D) - d0) >> hshift) << lowbits) & ((1u << nbits) - 1u);
-    return d;
+__device__ __forceinline__ K group_base(uint32_t d0, int SB);
+template <>
+__device__ __forceinline__ uint64_t group_base<uint64_t>(uint32_t d0, int SB) {
+    return SB < 64 ? (uint64_t)d0 << SB : 0ull;  // SB <= 62 for one-word keys
+}
+template <>
+__device__ __forceinline__ Key2 group_base<Key2>(uint32_t d0, int SB) {
+    if (SB >= 64)
+        return Key2{(uint64_t)d0 << (SB - 64), 0ull};
+    if (SB == 0)
+        return Key2{0ull, (uint64_t)d0};
+    return Key2{(uint64_t)d0 >> (64 - SB), (uint64_t)d0 << SB};
+}
+__device__ __forceinline__ uint64_t key_sub(uint64_t a, uint64_t b) { return a - b; }
+__device__ __forceinline__ Key2 key_sub(const Key2 &a, const Key2 &b) {
+    return Key2{a.hi - b.hi - (a.lo < b.lo ? 1ull : 0ull), a.lo - b.lo};
+}
+
+// Bits [shift, shift + nbits) of V, nbits <= 12.
+template <typename K>
+__device__ __forceinline__ uint32_t vdigit(const K &key, int shift, int nbits, const K &vbase) {
+    return digit_of(key_sub(key, vbase), shift, (1u << nbits) - 1u);
 }
 
 // Start and size of bin d of the MSD pass (starts packed two per word).
@@ -161,10 +176,12 @@ __device__ __forceinline__ Key2 shift_up_lane(const Key2 &x) { return Key2{shift
 // Number of lanes whose flag is set in a ballot.
 __device__ __forceinline__ uint32_t wave_count(uint64_t ball) { return (uint32_t)__popcll(ball); }
 
-template <typename K>
+// TBITS: log2 of the pattern table entries when fixed at compile time (the
+// default table: the pattern fields of the hash become constant shifts), or
+// 0 to take it from the arguments.
+template <typename K, int TBITS>
 // Two workgroups per CU (LDS < 80 KB each) hide more latency than the
-// registers saved by running one: the kernel is bound by LDS and ballot
-// latency, not by issue rate.
+// registers saved by running one.
 __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void bucket_kernel(BucketArgs a) {
     constexpr int ITEMS = BkItems<K>::value;
     constexpr int CAP = BK_THREADS * ITEMS;
@@ -198,7 +215,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     const int tid0 = threadIdx.x;
     const K *__restrict__ keys = static_cast<const K *>(a.keys);
     K *__restrict__ gap_keys = static_cast<K *>(a.gap_keys);
-    const uint32_t n_tab = 1u << a.table_bits;
+    const int tbits = TBITS ? TBITS : (int)a.table_bits;
+    const uint32_t n_tab = 1u << tbits;
     const uint32_t tmask = n_tab - 1;
     for (uint32_t i = tid0; i < n_tab; i += BK_THREADS)
         s_table[i] = a.table[i];
@@ -304,6 +322,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                 s_b[2] = bucket_of(key[i], a.k, D);
         __syncthreads();
         const uint32_t d0 = s_b[0];
+        const K vbase = group_base<K>(d0, SB);
         // does the last loaded bucket continue past the loaded keys?
         const bool incomplete = s_b[1] == s_b[2];
         uint32_t rb[ITEMS];  // bucket index within the group
@@ -430,7 +449,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                     uint64_t *b = s_filter + f0 + (uint32_t)__umul64hi(h, nb);
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
-                        const uint64_t m = s_table[(h >> (w * a.table_bits)) & tmask];
+                        const uint64_t m = s_table[(h >> (w * tbits)) & tmask];
                         const uint64_t old =
                             atomicOr((unsigned long long *)(b + w * blocks_cut), (unsigned long long)m);
                         if (old & m)
@@ -448,7 +467,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                     bool all = true;
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
-                        const uint64_t m = s_table[(h >> (w * a.table_bits)) & tmask];
+                        const uint64_t m = s_table[(h >> (w * tbits)) & tmask];
                         all &= (b[w * blocks_cut] & m) == m;
                     }
                     sv |= (uint32_t)all << i;
@@ -487,7 +506,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         for (int i = 0; i < ITEMS; i++) {
             rd[i] = 0;
             if (i < n_items && ((sv >> i) & 1u)) {
-                const uint32_t d = vdigit(key[i], mshift, MB, SB, a.k, D, d0);
+                const uint32_t d = vdigit(key[i], mshift, MB, vbase);
                 const uint32_t sh = (d & 1u) * 16u;
                 const uint32_t old = atomicAdd(&s_c32[d >> 1], 1u << sh);
                 rd[i] = (((old >> sh) & 0xFFFFu) << BK_MSD_BITS) | d;
@@ -524,8 +543,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             if (i < n_ch && e > 0 && e < n_surv) {
                 const K x = s_ex[e], y = s_ex[e - 1];
                 if (x != y) {
-                    const uint32_t dx = vdigit(x, mshift, MB, SB, a.k, D, d0);
-                    if (dx == vdigit(y, mshift, MB, SB, a.k, D, d0))
+                    const uint32_t dx = vdigit(x, mshift, MB, vbase);
+                    if (dx == vdigit(y, mshift, MB, vbase))
                         atomicOr(&s_mix[dx >> 5], 1u << (dx & 31u));
                 }
             }
@@ -666,7 +685,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                     const uint32_t e = (uint32_t)i * BK_THREADS + tid;
                     bool f = false;
                     if (e < n_surv) {
-                        const uint32_t d = vdigit(s_ex[e], mshift, MB, SB, a.k, D, d0);
+                        const uint32_t d = vdigit(s_ex[e], mshift, MB, vbase);
                         f = (s_mix[d >> 5] >> (d & 31u)) & 1u;
                     }
                     fm |= (uint32_t)f << i;
@@ -727,7 +746,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                         for (int j = 0; j < IL; j++) {
                             const int i = i0 + j;
                             act[j] = i < ITEMS && ((sv >> i) & 1u);
-                            dg[j] = act[j] ? vdigit(key[i], shift, BK_SORT_BITS, SB, a.k, D, d0) : 0u;
+                            dg[j] = act[j] ? vdigit(key[i], shift, BK_SORT_BITS, vbase) : 0u;
                             peers[j] = __ballot(act[j]);
                         }
 #pragma unroll
@@ -1089,10 +1108,18 @@ int bucket_capacity(int key_words) {
 }
 
 hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream) {
-    if (key_words == 2)
-        bucket_kernel<Key2><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
-    else
-        bucket_kernel<uint64_t><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
+    const bool fixed = a.table_bits == BK_TABLE_BITS;
+    if (key_words == 2) {
+        if (fixed)
+            bucket_kernel<Key2, BK_TABLE_BITS><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
+        else
+            bucket_kernel<Key2, 0><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
+    } else {
+        if (fixed)
+            bucket_kernel<uint64_t, BK_TABLE_BITS><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
+        else
+            bucket_kernel<uint64_t, 0><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
+    }
     return hipGetLastError();
 }
 
