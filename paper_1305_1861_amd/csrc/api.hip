@@ -174,7 +174,8 @@ struct Plan {
     size_t off_ctr, off_table, off_packed, off_valid, off_starts, off_filter;
     size_t off_keys_a, off_keys_b, off_counts, off_sort, off_compact;
     size_t off_gapc, off_f, off_part, off_rec_start, off_rec_nout, off_rec_off, off_rec_scan;
-    size_t off_fb_list, off_fb_ent, off_fbc, off_misc, total;
+    size_t off_fb_list, off_fb_ent, off_fbc, off_misc, off_chunks, total;
+    uint32_t n_chunks = 0;
     size_t off_libs, off_lib_keys, off_lib_stats, off_lib_ctr, off_lib_first;
     size_t sort_bytes, compact_bytes;
 };
@@ -184,6 +185,8 @@ struct Misc {
     uint32_t fb_count;
     uint32_t totals[3];  // [1] records out
     DevCounters fb_ctr;
+    uint32_t chunk_next;  // bucket kernel: next chunk to take
+    uint32_t pad[3];
 };
 
 // Plan of one call over n_libs libraries: library j owns reads
@@ -286,6 +289,10 @@ tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *
         p->fb_cap = p->cap / ((uint64_t)bucket_capacity(p->key_words) + 1) + 1;
         p->fb_nb_max = p->screen ? ceil_div((uint64_t)p->opts.beta * std::max<uint64_t>(p->cap, 1), 256) + p->fb_cap : 0;
         p->part_words = partition_scratch_words(p->part, p->key_words);
+        // chunks of the bucket kernel's schedule: about 64K keys each, at
+        // most 16K of them, at least one per workgroup
+        p->n_chunks = (uint32_t)std::min<uint64_t>(16384, std::max<uint64_t>((uint64_t)bucket_grid(),
+                                                                              ceil_div(p->cap, 65536)));
     }
     p->sort_bytes = radix_scratch_bytes(p->cap, p->key_words);
     p->compact_bytes = compact_scratch_bytes(p->cap);
@@ -320,6 +327,7 @@ tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *
         p->off_fb_ent = take(p->fb_cap * sizeof(FbEntry));
         p->off_fbc = take(p->cap * sizeof(uint32_t));
         p->off_misc = take(sizeof(Misc));
+        p->off_chunks = take(((size_t)p->n_chunks + 1) * sizeof(uint32_t));
         p->off_libs = take(n_libs * sizeof(LibDesc));
         p->off_lib_keys = take((n_libs + 1) * sizeof(uint32_t));
         p->off_lib_stats = take(n_libs * 4 * sizeof(unsigned long long));
@@ -607,6 +615,9 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
     ba.fb_list = fb_list;
     ba.fb_count = &misc->fb_count;
     ba.fb_cap = (uint32_t)p.fb_cap;
+    ba.n_chunks = p.n_chunks;
+    ba.chunk_bounds = reinterpret_cast<uint32_t *>(ws + p.off_chunks);
+    ba.chunk_next = &misc->chunk_next;
     TK_HIP(launch_bucket(ba, kw, grid, s));
     if ((st = tm.end(TK_STAGE_BUCKET, s)) != TK_OK)
         return st;

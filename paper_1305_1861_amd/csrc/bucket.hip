@@ -204,6 +204,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     __shared__ uint32_t s_w[2][BK_WAVES];
     __shared__ unsigned long long s_pos[2];
     __shared__ uint32_t s_u[4];
+    __shared__ uint32_t s_chunk;
     // statistics accumulated over the workgroup's groups: per wave (false
     // positives, counts in [2, c), runs) and per workgroup (survivors); every
     // sum is below the number of windows, hence below 2^32
@@ -225,16 +226,13 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     if (tid0 == 0)
         s_tot[0] = 0;
 
-    const uint64_t G = gridDim.x, g = blockIdx.x;
-    const uint64_t n = a.lib_keys[a.n_libs];
-    if (tid0 == 0) {
-        s_pos[0] = group_start(a, keys, n * g / G);
-        s_pos[1] = group_start(a, keys, n * (g + 1) / G);
-    }
     __syncthreads();
-    uint64_t pos = s_pos[0];
-    const uint64_t end = s_pos[1];
-    uint32_t jl = library_of(a, pos);  // library of the groups being processed
+    // Chunks of the key array (whole groups; bounds precomputed) are taken
+    // from a counter: a group's cost is not proportional to its keys (small
+    // groups of large buckets pay the same per-group overhead), so equal key
+    // ranges per workgroup would finish unevenly.
+    uint64_t pos = 0, end = 0;
+    uint32_t jl = 0;  // library of the groups being processed (0: nothing gathered yet)
     // statistics of library jl gathered so far go to its counters (thread 0;
     // the counters it reads were written before a barrier)
     auto flush_stats = [&](uint32_t j) {
@@ -271,6 +269,16 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         if (t == 0 && p + nl < le)
             beyond = keys[p + nl];
     };
+    for (;;) {
+    if (tid0 == 0)
+        s_chunk = atomicAdd(a.chunk_next, 1u);
+    __syncthreads();
+    const uint32_t chunk = s_chunk;
+    __syncthreads();  // s_chunk is rewritten only after every thread has read it
+    if (chunk >= a.n_chunks)
+        break;
+    pos = a.chunk_bounds[chunk];
+    end = a.chunk_bounds[chunk + 1];
     load_group(pos, tid0);
 
     while (pos < end) {
@@ -927,6 +935,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         pos += n_sb;
         __syncthreads();  // shared buffers are reused by the next group
     }
+    }
     // statistics of the last library of this workgroup
     __syncthreads();
     if (tid0 == 0)
@@ -1099,6 +1108,17 @@ __global__ __launch_bounds__(256) void lib_stats_kernel(const LibDesc *__restric
     out_first[j] = first;
 }
 
+// Bounds of the bucket kernel's chunks: chunk c covers the keys from the
+// first group start at or after n * c / C to the next such start.
+template <typename K>
+__global__ __launch_bounds__(256) void chunk_bounds_kernel(BucketArgs a, uint32_t C, uint32_t *__restrict__ bounds) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > C)
+        return;
+    const uint64_t n = a.lib_keys[a.n_libs];
+    bounds[c] = (uint32_t)group_start(a, static_cast<const K *>(a.keys), n * c / C);
+}
+
 }  // namespace
 
 int bucket_grid() { return device_cu_count() * 2; }
@@ -1108,6 +1128,17 @@ int bucket_capacity(int key_words) {
 }
 
 hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream) {
+    // a.chunk_bounds (n_chunks + 1 words, written here) and *a.chunk_next
+    // (zero on entry) belong to the caller's workspace
+    const unsigned cg = (unsigned)((a.n_chunks + 1 + 255) / 256);
+    uint32_t *bounds = const_cast<uint32_t *>(a.chunk_bounds);
+    if (key_words == 2)
+        chunk_bounds_kernel<Key2><<<dim3(cg), dim3(256), 0, stream>>>(a, a.n_chunks, bounds);
+    else
+        chunk_bounds_kernel<uint64_t><<<dim3(cg), dim3(256), 0, stream>>>(a, a.n_chunks, bounds);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
     const bool fixed = a.table_bits == BK_TABLE_BITS;
     if (key_words == 2) {
         if (fixed)

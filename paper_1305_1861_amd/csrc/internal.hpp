@@ -111,6 +111,9 @@ struct BucketArgs {
     uint32_t *fb_list;     // oversized buckets: (bucket id, start, size)
     uint32_t *fb_count;
     uint32_t fb_cap;
+    uint32_t n_chunks;            // chunks of the dynamic schedule
+    const uint32_t *chunk_bounds; // n_chunks + 1 key positions (filled by launch_bucket)
+    uint32_t *chunk_next;         // chunk counter, zero before the launch
 };
 int bucket_grid();
 int bucket_capacity(int key_words);
