@@ -176,11 +176,78 @@ __device__ __forceinline__ Key2 window_key2(const uint64_t *__restrict__ packed,
     return window_key2(packed[w], w ? packed[w - 1] : 0, w > 1 ? packed[w - 2] : 0, t, k);
 }
 
+// Rolling extraction along the consecutive windows of one packed word: the
+// window ending at base t + 1 is the one ending at t with the base of t + 1
+// appended (forward: shift left, new code at the bottom; reverse complement:
+// shift right, complemented code at the top).  init() takes the window
+// ending at t as above; key() equals window_key1/2 for every window reached.
+struct Roll1 {
+    uint64_t fwd, rc, mask;
+    int top;  // 2k - 2: bit of the first base of the reverse complement
+    __device__ __forceinline__ void init(uint64_t w0, uint64_t w1, uint64_t, uint32_t t, int k) {
+        const uint32_t s = 62 - 2 * t;
+        const uint64_t cat = s ? (w0 >> s) | (w1 << (64 - s)) : w0;
+        mask = (1ull << (2 * k)) - 1;
+        fwd = cat & mask;
+        rc = ~group_reverse(fwd) >> (64 - 2 * k);
+        top = 2 * k - 2;
+    }
+    __device__ __forceinline__ void step(uint32_t b) {
+        fwd = ((fwd << 2) | b) & mask;
+        rc = (rc >> 2) | ((uint64_t)(3u - b) << top);
+    }
+    __device__ __forceinline__ uint64_t key() const { return fwd < rc ? fwd : rc; }
+};
+
+struct Roll2 {
+    uint64_t hi, lo, rhi, rlo, hmask;
+    int top;  // 2k - 2
+    __device__ __forceinline__ void init(uint64_t w0, uint64_t w1, uint64_t w2, uint32_t t, int k) {
+        const uint32_t s = 62 - 2 * t;
+        if (s) {
+            lo = (w0 >> s) | (w1 << (64 - s));
+            hi = (w1 >> s) | (w2 << (64 - s));
+        } else {
+            lo = w0;
+            hi = w1;
+        }
+        hmask = (1ull << (2 * k - 64)) - 1;
+        hi &= hmask;
+        const uint64_t a_hi = ~group_reverse(lo);
+        const uint64_t a_lo = ~group_reverse(hi);
+        const int sh = 128 - 2 * k;  // 2..64
+        if (sh == 64) {
+            rlo = a_hi;
+            rhi = 0;
+        } else {
+            rlo = (a_lo >> sh) | (a_hi << (64 - sh));
+            rhi = a_hi >> sh;
+        }
+        top = 2 * k - 2;
+    }
+    __device__ __forceinline__ void step(uint32_t b) {
+        hi = ((hi << 2) | (lo >> 62)) & hmask;
+        lo = (lo << 2) | b;
+        const uint64_t c = 3u - b;
+        rlo = (rlo >> 2) | (rhi << 62);
+        rhi >>= 2;
+        if (top >= 64)
+            rhi |= c << (top - 64);
+        else
+            rlo |= c << top;  // k = 32
+    }
+    __device__ __forceinline__ Key2 key() const {
+        const bool fwd_smaller = hi < rhi || (hi == rhi && lo <= rlo);
+        return fwd_smaller ? Key2{hi, lo} : Key2{rhi, rlo};
+    }
+};
+
 template <bool TWO>
 struct KeyOf;
 template <>
 struct KeyOf<false> {
     using type = uint64_t;
+    using Roll = Roll1;
     __device__ __forceinline__ static uint64_t get(const uint64_t *packed, uint64_t w, uint32_t t, int k) {
         return window_key1(packed, w, t, k);
     }
@@ -191,6 +258,7 @@ struct KeyOf<false> {
 template <>
 struct KeyOf<true> {
     using type = Key2;
+    using Roll = Roll2;
     __device__ __forceinline__ static Key2 get(const uint64_t *packed, uint64_t w, uint32_t t, int k) {
         return window_key2(packed, w, t, k);
     }

@@ -152,10 +152,16 @@ __device__ __forceinline__ uint32_t load_tile(const PassArgs &a, uint64_t t0, ui
                 ok &= ~0u << (uint32_t)(lo - p0);  // lo - p0 < ITEMS
             if (p0 + ITEMS > t1)
                 ok &= (1u << (uint32_t)(t1 - p0)) - 1u;  // t1 - p0 < ITEMS
+            // consecutive windows: the first extracted whole, the others
+            // rolled on by one base each
+            typename KeyOf<std::is_same<K, Key2>::value>::Roll r;
+            r.init(w0, w1, w2, first, a.k);
 #pragma unroll
             for (int i = 0; i < ITEMS; i++) {
+                if (i)
+                    r.step((uint32_t)(w0 >> (62 - 2 * (first + i))) & 3u);
                 if ((ok >> i) & 1u) {
-                    key[i] = KeyOf<std::is_same<K, Key2>::value>::get(w0, w1, w2, first + i, a.k);
+                    key[i] = r.key();
                     vm |= 1u << i;
                 }
             }
