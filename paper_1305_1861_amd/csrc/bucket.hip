@@ -449,26 +449,39 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             for (uint32_t i = tid; i < blocks_cut * 8; i += BK_THREADS)
                 s_filter[i] = 0;
             __syncthreads();
+            // Bits are only ever set, and a second-plane bit implies its
+            // first-plane bit, so a word whose pattern bits are all in the
+            // second plane already needs no update: one read replaces both
+            // atomics (on deep libraries, for most sightings).  A sighting
+            // that finds all its bits set in either plane sets them all in
+            // the second plane, so its key is a candidate whatever comes
+            // later: it is marked now and skips the collect test.
 #pragma unroll
             for (int i = 0; i < ITEMS; i++) {
                 if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb) {
                     const uint32_t f0 = s_fo[rb[i]], nb = (uint32_t)s_fo[rb[i] + 1] - f0;
                     const uint64_t h = key_hash(key[i]);
                     uint64_t *b = s_filter + f0 + (uint32_t)__umul64hi(h, nb);
+                    bool seen = true;
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
                         const uint64_t m = s_table[(h >> (w * tbits)) & tmask];
-                        const uint64_t old =
-                            atomicOr((unsigned long long *)(b + w * blocks_cut), (unsigned long long)m);
-                        if (old & m)
-                            atomicOr((unsigned long long *)(b + (4 + w) * blocks_cut), (unsigned long long)(old & m));
+                        if ((b[(4 + w) * blocks_cut] & m) != m) {
+                            const uint64_t old =
+                                atomicOr((unsigned long long *)(b + w * blocks_cut), (unsigned long long)m);
+                            if (old & m)
+                                atomicOr((unsigned long long *)(b + (4 + w) * blocks_cut),
+                                         (unsigned long long)(old & m));
+                            seen &= (old & m) == m;
+                        }
                     }
+                    sv |= (uint32_t)seen << i;
                 }
             }
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < ITEMS; i++) {
-                if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb) {
+                if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb && !((sv >> i) & 1u)) {
                     const uint32_t f0 = s_fo[rb[i]], nb = (uint32_t)s_fo[rb[i] + 1] - f0;
                     const uint64_t h = key_hash(key[i]);
                     const uint64_t *b = s_filter + f0 + (uint32_t)__umul64hi(h, nb) + 4 * blocks_cut;
