@@ -279,7 +279,13 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         break;
     pos = a.chunk_bounds[chunk];
     end = a.chunk_bounds[chunk + 1];
-    load_group(pos, tid0);
+    {
+        // (thread index laundered as in the group loop below, so that the
+        // compiler does not hoist per-item addresses out of the chunk loop)
+        int tidc = tid0;
+        asm volatile("" : "+v"(tidc));
+        load_group(pos, tidc);
+    }
 
     while (pos < end) {
         // Thread indices are passed through an empty asm each iteration so
