@@ -450,6 +450,8 @@ def main() -> int:
     ap.add_argument("--shards", type=int, default=1,
                     help="time every key-range shard of the workload in turn (the share of one of this many "
                          "devices) and check that their results concatenate to the unsharded one")
+    ap.add_argument("--no-end-to-end", action="store_true",
+                    help="skip the end-to-end run from host buffers (reported beside the timed value)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain "
                          "device copy kernel (reference for HBM byte counters)")
@@ -560,6 +562,18 @@ def main() -> int:
             "algorithmic_bytes": int(model[dominant]), "launch_ms": stage_ms[dominant],
         },
     }
+    if not args.no_end_to_end:
+        # host buffers in, host result out (tk_count: device allocation, both
+        # PCIe copies and the same kernels); reported beside, never as value
+        del ws, r
+        torch.cuda.empty_cache()
+        tk.tk_count(lib.bases, lib.offsets, lib.k, lib.c)
+        t = time.perf_counter()
+        e2e = tk.tk_count(lib.bases, lib.offsets, lib.k, lib.c)
+        e2e_s = time.perf_counter() - t
+        out["end_to_end"] = {"ms": 1e3 * e2e_s, "windows_per_s": e2e.n_windows / e2e_s,
+                             "what": "tk_count on pageable host buffers: workspace allocation, copy of the "
+                                     "reads to the device, the timed path, copy of the records back"}
     if args.calibrate_copy_mib:
         src = torch.ones(args.calibrate_copy_mib << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
