@@ -450,6 +450,8 @@ def main() -> int:
     ap.add_argument("--shards", type=int, default=1,
                     help="time every key-range shard of the workload in turn (the share of one of this many "
                          "devices) and check that their results concatenate to the unsharded one")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time bucket bits and filter bits per window around the size rule; print the fastest")
     ap.add_argument("--no-end-to-end", action="store_true",
                     help="skip the end-to-end run from host buffers (reported beside the timed value)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -482,6 +484,17 @@ def main() -> int:
         return bench_approx(args, tk, readsim, torch, np, dev)
     if args.shards > 1:
         return bench_shards(args, tk, readsim, torch, np, dev)
+    if args.autotune:
+        from paper_1305_1861_amd.tune import autotune
+        lib = readsim.WORKLOADS[args.workload]()
+        bases = torch.from_numpy(lib.bases).to(dev)
+        offsets = torch.from_numpy(lib.offsets.view(np.int64)).to(dev)
+        t = autotune(bases, offsets, lib.k, lib.c, repeats=max(1, args.steps))
+        print(json.dumps({"workload": lib.name, "best": {"part_bits": t.part_bits, "bloom_beta": t.bloom_beta,
+                                                          "ms": t.ms},
+                          "timings": [{"part_bits": d, "bloom_beta": be, "ms": ms, "n_fallback": nf}
+                                      for d, be, ms, nf in t.timings], "host": platform.node()}), flush=True)
+        return 0
 
     t0 = time.perf_counter()
     lib = readsim.WORKLOADS[args.workload]()
