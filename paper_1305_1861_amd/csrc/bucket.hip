@@ -53,54 +53,15 @@ __device__ __forceinline__ uint32_t bucket_of(const K &key, int k, int D) {
     return digit_of(key, 2 * k - D, (1u << D) - 1u);
 }
 
-// Library holding key index p: the largest j with lib_keys[j] <= p (the
-// last library for p past the keys).
-__device__ __forceinline__ uint32_t library_of(const BucketArgs &a, uint64_t p) {
+// Library of bucket id b: the largest j with libs[j].bucket0 <= b.
+__device__ __forceinline__ uint32_t library_of_bucket(const BucketArgs &a, uint32_t b) {
     uint32_t lo = 0, hi = a.n_libs;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) / 2;
-        if (a.lib_keys[mid] <= p)
+        if (a.libs[mid].bucket0 <= b)
             lo = mid;
         else
             hi = mid;
-    }
-    return lo;
-}
-
-// First group start at or after p: p itself at a library's first key, else
-// the first index in [p, end of the library) whose bucket is greater than
-// the bucket of key p-1 (buckets are non-decreasing inside a library).
-template <typename K>
-__device__ uint64_t group_start(const BucketArgs &a, const K *__restrict__ keys, uint64_t p) {
-    const uint64_t n = a.lib_keys[a.n_libs];
-    if (p == 0 || p >= n)
-        return p < n ? p : n;
-    const uint32_t j = library_of(a, p);
-    if (p == a.lib_keys[j])
-        return p;
-    const int D = a.libs[j].D;
-    const uint32_t d = bucket_of(keys[p - 1], a.k, D);
-    uint64_t lo = p, hi = a.lib_keys[j + 1];
-    while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (bucket_of(keys[mid], a.k, D) > d)
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    return lo;
-}
-
-// End of bucket d starting at p: first index in [p, n) with bucket > d.
-template <typename K>
-__device__ uint64_t bucket_end(const K *__restrict__ keys, uint64_t n, uint64_t p, uint32_t d, int k, int D) {
-    uint64_t lo = p, hi = n;
-    while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (bucket_of(keys[mid], k, D) > d)
-            hi = mid;
-        else
-            lo = mid + 1;
     }
     return lo;
 }
@@ -198,11 +159,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     uint16_t *const s_start = s_aux;
     uint16_t *const s_fo = s_aux + BK_RMAX + 1;
     __shared__ uint32_t s_mix[BK_MSD_BINS / 32];  // mixed-bin flags of the MSD pass
-    __shared__ K s_xk[ITEMS][BK_WAVES];           // key of lane 63 of every (item, wave)
-    __shared__ uint32_t s_b[4];                   // bucket ids: first key, key past the group, last loaded, last kept
     __shared__ uint32_t s_part[ITEMS][BK_WAVES];
     __shared__ uint32_t s_w[2][BK_WAVES];
-    __shared__ unsigned long long s_pos[2];
     __shared__ uint32_t s_u[4];
     __shared__ uint32_t s_chunk;
     // statistics accumulated over the workgroup's groups: per wave (false
@@ -231,7 +189,6 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     // from a counter: a group's cost is not proportional to its keys (small
     // groups of large buckets pay the same per-group overhead), so equal key
     // ranges per workgroup would finish unevenly.
-    uint64_t pos = 0, end = 0;
     uint32_t jl = 0;  // library of the groups being processed (0: nothing gathered yet)
     // statistics of library jl gathered so far go to its counters (thread 0;
     // the counters it reads were written before a barrier)
@@ -249,25 +206,18 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         atomicAdd(o + 3, t[1]);
         s_tot[0] = 0;
     };
-    // keys of the group starting at p (item-major, sentinel past the group)
-    // and, in thread 0, the first key past it inside its library; every
+    // keys [p, p + n) of a group (item-major, sentinel past them); every
     // element is assigned so that no value is carried from one group to the
     // next
     K key[ITEMS];
-    K beyond = sentinel<K>();
-    auto load_group = [&](uint64_t p, int t) {
-        const uint64_t le = min(end, (uint64_t)a.lib_keys[library_of(a, p) + 1]);
-        const uint32_t nl = p < le ? (uint32_t)min<uint64_t>(CAP, le - p) : 0u;
+    auto load_group = [&](uint64_t p, uint32_t n, int t) {
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             const uint32_t e = (uint32_t)i * BK_THREADS + t;
             key[i] = sentinel<K>();
-            if (e < nl)
+            if (e < n)
                 key[i] = keys[p + e];
         }
-        beyond = sentinel<K>();
-        if (t == 0 && p + nl < le)
-            beyond = keys[p + nl];
     };
     for (;;) {
     if (tid0 == 0)
@@ -277,17 +227,23 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     __syncthreads();  // s_chunk is rewritten only after every thread has read it
     if (chunk >= a.n_chunks)
         break;
-    pos = a.chunk_bounds[chunk];
-    end = a.chunk_bounds[chunk + 1];
+    const uint32_t n_grp = a.grp_count[chunk];
+    const uint32_t gbase = chunk * a.chunk_buckets;
+    if (n_grp == 0)
+        continue;
+    // the chunk's first group: buckets [b0, b1], keys [pos, pos + n_sb)
+    uint32_t b0 = a.grp_first[gbase], b1 = a.grp_last[gbase];
+    uint64_t pos = a.bucket_starts[b0];
+    uint32_t n_sb = a.bucket_starts[b1 + 1] - (uint32_t)pos;
     {
         // (thread index laundered as in the group loop below, so that the
         // compiler does not hoist per-item addresses out of the chunk loop)
         int tidc = tid0;
         asm volatile("" : "+v"(tidc));
-        load_group(pos, tidc);
+        load_group(pos, n_sb, tidc);
     }
 
-    while (pos < end) {
+    for (uint32_t g = 0; g < n_grp; g++) {
         // Thread indices are passed through an empty asm each iteration so
         // the compiler recomputes what depends on them inside the loop
         // instead of keeping dozens of hoisted lane masks alive across it.
@@ -299,7 +255,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
 
         // ---- the group's library ----
         {
-            const uint32_t jn = library_of(a, pos);
+            const uint32_t jn = library_of_bucket(a, b0);
             if (jn != jl) {
                 if (tid == 0)
                     flush_stats(jl);
@@ -310,140 +266,46 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         const uint32_t c = a.libs[jl].c;       // its threshold
         const bool screen = c >= 2;
         const uint32_t bucket0 = a.libs[jl].bucket0;
-        const uint64_t lend = min(end, (uint64_t)a.lib_keys[jl + 1]);
         const int SB = 2 * a.k - D;  // key bits below the bucket digit
 
-        // ---- a group of whole buckets: up to CAP keys, loaded by the
-        // previous iteration (item-major) ----
-        const uint32_t n_load = (uint32_t)min<uint64_t>(CAP, lend - pos);
-        const int n_items = (int)((n_load + BK_THREADS - 1) / BK_THREADS);
-        // publish what other lanes need: lane 63's keys (the previous key of
-        // the next wave's lane 0), the first key's bucket, the buckets of the
-        // last loaded key and of the key past the group
-        if (lane == WAVE - 1) {
-#pragma unroll
-            for (int i = 0; i < ITEMS; i++)
-                if (i < n_items)
-                    s_xk[i][wave] = key[i];
-        }
-        if (tid == 0) {
-            s_b[0] = bucket_of(key[0], a.k, D);
-            s_b[1] = pos + n_load < lend ? bucket_of(beyond, a.k, D) : ~0u;
-        }
-#pragma unroll
-        for (int i = 0; i < ITEMS; i++)
-            if ((uint32_t)i * BK_THREADS + tid == n_load - 1)
-                s_b[2] = bucket_of(key[i], a.k, D);
-        __syncthreads();
-        const uint32_t d0 = s_b[0];
+        // ---- a group of whole buckets b0..b1 of one library (planned
+        // before the launch; keys loaded by the previous iteration) ----
+        const int n_items = (int)((n_sb + BK_THREADS - 1) / BK_THREADS);
+        const uint32_t d0 = b0 - bucket0;
+        const uint32_t R = b1 - b0 + 1;  // bucket ids spanned, <= BK_RMAX
         const K vbase = group_base<K>(d0, SB);
-        // does the last loaded bucket continue past the loaded keys?
-        const bool incomplete = s_b[1] == s_b[2];
-        uint32_t rb[ITEMS];  // bucket index within the group
-        uint32_t hm = 0;     // bit i: item i starts a bucket
+        // start of every bucket in the group, then its first filter block
+        for (uint32_t r = tid; r <= R; r += BK_THREADS)
+            s_start[r] = (uint16_t)(a.bucket_starts[b0 + r] - (uint32_t)pos);
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t carry = 0;
+            for (uint32_t r0 = 0; r0 < R; r0 += WAVE) {
+                const uint32_t r = r0 + lane;
+                uint32_t nb = 0;
+                if (r < R) {
+                    const uint32_t ns = (uint32_t)s_start[r + 1] - s_start[r];
+                    nb = (screen && ns) ? max(1u, (a.beta * ns + 255) / 256) : 0u;
+                }
+                const uint32_t inc = wave_inclusive_sum(nb);
+                if (r < R)
+                    s_fo[r] = (uint16_t)(carry + inc - nb);
+                carry += (uint32_t)__shfl(inc, WAVE - 1);
+            }
+            if (lane == 0)
+                s_fo[R] = (uint16_t)carry;
+        }
+        __syncthreads();
+        const uint32_t blocks_cut = s_fo[R];
+        uint32_t rb[ITEMS];  // bucket of each key, relative to b0
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             rb[i] = 0;
-            if (i < n_items) {
-                const uint32_t e = (uint32_t)i * BK_THREADS + tid;
-                // previous key: lane - 1 of this wave, or lane 63 of the
-                // previous wave (of the previous item for thread 0)
-                K prev = shift_up_lane(key[i]);
-                if (lane == 0 && e > 0)
-                    prev = wave > 0 ? s_xk[i][wave - 1] : s_xk[i > 0 ? i - 1 : 0][BK_WAVES - 1];
-                const bool head = e < n_load && (e == 0 || bucket_of(prev, a.k, D) != bucket_of(key[i], a.k, D));
-                hm |= (uint32_t)head << i;
-                const uint64_t hb = __ballot(head);
-                rb[i] = (uint32_t)__popcll(hb & lt) + (uint32_t)head;  // inclusive, within the wave
-                if (lane == 0)
-                    s_part[i][wave] = (uint32_t)__popcll(hb);
-            }
+            if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb)
+                rb[i] = bucket_of(key[i], a.k, D) - d0;
         }
-        __syncthreads();
-        if (tid < WAVE) {
-            // exclusive prefix of the head counts in (item, wave) order
-            const uint32_t tot = exclusive_parts(&s_part[0][0], n_items * BK_WAVES, tid);
-            if (tid == WAVE - 1)
-                s_u[0] = tot;  // number of buckets in the loaded keys
-        }
-        __syncthreads();
-        // buckets beyond the first BK_RMAX wait for the next group
-        const uint32_t R_all = s_u[0];
-        const uint32_t R = min(R_all, (uint32_t)BK_RMAX);
-#pragma unroll
-        for (int i = 0; i < ITEMS; i++) {
-            if (i < n_items) {
-                const uint32_t e = (uint32_t)i * BK_THREADS + tid;
-                rb[i] += s_part[i][wave];  // heads at positions <= e
-                if (e < n_load) {
-                    rb[i] -= 1;
-                    if (((hm >> i) & 1u) && rb[i] <= (uint32_t)BK_RMAX)
-                        s_start[rb[i]] = (uint16_t)e;
-                }
-            }
-        }
-        if (tid == 0 && R_all <= (uint32_t)BK_RMAX)
-            s_start[R] = (uint16_t)n_load;
-        __syncthreads();
-
-        // ---- per-bucket filter sizes, their offsets, and where the group ends ----
-        // thread t owns buckets [t * rpt, (t + 1) * rpt)
-        const uint32_t rpt = (R + BK_THREADS - 1) / BK_THREADS;
-        uint32_t nb_sum = 0;
-        for (uint32_t j = 0; j < rpt; j++) {
-            const uint32_t r = tid * rpt + j;
-            if (r < R) {
-                const uint32_t ns = (uint32_t)s_start[r + 1] - s_start[r];
-                nb_sum += screen ? max(1u, (a.beta * ns + 255) / 256) : 0u;
-            }
-        }
-        uint32_t nb_total;
-        uint32_t fo = block_exclusive_sum<BK_THREADS>(nb_sum, &nb_total);
-        uint32_t fits = 0;
-        for (uint32_t j = 0; j < rpt; j++) {
-            const uint32_t r = tid * rpt + j;
-            if (r < R) {
-                const uint32_t ns = (uint32_t)s_start[r + 1] - s_start[r];
-                const uint32_t nb = screen ? max(1u, (a.beta * ns + 255) / 256) : 0u;
-                s_fo[r] = (uint16_t)min(fo, 0xFFFFu);
-                const bool whole = !(incomplete && r + 1 == R_all);
-                fits += (whole && fo + nb <= FMAX) ? 1u : 0u;
-                fo += nb;
-            }
-        }
-        uint32_t r_cut;
-        block_exclusive_sum<BK_THREADS>(fits, &r_cut);
-        if (r_cut == 0) {
-            // the first bucket alone exceeds the registers: fallback path
-            if (tid == 0) {
-                const uint64_t e = bucket_end(keys, lend, pos + n_load, d0, a.k, D);
-                const uint64_t ns = e - pos;
-                s_pos[0] = e;
-                const uint32_t slot = atomicAdd(a.fb_count, 1u);
-                if (slot < a.fb_cap) {
-                    a.fb_list[3 * slot + 0] = bucket0 + d0;
-                    a.fb_list[3 * slot + 1] = (uint32_t)pos;
-                    a.fb_list[3 * slot + 2] = (uint32_t)ns;
-                }
-                a.rec_start[bucket0 + d0] = (uint32_t)pos;
-            }
-            __syncthreads();
-            pos = s_pos[0];
-            load_group(pos, tid);
-            __syncthreads();
-            continue;
-        }
-        const uint32_t n_sb = r_cut == R_all ? n_load : (uint32_t)s_start[r_cut];
-        const uint32_t blocks_cut = r_cut == R ? nb_total : (uint32_t)s_fo[r_cut];
-        if (tid == 0)
-            s_fo[r_cut] = (uint16_t)blocks_cut;
-#pragma unroll
-        for (int i = 0; i < ITEMS; i++)
-            if ((uint32_t)i * BK_THREADS + tid == n_sb - 1)
-                s_b[3] = bucket_of(key[i], a.k, D);
-        __syncthreads();
         // span of bucket ids in the group -> bits of the bucket part of the sort key
-        const uint32_t span = s_b[3] - d0;
+        const uint32_t span = R - 1;
         const int RB = span ? 32 - __clz(span) : 0;
 
         // ---- screen and collect, each bucket against its own filter ----
@@ -925,7 +787,15 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         }
         // the next group's keys are requested now, so that their latency
         // overlaps the record writes and the bookkeeping below
-        load_group(pos + n_sb, tid);
+        uint32_t nb0 = 0, nb1 = 0, n_next = 0;  // the chunk's next group
+        uint64_t p_next = 0;
+        if (g + 1 < n_grp) {
+            nb0 = a.grp_first[gbase + g + 1];
+            nb1 = a.grp_last[gbase + g + 1];
+            p_next = a.bucket_starts[nb0];
+            n_next = a.bucket_starts[nb1 + 1] - (uint32_t)p_next;
+        }
+        load_group(p_next, n_next, tid);
         uint32_t *gcnt = a.gap_counts + pos;
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
@@ -951,7 +821,10 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             a.rec_nout[bucket0 + d0] = n_kept;
             s_tot[0] += n_surv;
         }
-        pos += n_sb;
+        pos = p_next;
+        n_sb = n_next;
+        b0 = nb0;
+        b1 = nb1;
         __syncthreads();  // shared buffers are reused by the next group
     }
     }
@@ -1127,15 +1000,65 @@ __global__ __launch_bounds__(256) void lib_stats_kernel(const LibDesc *__restric
     out_first[j] = first;
 }
 
-// Bounds of the bucket kernel's chunks: chunk c covers the keys from the
-// first group start at or after n * c / C to the next such start.
+// The schedule's groups (one thread per chunk of chunk_buckets bucket ids):
+// greedy, in key order, a group takes whole non-empty buckets of one library
+// while its keys fit the registers (CAP), its filters the exchange buffer
+// (FMAX blocks) and its bucket ids span at most BK_RMAX.  A bucket too large
+// on its own goes to the fallback list instead (its records are filed under
+// it by the fallback kernels).  Groups never cross a chunk boundary.
 template <typename K>
-__global__ __launch_bounds__(256) void chunk_bounds_kernel(BucketArgs a, uint32_t C, uint32_t *__restrict__ bounds) {
+__global__ __launch_bounds__(256) void plan_groups(BucketArgs a) {
+    constexpr uint32_t CAP = BK_THREADS * BkItems<K>::value;
+    constexpr uint32_t FMAX = (uint32_t)((CAP + 2) * sizeof(K) / 64);
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > C)
+    if (c >= a.n_chunks)
         return;
-    const uint64_t n = a.lib_keys[a.n_libs];
-    bounds[c] = (uint32_t)group_start(a, static_cast<const K *>(a.keys), n * c / C);
+    const uint32_t b_lo = c * a.chunk_buckets;
+    const uint32_t b_hi = min(b_lo + a.chunk_buckets, a.n_buckets);
+    const uint32_t *bs = a.bucket_starts;
+    uint32_t j = library_of_bucket(a, b_lo);
+    uint32_t ng = 0;
+    for (uint32_t b = b_lo; b < b_hi;) {
+        while (j + 1 < a.n_libs && a.libs[j + 1].bucket0 <= b)
+            j++;
+        const uint32_t lib_end = j + 1 < a.n_libs ? a.libs[j + 1].bucket0 : a.n_buckets;
+        const bool screen = a.libs[j].c >= 2;
+        const uint32_t s0 = bs[b], ns = bs[b + 1] - s0;
+        if (ns == 0) {
+            b++;
+            continue;
+        }
+        const uint32_t nb = screen ? max(1u, (a.beta * ns + 255) / 256) : 0u;
+        if (ns > CAP || nb > FMAX) {
+            const uint32_t slot = atomicAdd(a.fb_count, 1u);
+            if (slot < a.fb_cap) {
+                a.fb_list[3 * slot + 0] = b;
+                a.fb_list[3 * slot + 1] = s0;
+                a.fb_list[3 * slot + 2] = ns;
+            }
+            a.rec_start[b] = s0;
+            b++;
+            continue;
+        }
+        uint32_t n_keys = ns, n_blocks = nb, last = b;
+        const uint32_t e_max = min(min(b_hi, lib_end), b + (uint32_t)BK_RMAX);
+        for (uint32_t e = b + 1; e < e_max; e++) {
+            const uint32_t ne = bs[e + 1] - bs[e];
+            if (ne == 0)
+                continue;
+            const uint32_t nbe = screen ? max(1u, (a.beta * ne + 255) / 256) : 0u;
+            if (n_keys + ne > CAP || n_blocks + nbe > FMAX)
+                break;
+            n_keys += ne;
+            n_blocks += nbe;
+            last = e;
+        }
+        a.grp_first[b_lo + ng] = b;
+        a.grp_last[b_lo + ng] = last;
+        ng++;
+        b = last + 1;
+    }
+    a.grp_count[c] = ng;
 }
 
 }  // namespace
@@ -1147,14 +1070,13 @@ int bucket_capacity(int key_words) {
 }
 
 hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream) {
-    // a.chunk_bounds (n_chunks + 1 words, written here) and *a.chunk_next
-    // (zero on entry) belong to the caller's workspace
-    const unsigned cg = (unsigned)((a.n_chunks + 1 + 255) / 256);
-    uint32_t *bounds = const_cast<uint32_t *>(a.chunk_bounds);
+    // the groups of every chunk (grp_* and *a.chunk_next, zero on entry,
+    // belong to the caller's workspace)
+    const unsigned cg = (unsigned)((a.n_chunks + 255) / 256);
     if (key_words == 2)
-        chunk_bounds_kernel<Key2><<<dim3(cg), dim3(256), 0, stream>>>(a, a.n_chunks, bounds);
+        plan_groups<Key2><<<dim3(cg), dim3(256), 0, stream>>>(a);
     else
-        chunk_bounds_kernel<uint64_t><<<dim3(cg), dim3(256), 0, stream>>>(a, a.n_chunks, bounds);
+        plan_groups<uint64_t><<<dim3(cg), dim3(256), 0, stream>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;

@@ -86,12 +86,14 @@ struct PartPlan {
     uint64_t cap;         // key capacity of tmp and out
     uint32_t shard_count; // key-range shards (one library): 1 = none
     uint32_t shard_index; // the shard whose keys are kept
+    uint32_t n_buckets;   // buckets of all libraries
 };
 size_t partition_scratch_words(const PartPlan &p, int key_words);
 // out receives the keys; lib_keys (device, n_libs + 1) the first key of
-// every library and the number of keys.
+// every library and the number of keys; bucket_starts (device,
+// n_buckets + 1) the first key of every bucket and the number of keys.
 hipError_t partition_keys(const PartPlan &p, int key_words, void *tmp, void *out, uint32_t *scratch,
-                          size_t scratch_words, uint32_t *lib_keys, hipStream_t stream);
+                          size_t scratch_words, uint32_t *lib_keys, uint32_t *bucket_starts, hipStream_t stream);
 
 // ---- bucket.hip -----------------------------------------------------------
 struct BucketArgs {
@@ -111,9 +113,16 @@ struct BucketArgs {
     uint32_t *fb_list;     // oversized buckets: (bucket id, start, size)
     uint32_t *fb_count;
     uint32_t fb_cap;
-    uint32_t n_chunks;            // chunks of the dynamic schedule
-    const uint32_t *chunk_bounds; // n_chunks + 1 key positions (filled by launch_bucket)
-    uint32_t *chunk_next;         // chunk counter, zero before the launch
+    // the schedule: chunk c holds the bucket ids [c * chunk_buckets,
+    // (c + 1) * chunk_buckets); launch_bucket cuts each chunk into groups of
+    // whole buckets (first and last non-empty bucket of group g at
+    // grp_first/grp_last[c * chunk_buckets + g], grp_count[c] groups) and
+    // lists the buckets too large for a group in fb_list
+    uint32_t n_buckets;
+    const uint32_t *bucket_starts;  // n_buckets + 1 key positions (from the partition)
+    uint32_t n_chunks, chunk_buckets;
+    uint32_t *grp_first, *grp_last, *grp_count;
+    uint32_t *chunk_next;           // chunk counter, zero before the launch
 };
 int bucket_grid();
 int bucket_capacity(int key_words);

@@ -404,9 +404,39 @@ __global__ __launch_bounds__(SEG_THREADS) void pt_segments(PassArgs a, const uin
     }
 }
 
+// First key of every bucket (global id b = bucket0 of its library + its top
+// D bits; entry n_buckets: the number of keys).  A bucket is digit d2 of
+// its library's segment s: after the second pass it starts where the scan
+// placed digit d2 of the segment's first chunk; a segment without keys, and
+// every segment of a library without a second digit, gives its own start.
+__global__ __launch_bounds__(256) void pt_bucket_starts(PassArgs a, const uint32_t *__restrict__ scan2, bool pass2,
+                                                        const uint32_t *__restrict__ total1p, uint32_t n_buckets,
+                                                        uint32_t *__restrict__ starts) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= n_buckets; t += stride) {
+        const uint32_t b = (uint32_t)t;
+        if (b == n_buckets) {
+            starts[b] = *total1p;
+            continue;
+        }
+        const uint32_t j = last_le(a.n_libs, b, [&](uint32_t i) { return (uint64_t)a.libs[i].bucket0; });
+        const LibDesc &L = a.libs[j];
+        const uint32_t d = b - L.bucket0;
+        const uint32_t sg = L.seg0 + (d >> L.D2);
+        const uint32_t d2 = d & ((1u << L.D2) - 1u);
+        uint32_t st = a.seg[sg];
+        if (pass2) {
+            const uint32_t nch = a.cb[sg + 1] - a.cb[sg];
+            if (nch)
+                st = scan2[a.eb[sg] + (uint64_t)d2 * nch];
+        }
+        starts[b] = st;
+    }
+}
+
 template <typename K>
 hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scratch, size_t scratch_words,
-                         uint32_t *lib_keys, hipStream_t stream) {
+                         uint32_t *lib_keys, uint32_t *bucket_starts, hipStream_t stream) {
     if (p.D2max < 0 || p.D2max > PT_MAX_BITS)
         return hipErrorInvalidValue;
     const uint64_t n1 = p.n_hist1;
@@ -466,8 +496,11 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
     pt_segments<K><<<dim3(sgrid), dim3(SEG_THREADS), 0, stream>>>(a, hist, n1, total1, seg, cb, eb, lib_keys);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    if (!p.D2max)
-        return hipSuccess;
+    const unsigned bgrid = (unsigned)std::min<uint64_t>(ceil_div((uint64_t)p.n_buckets + 1, 256), 8192);
+    if (!p.D2max) {
+        pt_bucket_starts<<<dim3(bgrid), dim3(256), 0, stream>>>(a, nullptr, false, total1, p.n_buckets, bucket_starts);
+        return hipGetLastError();
+    }
 
     // pass 2: tmp -> out, every segment by its library's next D2 bits
     if ((e = launch_exclusive_scan(cb, cb, p.nseg, sscan, cb + p.nseg, stream)) != hipSuccess ||
@@ -482,6 +515,9 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
     if ((e = launch_exclusive_scan(hist, hist, n2, hist + n2, total1 + 1, stream)) != hipSuccess)
         return e;
     pt_scatter<K, false><<<dim3((unsigned)grid2), block, 0, stream>>>(a, hist, static_cast<K *>(out));
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    pt_bucket_starts<<<dim3(bgrid), dim3(256), 0, stream>>>(a, hist, true, total1, p.n_buckets, bucket_starts);
     return hipGetLastError();
 }
 
@@ -498,9 +534,10 @@ size_t partition_scratch_words(const PartPlan &p, int key_words) {
 }
 
 hipError_t partition_keys(const PartPlan &p, int key_words, void *tmp, void *out, uint32_t *scratch,
-                          size_t scratch_words, uint32_t *lib_keys, hipStream_t stream) {
-    return key_words == 2 ? run_partition<Key2>(p, tmp, out, scratch, scratch_words, lib_keys, stream)
-                          : run_partition<uint64_t>(p, tmp, out, scratch, scratch_words, lib_keys, stream);
+                          size_t scratch_words, uint32_t *lib_keys, uint32_t *bucket_starts, hipStream_t stream) {
+    return key_words == 2
+               ? run_partition<Key2>(p, tmp, out, scratch, scratch_words, lib_keys, bucket_starts, stream)
+               : run_partition<uint64_t>(p, tmp, out, scratch, scratch_words, lib_keys, bucket_starts, stream);
 }
 
 }  // namespace tk
