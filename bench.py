@@ -26,13 +26,24 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_1305_1861_amd", "csrc")
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE; used
 # only while the kernel sources still hash to the recorded digest
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bucket_large-library.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large-library.json")
 STAGE_SOURCES = {
     "bucket": ["bucket.hip", "device.hpp", "internal.hpp"],
     "partition": ["partition.hip", "scan.hip", "device.hpp", "internal.hpp"],
     "pack": ["pack.hip", "device.hpp", "internal.hpp"],
     "gather": ["bucket.hip", "device.hpp", "internal.hpp"],
 }
+# kernels of each stage of the partitioned path (name prefixes in rocprofv3
+# records; the shared scan kernels are left out)
+STAGE_KERNELS = {
+    "pack": ["mark_read_starts", "pack_kernel"],
+    "partition": ["pt_hist", "pt_scatter", "pt_segments", "pt_bucket_starts"],
+    "bucket": ["plan_groups", "bucket_kernel"],
+    "gather": ["gather_kernel"],
+}
+# stages made of one main kernel: the roofline's "dominant kernel" is the
+# slowest of these (the partition is a sequence of radix passes)
+SINGLE_KERNEL_STAGES = ("bucket", "gather", "screen", "collect", "pack")
 
 WORKLOAD_INFO = {
     "phased": dict(library="the large library, streamed from host memory in chunks into a resident SAC"),
@@ -86,18 +97,67 @@ def sources_digest(stage: str) -> str:
 
 
 def measured_traffic(path: str, stage: str, workload: str):
-    """HBM bytes per launch of `stage` from a counter record, or None when the
-    record is missing, covers another stage or workload, or predates the
-    current kernel sources."""
+    """HBM bytes per launch of `stage` from the counter record, or None when
+    the record is missing, covers another workload or not this stage, or
+    predates the stage's current kernel sources."""
     if not path or not os.path.exists(path):
         return None, "no counter record"
     with open(path) as f:
         tr = json.load(f)
-    if tr.get("stage") != stage or tr.get("workload") != workload:
-        return None, f"counter record covers {tr.get('stage')} on {tr.get('workload')}"
-    if tr.get("sources_sha256") != sources_digest(stage):
+    if tr.get("workload") != workload:
+        return None, f"counter record covers {tr.get('workload')}"
+    st = tr.get("stages", {}).get(stage)
+    if st is None:
+        return None, f"counter record has no {stage} stage"
+    if st.get("sources_sha256") != sources_digest(stage):
         return None, "kernel sources changed since the counters were taken"
-    return tr.get("bytes"), tr.get("source", path)
+    return st.get("bytes"), tr.get("source", path)
+
+
+WORKLOAD_NAMES = {"small": "uniform-1Mbp-10x-L100-k31", "large": "repeats-50Mbp-30x-L100-k31",
+                  "long_k": "uniform-20Mbp-40x-L150-k63-N"}
+
+
+def record_traffic(fetch_csv: str, write_csv: str, copy_bytes: int, workload: str, source: str, out: str) -> dict:
+    """Per-stage HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE,
+    then WRITE_SIZE, in KiB per dispatch) of one bench step (--steps 1
+    --warmup 0) that ends with plain device copies of copy_bytes each
+    (--calibrate-copy-mib): each counter is scaled by what it reads for one
+    of those copies."""
+    import csv
+    import re
+    from collections import defaultdict
+
+    def per_kernel(path):
+        d = defaultdict(list)
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                name = re.sub(r"^void\s+", "", r["Kernel_Name"]).replace("tk::(anonymous namespace)::", "")
+                d[name].append(float(r["Counter_Value"]))
+        return d
+    fe, wr = per_kernel(fetch_csv), per_kernel(write_csv)
+    copies = [n for n in fe if "copyBuffer" in n]
+    if not copies:
+        raise SystemExit("no calibration copy in the counter records (run the step with --calibrate-copy-mib)")
+    cf = max(max(fe[n]) for n in copies)
+    cw = max(max(wr[n]) for n in copies)
+    fs, ws_ = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    rec = {"workload": workload, "source": source, "copy_bytes": copy_bytes, "copy_fetch_size_kib": cf,
+           "copy_write_size_kib": cw, "fetch_scale": fs, "write_scale": ws_, "stages": {}}
+    for stage, prefixes in STAGE_KERNELS.items():
+        names = sorted(n for n in fe if any(n.startswith(q) for q in prefixes))
+        if not names:
+            continue
+        f_kib = sum(fe[n][0] for n in names)
+        w_kib = sum(wr[n][0] for n in names if n in wr)
+        rd, wt = f_kib * 1024.0 * fs, w_kib * 1024.0 * ws_
+        rec["stages"][stage] = {"kernels": [n.split("(")[0] for n in names], "fetch_size_kib": round(f_kib, 3),
+                                "write_size_kib": round(w_kib, 3), "read_bytes": int(rd), "written_bytes": int(wt),
+                                "bytes": int(rd + wt), "sources_sha256": sources_digest(stage)}
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    return rec
 
 
 def cpu_baseline(lib, target_s: float = 12.0) -> dict:
@@ -450,6 +510,9 @@ def main() -> int:
     ap.add_argument("--shards", type=int, default=1,
                     help="time every key-range shard of the workload in turn (the share of one of this many "
                          "devices) and check that their results concatenate to the unsharded one")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="write the per-stage HBM byte record (--traffic) from two rocprofv3 --pmc counter "
+                         "files of one step of --workload run with --calibrate-copy-mib, then exit")
     ap.add_argument("--autotune", action="store_true",
                     help="time bucket bits and filter bits per window around the size rule; print the fastest")
     ap.add_argument("--no-end-to-end", action="store_true",
@@ -458,6 +521,13 @@ def main() -> int:
                     help="after the run, copy a buffer of this many MiB three times with a plain "
                          "device copy kernel (reference for HBM byte counters)")
     args = ap.parse_args()
+
+    if args.record_traffic:
+        rec = record_traffic(args.record_traffic[0], args.record_traffic[1], args.calibrate_copy_mib << 20,
+                             WORKLOAD_NAMES[args.workload], f"profiles/kernels_{args.workload}-library_per-bucket.md",
+                             args.traffic)
+        print(json.dumps({s: v["bytes"] for s, v in rec["stages"].items()}))
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -533,9 +603,17 @@ def main() -> int:
     key_bytes = 8 * r.key_words
     model = algorithmic_bytes(lib.n_bases, r.n_windows, r.n_collected, r.n, key_bytes, r.sort_passes,
                               lib.c >= 2, r.part_bits)
-    dominant = max(model, key=lambda s: stage_ms.get(s, 0.0))
+    single = [s for s in model if s in SINGLE_KERNEL_STAGES] or list(model)
+    dominant = max(single, key=lambda s: stage_ms.get(s, 0.0))
     achieved = model[dominant] / (stage_ms[dominant] * 1e-3) / 1e9
     traffic, traffic_src = measured_traffic(args.traffic, dominant, lib.name)
+    stages = {}
+    for st, b in model.items():
+        ms = stage_ms.get(st, 0.0)
+        ach = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        tr_b, _ = measured_traffic(args.traffic, st, lib.name)
+        stages[st] = {"ms": ms, "algorithmic_bytes": int(b), "achieved": ach, "frac": ach / HBM_PEAK_GBS,
+                      "traffic": tr_b}
     path_bytes = sum(model.values())
     step_s = ms_per_step * 1e-3
     out = {
@@ -574,6 +652,7 @@ def main() -> int:
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
             "algorithmic_bytes": int(model[dominant]), "launch_ms": stage_ms[dominant],
         },
+        "stages": stages,
     }
     if not args.no_end_to_end:
         # host buffers in, host result out (tk_count: device allocation, both
