@@ -343,15 +343,22 @@ def test_many_oversized_buckets(tk, oracle_lib, which, part_bits):
 
 
 def test_bucket_capacity_edges(tk, oracle_lib):
-    """Buckets of exactly the register capacity and one more."""
+    """One bucket (part_bits 0) of exactly the register capacity, one less
+    and one more: 512 threads x 14 one-word keys = 7168, x 7 two-word keys =
+    3584 windows.  A second read repeats the first third of the first, so
+    the bucket holds frequent and single k-mers."""
     rng = np.random.default_rng(77)
-    for n_windows in (7679, 7680, 7681, 3584, 3585):
-        for k in (31, 63):
-            L = n_windows + k - 1
-            read = "".join("ACGT"[x] for x in rng.integers(0, 4, L))
-            bases, offsets = readsim.from_strings([read, read[: L // 2]])
-            case(f"capacity edge windows={n_windows} k={k}")
-            check_against_oracle(tk, oracle_lib, bases, offsets, k, 2, opts=dict(part_bits=0))
+    for k, caps in ((31, (7167, 7168, 7169, 3584)), (63, (3583, 3584, 3585, 7168))):
+        for total in caps:
+            m = total // 3  # windows of the second read
+            L1 = total - m + k - 1
+            read = "".join("ACGT"[x] for x in rng.integers(0, 4, L1))
+            bases, offsets = readsim.from_strings([read, read[: m + k - 1]])
+            case(f"capacity edge windows={total} k={k}")
+            r = check_against_oracle(tk, oracle_lib, bases, offsets, k, 2, opts=dict(part_bits=0))
+            assert r.n_windows == total
+            cap = 7168 if k <= 31 else 3584
+            assert r.n_fallback == (1 if total > cap else 0), (total, r.n_fallback)
 
 
 # --------------------------------------------------------------------------
