@@ -129,52 +129,83 @@ __device__ __forceinline__ bool chunk_of(const PassArgs &a, Chunk &ch) {
 // windows of one packed word; positions outside [lo, t1) are skipped.
 // Pass 2: keys [t0, t1) of the pass-1 output, item-major.  Bit i of the
 // result: item i holds a key.
-template <typename K, bool FROM_WIN>
-__device__ __forceinline__ uint32_t load_tile(const PassArgs &a, uint64_t t0, uint64_t t1, uint64_t lo,
-                                              K (&key)[PtItems<K>::value]) {
+// Pass 1 in two steps, so that the loads of the next tile can be in flight
+// while this one is processed: fetch_win issues the loads of one thread's
+// packed words and validity bits, extract_win rolls the keys out of them.
+struct RawWin {
+    uint64_t w0, w1, w2;  // packed words w, w - 1, w - 2 (0 before the first)
+    uint32_t vword;       // valid[w]
+    uint32_t okmask;      // this thread's items inside [lo, t1)
+};
+
+template <typename K>
+__device__ __forceinline__ RawWin fetch_win(const PassArgs &a, uint64_t t0, uint64_t t1, uint64_t lo) {
     constexpr int ITEMS = PtItems<K>::value;
+    constexpr int PER_WORD = 32 / ITEMS;  // threads per packed word
     const int tid = threadIdx.x;
+    const uint64_t w = t0 / 32 + (uint64_t)(tid / PER_WORD);
+    const uint32_t first = (uint32_t)(tid % PER_WORD) * ITEMS;
+    const uint64_t p0 = w * 32 + first;  // position of item 0
+    RawWin r{0, 0, 0, 0, 0};
+    if (p0 < t1 && p0 + ITEMS > lo) {
+        r.w0 = a.packed[w];
+        r.w1 = w ? a.packed[w - 1] : 0;
+        r.w2 = (std::is_same<K, Key2>::value && w > 1) ? a.packed[w - 2] : 0;
+        r.vword = a.valid[w];
+        uint32_t ok = ITEMS == 32 ? ~0u : (1u << (ITEMS & 31)) - 1u;
+        if (p0 < lo)
+            ok &= ~0u << (uint32_t)(lo - p0);  // lo - p0 < ITEMS
+        if (p0 + ITEMS > t1)
+            ok &= (1u << (uint32_t)(t1 - p0)) - 1u;  // t1 - p0 < ITEMS
+        r.okmask = ok;
+    }
+    return r;
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t extract_win(const PassArgs &a, const RawWin &r, K (&key)[PtItems<K>::value]) {
+    constexpr int ITEMS = PtItems<K>::value;
+    constexpr int PER_WORD = 32 / ITEMS;
+    const uint32_t first = (uint32_t)(threadIdx.x % PER_WORD) * ITEMS;
     uint32_t vm = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; i++)
         key[i] = K{};
-    if (FROM_WIN) {
-        constexpr int PER_WORD = 32 / ITEMS;  // threads per packed word
-        const uint64_t w = t0 / 32 + (uint64_t)(tid / PER_WORD);
-        const uint32_t first = (uint32_t)(tid % PER_WORD) * ITEMS;
-        const uint64_t p0 = w * 32 + first;  // position of item 0
-        if (p0 < t1 && p0 + ITEMS > lo) {
-            const uint64_t w0 = a.packed[w];
-            const uint64_t w1 = w ? a.packed[w - 1] : 0;
-            const uint64_t w2 = (std::is_same<K, Key2>::value && w > 1) ? a.packed[w - 2] : 0;
-            uint32_t ok = (a.valid[w] >> first) & (ITEMS == 32 ? ~0u : (1u << (ITEMS & 31)) - 1u);
-            if (p0 < lo)
-                ok &= ~0u << (uint32_t)(lo - p0);  // lo - p0 < ITEMS
-            if (p0 + ITEMS > t1)
-                ok &= (1u << (uint32_t)(t1 - p0)) - 1u;  // t1 - p0 < ITEMS
-            // consecutive windows: the first extracted whole, the others
-            // rolled on by one base each
-            typename KeyOf<std::is_same<K, Key2>::value>::Roll r;
-            r.init(w0, w1, w2, first, a.k);
-#pragma unroll
-            for (int i = 0; i < ITEMS; i++) {
-                if (i)
-                    r.step((uint32_t)(w0 >> (62 - 2 * (first + i))) & 3u);
-                if ((ok >> i) & 1u) {
-                    key[i] = r.key();
-                    vm |= 1u << i;
-                }
-            }
-        }
-    } else {
-        const K *__restrict__ in = static_cast<const K *>(a.keys_in);
+    if (r.okmask) {
+        const uint32_t ok = (r.vword >> first) & r.okmask;
+        // consecutive windows: the first extracted whole, the others
+        // rolled on by one base each
+        typename KeyOf<std::is_same<K, Key2>::value>::Roll rl;
+        rl.init(r.w0, r.w1, r.w2, first, a.k);
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
-            const uint64_t e = t0 + (uint64_t)i * PT_THREADS + tid;
-            if (e < t1) {
-                key[i] = in[e];
+            if (i)
+                rl.step((uint32_t)(r.w0 >> (62 - 2 * (first + i))) & 3u);
+            if ((ok >> i) & 1u) {
+                key[i] = rl.key();
                 vm |= 1u << i;
             }
+        }
+    }
+    return vm;
+}
+
+template <typename K, bool FROM_WIN>
+__device__ __forceinline__ uint32_t load_tile(const PassArgs &a, uint64_t t0, uint64_t t1, uint64_t lo,
+                                              K (&key)[PtItems<K>::value]) {
+    constexpr int ITEMS = PtItems<K>::value;
+    if (FROM_WIN)
+        return extract_win<K>(a, fetch_win<K>(a, t0, t1, lo), key);
+    const int tid = threadIdx.x;
+    uint32_t vm = 0;
+    const K *__restrict__ in = static_cast<const K *>(a.keys_in);
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        key[i] = K{};
+        const uint64_t e = t0 + (uint64_t)i * PT_THREADS + tid;
+        if (e < t1) {
+            key[i] = in[e];
+            vm |= 1u << i;
         }
     }
     return vm;
@@ -192,13 +223,42 @@ __global__ __launch_bounds__(PT_THREADS) void pt_hist(PassArgs a, uint32_t *__re
     for (int d = tid; d < PT_MAX_BINS; d += PT_THREADS)
         s_h[d] = 0;
     __syncthreads();
-    for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += pt_tile<K>()) {
-        K key[ITEMS];
-        const uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + pt_tile<K>(), ch.c1), ch.lo, key);
+    if (FROM_WIN) {
+        // the next tile's words are requested before this tile's keys are
+        // rolled out and counted
+        RawWin cur = ch.c0 < ch.c1 ? fetch_win<K>(a, ch.c0, min(ch.c0 + pt_tile<K>(), ch.c1), ch.lo)
+                                   : RawWin{0, 0, 0, 0, 0};
+        for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += pt_tile<K>()) {
+            const uint64_t tn = t0 + pt_tile<K>();
+            RawWin nxt{0, 0, 0, 0, 0};
+            if (tn < ch.c1)
+                nxt = fetch_win<K>(a, tn, min(tn + pt_tile<K>(), ch.c1), ch.lo);
+            // each key is counted as it is rolled out (no key array held)
+            if (cur.okmask) {
+                constexpr int PER_WORD = 32 / ITEMS;
+                const uint32_t first = (uint32_t)(tid % PER_WORD) * ITEMS;
+                const uint32_t ok = (cur.vword >> first) & cur.okmask;
+                typename KeyOf<std::is_same<K, Key2>::value>::Roll rl;
+                rl.init(cur.w0, cur.w1, cur.w2, first, a.k);
 #pragma unroll
-        for (int i = 0; i < ITEMS; i++)
-            if ((vm >> i) & 1u)
-                atomicAdd(&s_h[digit_of(key[i], ch.shift, mask)], 1u);
+                for (int i = 0; i < ITEMS; i++) {
+                    if (i)
+                        rl.step((uint32_t)(cur.w0 >> (62 - 2 * (first + i))) & 3u);
+                    if ((ok >> i) & 1u)
+                        atomicAdd(&s_h[digit_of(rl.key(), ch.shift, mask)], 1u);
+                }
+            }
+            cur = nxt;
+        }
+    } else {
+        for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += pt_tile<K>()) {
+            K key[ITEMS];
+            const uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + pt_tile<K>(), ch.c1), ch.lo, key);
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++)
+                if ((vm >> i) & 1u)
+                    atomicAdd(&s_h[digit_of(key[i], ch.shift, mask)], 1u);
+        }
     }
     __syncthreads();
     for (uint32_t d = tid; d < bins; d += PT_THREADS)
