@@ -175,7 +175,6 @@ struct Plan {
     size_t off_keys_a, off_keys_b, off_counts, off_sort, off_compact;
     size_t off_gapc, off_f, off_part, off_rec_start, off_rec_nout, off_rec_off, off_rec_scan;
     size_t off_fb_list, off_fb_ent, off_fbc, off_misc, off_bstart, off_grp_first, off_grp_last, off_grp_count, total;
-    uint32_t n_chunks = 0, chunk_buckets = 0;
     size_t off_libs, off_lib_keys, off_lib_stats, off_lib_ctr, off_lib_first;
     size_t sort_bytes, compact_bytes;
 };
@@ -289,10 +288,6 @@ tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *
         p->fb_cap = p->cap / ((uint64_t)bucket_capacity(p->key_words) + 1) + 1;
         p->fb_nb_max = p->screen ? ceil_div((uint64_t)p->opts.beta * std::max<uint64_t>(p->cap, 1), 256) + p->fb_cap : 0;
         p->part_words = partition_scratch_words(p->part, p->key_words);
-        // chunks of the bucket kernel's schedule: 32 bucket ids each (about
-        // 64K keys under the size rule)
-        p->chunk_buckets = 32;
-        p->n_chunks = (uint32_t)std::max<uint64_t>(1, ceil_div(n_bk, p->chunk_buckets));
         p->part.n_buckets = (uint32_t)n_bk;
     }
     p->sort_bytes = radix_scratch_bytes(p->cap, p->key_words);
@@ -329,9 +324,12 @@ tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *
         p->off_fbc = take(p->cap * sizeof(uint32_t));
         p->off_misc = take(sizeof(Misc));
         p->off_bstart = take((p->n_buckets + 1) * sizeof(uint32_t));
-        p->off_grp_first = take((size_t)p->n_chunks * p->chunk_buckets * sizeof(uint32_t));
-        p->off_grp_last = take((size_t)p->n_chunks * p->chunk_buckets * sizeof(uint32_t));
-        p->off_grp_count = take((size_t)p->n_chunks * sizeof(uint32_t));
+        // the group plan for any chunk size up to BK_CHUNK_MAX bucket ids
+        // (chosen per call from the device): at most n_buckets groups and
+        // chunks
+        p->off_grp_first = take((p->n_buckets + BK_CHUNK_MAX) * sizeof(uint32_t));
+        p->off_grp_last = take((p->n_buckets + BK_CHUNK_MAX) * sizeof(uint32_t));
+        p->off_grp_count = take((p->n_buckets + 1) * sizeof(uint32_t));
         p->off_libs = take(n_libs * sizeof(LibDesc));
         p->off_lib_keys = take((n_libs + 1) * sizeof(uint32_t));
         p->off_lib_stats = take(n_libs * 4 * sizeof(unsigned long long));
@@ -622,8 +620,11 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
     ba.fb_cap = (uint32_t)p.fb_cap;
     ba.n_buckets = (uint32_t)p.n_buckets;
     ba.bucket_starts = bstart;
-    ba.n_chunks = p.n_chunks;
-    ba.chunk_buckets = p.chunk_buckets;
+    // chunks of BK_CHUNK_MAX bucket ids (about 64K keys under the size
+    // rule), fewer when that leaves under two chunks per workgroup
+    ba.chunk_buckets = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>(BK_CHUNK_MAX, p.n_buckets / (2 * (uint64_t)grid)));
+    ba.n_chunks = (uint32_t)std::max<uint64_t>(1, ceil_div(p.n_buckets, ba.chunk_buckets));
     ba.grp_first = reinterpret_cast<uint32_t *>(ws + p.off_grp_first);
     ba.grp_last = reinterpret_cast<uint32_t *>(ws + p.off_grp_last);
     ba.grp_count = reinterpret_cast<uint32_t *>(ws + p.off_grp_count);

@@ -125,6 +125,7 @@ struct BucketArgs {
     uint32_t *chunk_next;           // chunk counter, zero before the launch
 };
 int bucket_grid();
+constexpr uint32_t BK_CHUNK_MAX = 32;  // bucket ids per chunk of the bucket kernel's schedule
 int bucket_capacity(int key_words);
 hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream);
 // Oversized buckets (more keys than a workgroup holds) of one library, in
