@@ -714,6 +714,18 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             }
         }
 
+        // the next group's keys are requested now (the sorted keys are in
+        // s_ex), so that their latency overlaps the run-length pass, the
+        // record writes and the bookkeeping below
+        uint32_t nb0 = 0, nb1 = 0, n_next = 0;  // the chunk's next group
+        uint64_t p_next = 0;
+        if (g + 1 < n_grp) {
+            nb0 = a.grp_first[gbase + g + 1];
+            nb1 = a.grp_last[gbase + g + 1];
+            p_next = a.bucket_starts[nb0];
+            n_next = a.bucket_starts[nb1 + 1] - (uint32_t)p_next;
+        }
+        load_group(p_next, n_next, tid);
         // ---- run-length compaction of s_ex[0, n_surv) ----
         // positions in (wave, item, lane) order with n_it items per wave.  A
         // run's count is its tail position minus its head position plus one;
@@ -785,17 +797,6 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             kbase += w < wave ? s_w[0][w] : 0;
             n_kept += s_w[0][w];
         }
-        // the next group's keys are requested now, so that their latency
-        // overlaps the record writes and the bookkeeping below
-        uint32_t nb0 = 0, nb1 = 0, n_next = 0;  // the chunk's next group
-        uint64_t p_next = 0;
-        if (g + 1 < n_grp) {
-            nb0 = a.grp_first[gbase + g + 1];
-            nb1 = a.grp_last[gbase + g + 1];
-            p_next = a.bucket_starts[nb0];
-            n_next = a.bucket_starts[nb1 + 1] - (uint32_t)p_next;
-        }
-        load_group(p_next, n_next, tid);
         uint32_t *gcnt = a.gap_counts + pos;
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
