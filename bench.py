@@ -532,7 +532,8 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
-              "this build has no multi-GPU path.", file=sys.stderr)
+              "the library counts on one device (tk_options.shard_count/shard_index give one device's share "
+              "of a key-range split).", file=sys.stderr)
         return 2
 
     import numpy as np
