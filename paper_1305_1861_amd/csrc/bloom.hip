@@ -12,8 +12,9 @@
 // block gets entry (h >> (w * table_bits)) mod 2^table_bits.
 //
 // screen : for every valid window, old = atomicOr(S[w], m_w) and, for the
-//          bits that were already set, atomicOr(T[w], old & m_w).  A T bit
-//          is set iff its position was touched at least twice, in any order.
+//          bits that were already set, atomicOr(T[w], old & m_w), skipped for
+//          words whose bits are all in T already.  A T bit is set iff its
+//          position was touched at least twice, in any order.
 // collect: a window is a candidate iff all its pattern bits are set in T.
 //          Candidates are appended with one atomicAdd per wave (ballot +
 //          popcount for the lane offsets).  Every key seen at least twice is
@@ -52,16 +53,23 @@ __global__ __launch_bounds__(BLOOM_THREADS) void screen_kernel(BloomArgs a) {
         const uint64_t h = key_hash(key);
         const uint64_t blk = __umul64hi(h, a.n_blocks);
         uint64_t *b = a.filter + blk * 8;
-        uint64_t m[4], old[4];
+        uint64_t m[4];
 #pragma unroll
         for (int i = 0; i < 4; i++)
             m[i] = s_table[(h >> (i * a.table_bits)) & (n_tab - 1)];
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-            old[i] = __hip_atomic_fetch_or(b + i, m[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // Bits are only ever set and a T bit implies its S bit, so a word
+        // whose pattern bits are already all in T needs neither atomic: the
+        // T half of the block (the same cache line) is read first.  A stale
+        // read only costs atomics that change nothing.
+        const ulonglong2 *tp = reinterpret_cast<const ulonglong2 *>(b + 4);
+        const ulonglong2 t01 = tp[0], t23 = tp[1];
+        const uint64_t tw[4] = {t01.x, t01.y, t23.x, t23.y};
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            const uint64_t again = old[i] & m[i];
+            if ((tw[i] & m[i]) == m[i])
+                continue;
+            const uint64_t old = __hip_atomic_fetch_or(b + i, m[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t again = old & m[i];
             if (again)
                 __hip_atomic_fetch_or(b + 4 + i, again, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
