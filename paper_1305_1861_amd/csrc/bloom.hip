@@ -16,9 +16,9 @@
 //          words whose bits are all in T already.  A T bit is set iff its
 //          position was touched at least twice, in any order.
 // collect: a window is a candidate iff all its pattern bits are set in T.
-//          Candidates are appended with one atomicAdd per wave (ballot +
-//          popcount for the lane offsets).  Every key seen at least twice is
-//          a candidate.
+//          Candidates are staged per block in LDS (ballot + popcount for
+//          the lane offsets) and appended a buffer at a time with one
+//          atomicAdd.  Every key seen at least twice is a candidate.
 //
 // Threads map one-to-one onto base positions: position p = 32w + t is the
 // last base of the window handled by that lane.  A persistent grid strides
@@ -76,22 +76,50 @@ __global__ __launch_bounds__(BLOOM_THREADS) void screen_kernel(BloomArgs a) {
     }
 }
 
+// Candidates go to a per-block LDS buffer first; a full buffer (and the
+// rest at the end) is appended with one atomicAdd and copied out coalesced,
+// instead of one atomic on the single output counter per wave.
+constexpr int COLLECT_BUF = 2048;
+
 template <bool TWO, bool SCREEN>
 __global__ __launch_bounds__(BLOOM_THREADS) void collect_kernel(BloomArgs a, typename KeyOf<TWO>::type *__restrict__ out,
                                                                 uint64_t capacity,
                                                                 unsigned long long *__restrict__ n_out) {
     using K = typename KeyOf<TWO>::type;
     extern __shared__ uint64_t s_table[];
+    __shared__ K s_buf[COLLECT_BUF];
+    __shared__ uint32_t s_wc[BLOOM_THREADS / WAVE];
+    __shared__ uint32_t s_n;
+    __shared__ unsigned long long s_base;
     const uint32_t n_tab = 1u << a.table_bits;
     if (SCREEN)
         load_table(a.table, n_tab, s_table);
+    const int tid = threadIdx.x;
+    const int wave = tid / WAVE;
+    if (tid == 0)
+        s_n = 0;
+    __syncthreads();
+    auto flush = [&]() {
+        const uint32_t n = s_n;
+        if (tid == 0)
+            s_base = atomicAdd(n_out, (unsigned long long)n);
+        __syncthreads();
+        const uint64_t base = s_base;
+        for (uint32_t j = tid; j < n; j += BLOOM_THREADS)
+            if (base + j < capacity)
+                out[base + j] = s_buf[j];
+        __syncthreads();
+        if (tid == 0)
+            s_n = 0;
+        __syncthreads();
+    };
     const uint64_t n_pos = a.n_words * 32;
     const uint64_t stride = (uint64_t)gridDim.x * BLOOM_THREADS;
     // every lane of a block runs the same number of iterations, so the wave
-    // ballot below always sees all 64 lanes
+    // ballots and the barriers below always see every thread
     const uint64_t first = (uint64_t)blockIdx.x * BLOOM_THREADS;
     for (uint64_t base = first; base < n_pos; base += stride) {
-        const uint64_t p = base + threadIdx.x;
+        const uint64_t p = base + tid;
         bool cand = false;
         K key{};
         if (p < n_pos) {
@@ -117,16 +145,25 @@ __global__ __launch_bounds__(BLOOM_THREADS) void collect_kernel(BloomArgs a, typ
             }
         }
         const uint64_t ball = __ballot(cand);
-        if (ball) {
-            uint64_t at = 0;
-            if (lane_id() == 0)
-                at = atomicAdd(n_out, (unsigned long long)__popcll(ball));
-            at = read_lane64(at, 0);
-            const uint64_t idx = at + __popcll(ball & lanemask_lt());
-            if (cand && idx < capacity)
-                out[idx] = key;
+        if (lane_id() == 0)
+            s_wc[wave] = (uint32_t)__popcll(ball);
+        __syncthreads();
+        uint32_t off = s_n, tot = 0;
+        for (int v = 0; v < BLOOM_THREADS / WAVE; v++) {
+            off += v < wave ? s_wc[v] : 0u;
+            tot += s_wc[v];
         }
+        if (cand)
+            s_buf[off + (uint32_t)__popcll(ball & lanemask_lt())] = key;
+        __syncthreads();
+        if (tid == 0)
+            s_n += tot;
+        __syncthreads();
+        if (s_n + BLOOM_THREADS > COLLECT_BUF)
+            flush();
     }
+    if (s_n)
+        flush();
 }
 
 }  // namespace
