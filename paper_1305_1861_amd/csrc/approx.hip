@@ -20,6 +20,7 @@ namespace tk {
 namespace {
 
 constexpr int AP_THREADS = 256;
+constexpr int AP_BUF = 2048;  // reported keys staged per block
 
 template <bool TWO, bool CTURTLE>
 __global__ __launch_bounds__(AP_THREADS) void approx_kernel(const uint64_t *__restrict__ packed,
@@ -30,10 +31,15 @@ __global__ __launch_bounds__(AP_THREADS) void approx_kernel(const uint64_t *__re
                                                             uint64_t capacity, unsigned long long *__restrict__ n_out) {
     using K = typename KeyOf<TWO>::type;
     __shared__ uint64_t s_table[1024];
+    __shared__ K s_buf[AP_BUF];
+    __shared__ uint32_t s_wc[AP_THREADS / WAVE];
+    __shared__ uint32_t s_n;
+    __shared__ unsigned long long s_base;
+    BlockAppender<K, AP_THREADS, AP_BUF> app{s_buf, s_wc, &s_n, &s_base, out, capacity, n_out};
     const uint32_t n_tab = 1u << table_bits, tm = n_tab - 1;
     for (uint32_t i = threadIdx.x; i < n_tab; i += AP_THREADS)
         s_table[i] = table[i];
-    __syncthreads();
+    app.init();  // (its barrier also publishes the table)
     const uint64_t n_pos = n_words * 32;
     const uint64_t stride = (uint64_t)gridDim.x * AP_THREADS;
     // every lane of a block runs the same number of iterations (wave ballots)
@@ -65,17 +71,9 @@ __global__ __launch_bounds__(AP_THREADS) void approx_kernel(const uint64_t *__re
                 }
             }
         }
-        const uint64_t ball = __ballot(emit);
-        if (ball) {
-            uint64_t at = 0;
-            if (lane_id() == 0)
-                at = atomicAdd(n_out, (unsigned long long)__popcll(ball));
-            at = read_lane64(at, 0);
-            const uint64_t o = at + __popcll(ball & lanemask_lt());
-            if (emit && o < capacity)
-                out[o] = key;
-        }
+        app.push(emit, key);
     }
+    app.finish();
 }
 
 // counts[i] += add (or = 0 when add is 0)

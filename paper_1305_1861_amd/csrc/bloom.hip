@@ -76,10 +76,7 @@ __global__ __launch_bounds__(BLOOM_THREADS) void screen_kernel(BloomArgs a) {
     }
 }
 
-// Candidates go to a per-block LDS buffer first; a full buffer (and the
-// rest at the end) is appended with one atomicAdd and copied out coalesced,
-// instead of one atomic on the single output counter per wave.
-constexpr int COLLECT_BUF = 2048;
+constexpr int COLLECT_BUF = 2048;  // candidates staged per block
 
 template <bool TWO, bool SCREEN>
 __global__ __launch_bounds__(BLOOM_THREADS) void collect_kernel(BloomArgs a, typename KeyOf<TWO>::type *__restrict__ out,
@@ -95,24 +92,8 @@ __global__ __launch_bounds__(BLOOM_THREADS) void collect_kernel(BloomArgs a, typ
     if (SCREEN)
         load_table(a.table, n_tab, s_table);
     const int tid = threadIdx.x;
-    const int wave = tid / WAVE;
-    if (tid == 0)
-        s_n = 0;
-    __syncthreads();
-    auto flush = [&]() {
-        const uint32_t n = s_n;
-        if (tid == 0)
-            s_base = atomicAdd(n_out, (unsigned long long)n);
-        __syncthreads();
-        const uint64_t base = s_base;
-        for (uint32_t j = tid; j < n; j += BLOOM_THREADS)
-            if (base + j < capacity)
-                out[base + j] = s_buf[j];
-        __syncthreads();
-        if (tid == 0)
-            s_n = 0;
-        __syncthreads();
-    };
+    BlockAppender<K, BLOOM_THREADS, COLLECT_BUF> app{s_buf, s_wc, &s_n, &s_base, out, capacity, n_out};
+    app.init();
     const uint64_t n_pos = a.n_words * 32;
     const uint64_t stride = (uint64_t)gridDim.x * BLOOM_THREADS;
     // every lane of a block runs the same number of iterations, so the wave
@@ -144,26 +125,9 @@ __global__ __launch_bounds__(BLOOM_THREADS) void collect_kernel(BloomArgs a, typ
                 }
             }
         }
-        const uint64_t ball = __ballot(cand);
-        if (lane_id() == 0)
-            s_wc[wave] = (uint32_t)__popcll(ball);
-        __syncthreads();
-        uint32_t off = s_n, tot = 0;
-        for (int v = 0; v < BLOOM_THREADS / WAVE; v++) {
-            off += v < wave ? s_wc[v] : 0u;
-            tot += s_wc[v];
-        }
-        if (cand)
-            s_buf[off + (uint32_t)__popcll(ball & lanemask_lt())] = key;
-        __syncthreads();
-        if (tid == 0)
-            s_n += tot;
-        __syncthreads();
-        if (s_n + BLOOM_THREADS > COLLECT_BUF)
-            flush();
+        app.push(cand, key);
     }
-    if (s_n)
-        flush();
+    app.finish();
 }
 
 }  // namespace

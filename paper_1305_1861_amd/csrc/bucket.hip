@@ -868,6 +868,8 @@ __global__ __launch_bounds__(256) void fb_screen(const K *__restrict__ keys, con
         uint64_t *b = filter + ((uint64_t)e.fpre + __umul64hi(h, (uint64_t)e.nb)) * 8;
         for (int w = 0; w < 4; w++) {
             const uint64_t m = table[(h >> (w * table_bits)) & tmask];
+            if ((b[4 + w] & m) == m)
+                continue;  // already in the second plane: the atomics would change nothing
             const uint64_t old = __hip_atomic_fetch_or(b + w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (old & m)
                 __hip_atomic_fetch_or(b + 4 + w, old & m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -880,8 +882,16 @@ __global__ __launch_bounds__(256) void fb_collect(const K *__restrict__ keys, co
                                                   uint32_t n_ent, uint64_t n, const uint64_t *__restrict__ table,
                                                   uint32_t table_bits, const uint64_t *__restrict__ filter, int screen,
                                                   K *__restrict__ out, unsigned long long *__restrict__ n_out) {
+    constexpr int FB_BUF = 1024;
+    __shared__ K s_buf[FB_BUF];
+    __shared__ uint32_t s_wc[256 / WAVE];
+    __shared__ uint32_t s_n;
+    __shared__ unsigned long long s_base;
+    BlockAppender<K, 256, FB_BUF> app{s_buf, s_wc, &s_n, &s_base, out, n, n_out};
+    app.init();
     const uint32_t tmask = (1u << table_bits) - 1u;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // every thread of a block runs the same number of iterations
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
         const uint64_t g = base + threadIdx.x;
         bool keep = false;
@@ -899,16 +909,9 @@ __global__ __launch_bounds__(256) void fb_collect(const K *__restrict__ keys, co
                 }
             }
         }
-        const uint64_t ball = __ballot(keep);
-        if (ball) {
-            uint64_t at = 0;
-            if (lane_id() == 0)
-                at = atomicAdd(n_out, (unsigned long long)__popcll(ball));
-            at = read_lane64(at, 0);
-            if (keep)
-                out[at + __popcll(ball & lanemask_lt())] = key;
-        }
+        app.push(keep, key);
     }
+    app.finish();
 }
 
 // One block per entry: the records of bucket d (a contiguous range of the

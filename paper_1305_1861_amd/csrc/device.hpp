@@ -120,6 +120,68 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *to
     return r;
 }
 
+// Appending items found by the threads of a block to one output array: the
+// items are staged in LDS (wave ballots for the offsets) and a full buffer
+// is appended with one atomicAdd on the output counter and copied out
+// coalesced, instead of one atomic on that counter per wave.  Every thread
+// of the block calls push() the same number of times, then finish().  The
+// LDS arrays belong to the caller's kernel.
+template <typename K, int THREADS, int BUF>
+struct BlockAppender {
+    K *s_buf;                      // BUF items
+    uint32_t *s_wc;                // THREADS / WAVE counts
+    uint32_t *s_n;                 // items staged
+    unsigned long long *s_base;    // output position of the buffer
+    K *out;
+    uint64_t capacity;             // items beyond it are counted, not written
+    unsigned long long *n_out;
+    static_assert(BUF >= THREADS, "a buffer holds at least one round");
+
+    __device__ void init() {
+        if (threadIdx.x == 0)
+            *s_n = 0;
+        __syncthreads();
+    }
+    __device__ void flush() {
+        const uint32_t n = *s_n;
+        if (threadIdx.x == 0)
+            *s_base = atomicAdd(n_out, (unsigned long long)n);
+        __syncthreads();
+        const uint64_t base = *s_base;
+        for (uint32_t j = threadIdx.x; j < n; j += THREADS)
+            if (base + j < capacity)
+                out[base + j] = s_buf[j];
+        __syncthreads();
+        if (threadIdx.x == 0)
+            *s_n = 0;
+        __syncthreads();
+    }
+    __device__ void push(bool emit, const K &item) {
+        const int wave = (int)threadIdx.x / WAVE;
+        const uint64_t ball = __ballot(emit);
+        if (__lane_id() == 0)
+            s_wc[wave] = (uint32_t)__popcll(ball);
+        __syncthreads();
+        uint32_t off = *s_n, tot = 0;
+        for (int v = 0; v < THREADS / WAVE; v++) {
+            off += v < wave ? s_wc[v] : 0u;
+            tot += s_wc[v];
+        }
+        if (emit)
+            s_buf[off + (uint32_t)__popcll(ball & lanemask_lt())] = item;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            *s_n += tot;
+        __syncthreads();
+        if (*s_n + THREADS > BUF)
+            flush();
+    }
+    __device__ void finish() {
+        if (*s_n)
+            flush();
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Canonical key of a k-mer window (paper §2.1, k-mer extraction): the window
 // ending at base p = 32w + t is a contiguous 2k-bit field of the big-endian
