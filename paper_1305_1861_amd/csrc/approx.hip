@@ -55,16 +55,26 @@ __global__ __launch_bounds__(AP_THREADS) void approx_kernel(const uint64_t *__re
                 const uint64_t h = key_hash(key);
                 const uint64_t w1 = __umul64hi(h, n_fw);
                 const uint64_t m1 = s_table[h & tm] | s_table[(h >> table_bits) & tm];
-                const uint64_t old1 = __hip_atomic_fetch_or(filter + w1, m1, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
-                if ((old1 & m1) == m1) {
+                // Bits are only ever set: a read that finds a pattern's bits
+                // all set decides exactly as the atomic would have (which
+                // would change nothing), so the atomic is issued only when
+                // the read finds a bit missing (a stale read only costs it).
+                bool seen = (filter[w1] & m1) == m1;
+                if (!seen) {
+                    const uint64_t old1 = __hip_atomic_fetch_or(filter + w1, m1, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+                    seen = (old1 & m1) == m1;
+                }
+                if (seen) {
                     if (CTURTLE) {
                         const uint64_t w2 = w1 + 1 < n_fw ? w1 + 1 : 0;
                         const uint64_t m2 = s_table[(h >> (2 * table_bits)) & tm] |
                                             s_table[(h >> (3 * table_bits)) & tm];
-                        const uint64_t old2 = __hip_atomic_fetch_or(filter + w2, m2, __ATOMIC_RELAXED,
-                                                                    __HIP_MEMORY_SCOPE_AGENT);
-                        emit = (old2 & m2) != m2;
+                        if ((filter[w2] & m2) != m2) {
+                            const uint64_t old2 = __hip_atomic_fetch_or(filter + w2, m2, __ATOMIC_RELAXED,
+                                                                        __HIP_MEMORY_SCOPE_AGENT);
+                            emit = (old2 & m2) != m2;
+                        }
                     } else {
                         emit = true;
                     }
