@@ -330,18 +330,29 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                     const uint32_t f0 = s_fo[rb[i]], nb = (uint32_t)s_fo[rb[i] + 1] - f0;
                     const uint64_t h = key_hash(key[i]);
                     uint64_t *b = s_filter + f0 + (uint32_t)__umul64hi(h, nb);
+                    // the four pattern words and second-plane words are
+                    // read together, then the first-plane atomics of the
+                    // words that need them are issued together, so that a
+                    // key waits for LDS three times rather than nine
+                    uint64_t m[4], t[4], o[4];
+#pragma unroll
+                    for (int w = 0; w < 4; w++) {
+                        m[w] = s_table[(h >> (w * tbits)) & tmask];
+                        t[w] = b[(4 + w) * blocks_cut];
+                    }
+#pragma unroll
+                    for (int w = 0; w < 4; w++) {
+                        o[w] = m[w];
+                        if ((t[w] & m[w]) != m[w])
+                            o[w] = atomicOr((unsigned long long *)(b + w * blocks_cut), (unsigned long long)m[w]);
+                    }
                     bool seen = true;
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
-                        const uint64_t m = s_table[(h >> (w * tbits)) & tmask];
-                        if ((b[(4 + w) * blocks_cut] & m) != m) {
-                            const uint64_t old =
-                                atomicOr((unsigned long long *)(b + w * blocks_cut), (unsigned long long)m);
-                            if (old & m)
-                                atomicOr((unsigned long long *)(b + (4 + w) * blocks_cut),
-                                         (unsigned long long)(old & m));
-                            seen &= (old & m) == m;
-                        }
+                        const uint64_t hit = o[w] & m[w];
+                        if ((t[w] & m[w]) != m[w] && hit)
+                            atomicOr((unsigned long long *)(b + (4 + w) * blocks_cut), (unsigned long long)hit);
+                        seen &= hit == m[w];
                     }
                     sv |= (uint32_t)seen << i;
                 }

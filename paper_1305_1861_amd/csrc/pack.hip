@@ -19,19 +19,23 @@ namespace {
 
 constexpr int PACK_THREADS = 256;  // one word (32 bases) per thread
 
-// Byte -> (code, is_base) for 4 bytes at once.  Upper-casing by clearing
-// bit 5 maps a/c/g/t onto A/C/G/T and no other byte onto them.
-__device__ __forceinline__ void classify4(uint32_t x, uint32_t &codes, uint32_t &bad4) {
+// 4 bytes -> their four 2-bit codes, first byte highest (g, 8 bits), and
+// their non-base flags (bad4, bit j: byte j).  Upper-casing by clearing bit
+// 5 maps a/c/g/t onto A/C/G/T and no other byte onto them.
+__device__ __forceinline__ void classify4(uint32_t x, uint32_t &g, uint32_t &bad4) {
     const uint32_t u = x & 0xDFDFDFDFu;
     // ((u >> 1) ^ (u >> 2)) & 3 per byte: A(0x41)->0, C(0x43)->1, G(0x47)->2, T(0x54)->3
-    codes = ((u >> 1) ^ (u >> 2)) & 0x03030303u;
-    // exact per-byte zero test: 0x80 in every byte of v that is zero
+    uint32_t codes = ((u >> 1) ^ (u >> 2)) & 0x03030303u;
+    // a byte is a base iff it equals the letter of its code, picked per byte
+    // from the bytes of 0x54474341 (A, C, G, T) by a byte permute; exact
+    // per-byte zero test: 0x80 in every byte of v that is zero
     auto zero_bytes = [](uint32_t v) { return ~(((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v | 0x7F7F7F7Fu); };
-    const uint32_t ok = zero_bytes(u ^ 0x41414141u) | zero_bytes(u ^ 0x43434343u) |
-                        zero_bytes(u ^ 0x47474747u) | zero_bytes(u ^ 0x54545454u);
-    codes &= (ok >> 7) * 3u;  // a non-base byte packs as code 0
-    const uint32_t nb = ~ok & 0x80808080u;
-    bad4 = ((nb >> 7) & 1u) | ((nb >> 14) & 2u) | ((nb >> 21) & 4u) | ((nb >> 28) & 8u);
+    const uint32_t ok = zero_bytes(u ^ __builtin_amdgcn_perm(0u, 0x54474341u, codes));
+    codes &= (ok >> 6) | (ok >> 7);  // a non-base byte packs as code 0
+    // one multiply gathers the four codes (byte j to bits 7-2j, 6-2j),
+    // another the four flags; their partial products never overlap
+    g = (codes * 0x40100401u) >> 24;
+    bad4 = ((((~ok) >> 7) & 0x01010101u) * 0x00204081u) >> 21 & 0xFu;
 }
 
 // Packed codes and non-base mask of word w.  Bytes past n_bases count as
@@ -59,18 +63,56 @@ __device__ __forceinline__ void load_word(const uint8_t *__restrict__ bases, uin
             x[i] = v;
         }
     }
-    code = 0;
+    uint32_t hi = 0, lo = 0;
     bad = 0;
 #pragma unroll
     for (int i = 0; i < 8; i++) {
-        uint32_t c4, b4;
-        classify4(x[i], c4, b4);
-        // bases 4i..4i+3 (byte j = base 4i+j) -> 8 bits, first base highest
-        const uint32_t g = ((c4 & 3u) << 6) | (((c4 >> 8) & 3u) << 4) | (((c4 >> 16) & 3u) << 2) |
-                           ((c4 >> 24) & 3u);
-        code |= (uint64_t)g << (56 - 8 * i);
+        uint32_t g, b4;
+        classify4(x[i], g, b4);  // bases 4i..4i+3 (byte j = base 4i+j)
+        if (i < 4)
+            hi |= g << (24 - 8 * i);
+        else
+            lo |= g << (56 - 8 * i);
         bad |= b4 << (4 * i);
     }
+    code = ((uint64_t)hi << 32) | lo;
+}
+
+// Bit t of the result: bits t - L + 1 .. t of x are all set (bits below bit
+// 0 count as clear); 0 <= L <= 32.  Windows of length 1, 2, 4, ... are
+// formed by doubling and combined along the binary digits of L.
+__device__ __forceinline__ uint32_t runs_of(uint32_t x, int L) {
+    uint32_t res = ~0u, pw = x;
+    int cov = 0;  // length combined so far, below the current digit
+#pragma unroll
+    for (int p = 1; p <= 32; p <<= 1) {
+        if (L & p) {
+            res &= pw << cov;
+            cov += p;
+        }
+        if (p < 32)
+            pw &= pw << p;
+    }
+    return res;
+}
+
+// Validity bits of one word: bit t is set iff the k-base window ending at
+// base t of the word lies in one read and holds only bases.  bad, st: the
+// word's non-base and read-start masks; run0 (<= 64): length of the base run
+// of one read that ends just before the word.  A window reaching back
+// before the word (t < k - 1) needs bases 0..t free of non-bases and read
+// starts and run0 >= k - 1 - t; a window inside the word needs its k bases
+// free of non-bases and its last k - 1 free of read starts (its first base
+// may start a read).
+__device__ __forceinline__ uint32_t window_bits(uint32_t bad, uint32_t st, int run0, int k) {
+    const uint32_t g = ~bad, ns = ~st;
+    const uint32_t pre = (g & ~(g + 1u)) & (ns & ~(ns + 1u));  // bits below the first break
+    const uint32_t before = k - 1 >= 32 ? ~0u : (1u << (k - 1)) - 1u;  // t < k - 1
+    const int need = max(0, k - 1 - run0);
+    uint32_t v = pre & before & (need >= 32 ? 0u : ~0u << need);
+    if (k <= 32)
+        v |= runs_of(g, k) & runs_of(ns, k - 1) & (~0u << (k - 1));
+    return v;
 }
 
 __global__ void mark_read_starts(const uint64_t *__restrict__ offsets, uint64_t n_reads, uint64_t n_bases,
@@ -126,13 +168,7 @@ __global__ __launch_bounds__(PACK_THREADS) void pack_kernel(const uint8_t *__res
         const uint64_t st64 = (uint64_t)s_st[tid] | ((uint64_t)s_st[tid + 1] << 32);
         const int qb = bad64 ? 63 - __clzll(bad64) : -1;
         const int qs = st64 ? 63 - __clzll(st64) : -1;
-        int run = 64 - max(qb + 1, qs);
-        for (int t = 0; t < 32; t++) {
-            const bool b = (bad >> t) & 1u;
-            const bool s = (st >> t) & 1u;
-            run = b ? 0 : (s ? 1 : min(run + 1, 64));
-            vbits |= (uint32_t)(run >= k) << t;
-        }
+        vbits = window_bits(bad, st, 64 - max(qb + 1, qs), k);
         valid[w] = vbits;
     }
     // valid windows of the block -> one atomic per block

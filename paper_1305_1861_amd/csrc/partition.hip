@@ -80,6 +80,7 @@ struct PassArgs {
     uint32_t nseg;
     const uint32_t *own;     // pass 1 of a key-range shard: its digits
                              // [own[0], own[1]); nullptr: every digit
+    uint64_t cap;            // keys the output can hold
 };
 
 // The chunk of this workgroup: elements [c0, c1) (window positions of pass
@@ -190,6 +191,25 @@ __device__ __forceinline__ uint32_t extract_win(const PassArgs &a, const RawWin 
     return vm;
 }
 
+// Two-bit codes of the 32 bases ending at base 32w + u (that base in bits
+// 1..0), -64 <= u <= 31, from the packed words w, w - 1 and w - 2 held in
+// r; bases before word w - 2 read as 0.
+__device__ __forceinline__ uint64_t codes_ending_at(const RawWin &r, int u) {
+    uint64_t a = r.w0, b = r.w1;
+    if (u < 0) {
+        a = r.w1;
+        b = r.w2;
+        u += 32;
+    }
+    if (u < 0) {
+        a = r.w2;
+        b = 0;
+        u += 32;
+    }
+    const uint32_t s = 62 - 2 * u;
+    return s ? (a >> s) | (b << (64 - s)) : a;
+}
+
 template <typename K, bool FROM_WIN>
 __device__ __forceinline__ uint32_t load_tile(const PassArgs &a, uint64_t t0, uint64_t t1, uint64_t lo,
                                               K (&key)[PtItems<K>::value]) {
@@ -233,8 +253,29 @@ __global__ __launch_bounds__(PT_THREADS) void pt_hist(PassArgs a, uint32_t *__re
             RawWin nxt{0, 0, 0, 0, 0};
             if (tn < ch.c1)
                 nxt = fetch_win<K>(a, tn, min(tn + pt_tile<K>(), ch.c1), ch.lo);
-            // each key is counted as it is rolled out (no key array held)
-            if (cur.okmask) {
+            if (cur.okmask && a.k >= 5) {
+                // The top bits of the canonical key, the smaller of the
+                // forward code and its reverse complement, are the smaller
+                // of the two codes' top bits.  So a window's digit (at most
+                // 10 bits) needs only its first five bases, forward, and its
+                // last five, reverse-complemented: two fields of words
+                // assembled once per thread, instead of the whole key.
+                constexpr int PER_WORD = 32 / ITEMS;
+                const int first = (tid % PER_WORD) * ITEMS;
+                const uint32_t ok = (cur.vword >> first) & cur.okmask;
+                const uint64_t last5 = ~group_reverse(codes_ending_at(cur, first + ITEMS - 1));
+                const uint64_t first5 = codes_ending_at(cur, first + ITEMS + 4 - a.k);
+                const int drop = 10 - ch.bits;
+#pragma unroll
+                for (int i = 0; i < ITEMS; i++) {
+                    if ((ok >> i) & 1u) {
+                        const uint32_t f = (uint32_t)(first5 >> (2 * (ITEMS - 1 - i))) & 0x3FFu;
+                        const uint32_t r = (uint32_t)(last5 >> (56 - 2 * ITEMS + 2 * i)) & 0x3FFu;
+                        atomicAdd(&s_h[min(f, r) >> drop], 1u);
+                    }
+                }
+            } else if (cur.okmask) {
+                // k < 5: each key is counted as it is rolled out
                 constexpr int PER_WORD = 32 / ITEMS;
                 const uint32_t first = (uint32_t)(tid % PER_WORD) * ITEMS;
                 const uint32_t ok = (cur.vword >> first) & cur.okmask;
@@ -348,7 +389,9 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint3
         for (uint32_t j = tid; j < n_tile; j += PT_THREADS) {
             const K x = s_stage[j];
             const uint32_t d = digit_of(x, ch.shift, mask);
-            out[(uint64_t)s_cur[d] + (j - s_cnt[d])] = x;
+            const uint64_t o = (uint64_t)s_cur[d] + (j - s_cnt[d]);
+            if (o < a.cap)  // holds whenever the counts match the keys
+                out[o] = x;
         }
         __syncthreads();
 #pragma unroll
@@ -527,6 +570,7 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
     a.cb = cb;
     a.eb = eb;
     a.nseg = p.nseg;
+    a.cap = p.cap;
 
     // pass 1: windows -> (second pass ? tmp : out), by (library, top D1 bits)
     void *out1 = p.D2max ? tmp : out;
