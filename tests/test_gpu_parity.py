@@ -14,7 +14,7 @@ from oracle import brute
 
 pytestmark = pytest.mark.gpu
 
-KS = [1, 2, 3, 5, 15, 21, 31, 32, 33, 55, 63]
+KS = [1, 2, 3, 4, 5, 15, 21, 31, 32, 33, 55, 63]
 
 
 def case(msg):
@@ -151,6 +151,36 @@ def test_pack_stage(tk, oracle_lib, k):
     assert (gp == hp).all()
     assert (gv == hv).all()
     assert int(nw.cpu().item()) == oracle_lib.count_windows(bases, offsets, k)
+
+
+def word_edge_library(k, seed):
+    """Reads whose starts, ends and N bases fall at every offset around the
+    32-base words: lengths about k and about multiples of 32, one N at each
+    position of a 96-base read, and single bases between them, shuffled;
+    every read twice."""
+    rng = np.random.default_rng(seed)
+    rand = lambda n: "".join("ACGT"[x] for x in rng.integers(0, 4, n))
+    reads = []
+    for L in sorted({k - 1, k, k + 1, 31, 32, 33, 63, 64, 65, 95, 96, 97}):
+        reads += [rand(L) for _ in range(3)] if L > 0 else [""]
+    base = rand(96)
+    reads += [base[:p] + "N" + base[p + 1:] for p in range(96)]
+    reads += [rand(1) for _ in range(40)]
+    rng.shuffle(reads)
+    return readsim.from_strings(reads + reads)
+
+
+@pytest.mark.parametrize("k", [2, 4, 5, 6, 31, 32, 33, 62, 63])
+def test_pack_and_count_at_word_edges(tk, oracle_lib, k):
+    for seed in range(3):
+        bases, offsets = word_edge_library(k, 40 * k + seed)
+        case(f"word edges k={k} seed={seed} n_bases={bases.size}")
+        db, do = to_device(bases, offsets)
+        packed, valid, nw = tk.tk_pack_device(db, do, k)
+        hp, hv = host_pack(bases, offsets, k)
+        assert (packed.cpu().numpy().view(np.uint64) == hp).all()
+        assert (valid.cpu().numpy().view(np.uint32) == hv).all()
+        check_against_oracle(tk, oracle_lib, bases, offsets, k, 2)
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 100, 4095, 4096, 4097, 100_003])
