@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -389,7 +390,100 @@ namespace {
 
 int g_cu_cache[64];
 
+// memcpy split over up to 8 host threads (slices of at least 4 MB)
+void parallel_memcpy(void *dst, const void *src, size_t bytes) {
+    constexpr size_t MIN_PART = size_t(4) << 20;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t parts = std::min<size_t>({8, (size_t)hw, std::max<size_t>(1, bytes / MIN_PART)});
+    if (parts <= 1) {
+        memcpy(dst, src, bytes);
+        return;
+    }
+    std::vector<std::thread> pool;
+    const size_t step = (bytes + parts - 1) / parts;
+    for (size_t i = 1; i < parts; i++) {
+        const size_t a = i * step, b = std::min(bytes, a + step);
+        if (a < b)
+            pool.emplace_back([=] { memcpy(static_cast<char *>(dst) + a, static_cast<const char *>(src) + a, b - a); });
+    }
+    memcpy(dst, src, std::min(bytes, step));
+    for (auto &t : pool)
+        t.join();
+}
+
 }  // namespace
+
+// Copy between pageable host memory and device memory through two pinned
+// staging slices: the DMA of one slice overlaps the host-side copy of the
+// other.  Host to device: returns once every slice is on its way (ordered on
+// `stream`, before anything enqueued later); device to host: returns once
+// the data is in dst.  Pageable copies by the runtime alone ran at about
+// 4 GB/s here.
+hipError_t staged_copy(void *dst, const void *src, size_t bytes, bool to_device, hipStream_t stream) {
+    if (!bytes)
+        return hipSuccess;
+    constexpr size_t SLICE = size_t(64) << 20;
+    void *pin[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    const size_t n_slices = (bytes + SLICE - 1) / SLICE;
+    const size_t nbuf = std::min<size_t>(2, n_slices);
+    for (size_t i = 0; i < nbuf && e == hipSuccess; i++) {
+        e = hipHostMalloc(&pin[i], std::min(bytes, SLICE));
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    }
+    auto slice = [&](size_t i, size_t &off, size_t &len) {
+        off = i * SLICE;
+        len = std::min(SLICE, bytes - off);
+    };
+    for (size_t i = 0; i < n_slices && e == hipSuccess; i++) {
+        size_t off, len;
+        slice(i, off, len);
+        const int b = (int)(i % 2);
+        if (to_device) {
+            // the slot is free once the DMA of slice i - 2 has finished
+            if ((e = hipEventSynchronize(ev[b])) != hipSuccess)
+                break;
+            parallel_memcpy(pin[b], static_cast<const char *>(src) + off, len);
+            if ((e = hipMemcpyAsync(static_cast<char *>(dst) + off, pin[b], len, hipMemcpyHostToDevice, stream)) !=
+                hipSuccess)
+                break;
+            e = hipEventRecord(ev[b], stream);
+        } else {
+            if ((e = hipMemcpyAsync(pin[b], static_cast<const char *>(src) + off, len, hipMemcpyDeviceToHost,
+                                    stream)) != hipSuccess ||
+                (e = hipEventRecord(ev[b], stream)) != hipSuccess)
+                break;
+            if (i > 0) {  // slice i - 1 is drained while slice i travels
+                size_t po, pl;
+                slice(i - 1, po, pl);
+                if ((e = hipEventSynchronize(ev[1 - b])) != hipSuccess)
+                    break;
+                parallel_memcpy(static_cast<char *>(dst) + po, pin[1 - b], pl);
+            }
+        }
+    }
+    if (e == hipSuccess && !to_device) {
+        size_t po, pl;
+        slice(n_slices - 1, po, pl);
+        e = hipEventSynchronize(ev[(n_slices - 1) % 2]);
+        if (e == hipSuccess)
+            parallel_memcpy(static_cast<char *>(dst) + po, pin[(n_slices - 1) % 2], pl);
+    }
+    // the staging slices are released only after their last DMA
+    for (size_t i = 0; i < 2; i++) {
+        if (ev[i]) {
+            const hipError_t w = hipEventSynchronize(ev[i]);
+            if (e == hipSuccess)
+                e = w;
+            (void)hipEventDestroy(ev[i]);
+        }
+        if (pin[i])
+            (void)hipHostFree(pin[i]);
+    }
+    return e;
+}
 
 int device_cu_count() {
     int dev = 0;
@@ -971,8 +1065,8 @@ tk_status tk_count(const uint8_t *bases, const uint64_t *offsets, uint64_t n_rea
         return dev_fail("hipMalloc(offsets)", e);
     if ((e = hipMalloc(&d_ws, p.total ? p.total : 256)) != hipSuccess)
         return dev_fail("hipMalloc(workspace)", e);
-    if (n_bases && (e = hipMemcpyAsync(d_bases, bases, n_bases, hipMemcpyHostToDevice, s)) != hipSuccess)
-        return dev_fail("hipMemcpy(bases)", e);
+    if ((e = staged_copy(d_bases, bases, n_bases, true, s)) != hipSuccess)
+        return dev_fail("copy of the reads", e);
     if ((e = hipMemcpyAsync(d_offsets, offsets, (n_reads + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s)) !=
         hipSuccess)
         return dev_fail("hipMemcpy(offsets)", e);
@@ -998,14 +1092,10 @@ tk_status tk_count(const uint8_t *bases, const uint64_t *offsets, uint64_t n_rea
         free(res);
         return fail(TK_ENOMEM, "result allocation failed");
     }
-    if (dev.n) {
-        if ((e = hipMemcpyAsync(res->keys, dev.keys, dev.n * dev.key_words * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                                s)) != hipSuccess)
-            return dev_fail("hipMemcpy(keys)", e);
-        if ((e = hipMemcpyAsync(res->counts, dev.counts, dev.n * sizeof(uint32_t), hipMemcpyDeviceToHost, s)) !=
-            hipSuccess)
-            return dev_fail("hipMemcpy(counts)", e);
-    }
+    if ((e = staged_copy(res->keys, dev.keys, dev.n * dev.key_words * sizeof(uint64_t), false, s)) != hipSuccess)
+        return dev_fail("copy of the keys", e);
+    if ((e = staged_copy(res->counts, dev.counts, dev.n * sizeof(uint32_t), false, s)) != hipSuccess)
+        return dev_fail("copy of the counts", e);
     if ((e = hipStreamSynchronize(s)) != hipSuccess)
         return dev_fail("hipStreamSynchronize", e);
     cleanup();
@@ -1073,6 +1163,9 @@ tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_
     const size_t o_ctr = take(2 * sizeof(DevCounters)), o_misc = take(64), o_table = take(sizeof(uint64_t) << o.table_bits);
     const size_t o_filter = take(n_blocks * 64), o_bases = take(CB), o_offs = take((cr_max + 1) * sizeof(uint64_t));
     const size_t o_packed = take(CW * 8), o_valid = take(CW * 4), o_starts = take(CW * 4);
+    // second packed/valid buffer: the next chunk's words arrive while this
+    // chunk is collected (second pass)
+    const size_t o_packed2 = screen ? take(CW * 8) : 0, o_valid2 = screen ? take(CW * 4) : 0;
     const size_t o_ka = take(CB * kb), o_kb = take(CB * kb), o_rk = take(CB * kb), o_rc = take(CB * 4);
     const size_t sort_bytes = radix_scratch_bytes(CB, kw), cmp_bytes = compact_scratch_bytes(CB);
     const size_t o_sort = take(sort_bytes), o_cmp = take(cmp_bytes);
@@ -1083,11 +1176,30 @@ tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_
     if (device_bytes)
         *device_bytes = total;
 
+    // packed words and validity bits of every chunk, kept in pinned host
+    // memory between the passes (0.5 B per base instead of the 1 B per base
+    // of the reads, and no pageable staging in the second pass)
+    std::vector<uint64_t> wfirst(n_chunks + 1, 0);  // first word of every chunk in the pinned arrays
+    for (uint64_t q = 0; q < n_chunks; q++)
+        wfirst[q + 1] = wfirst[q] + ceil_div(offsets[cuts[q + 1]] - offsets[cuts[q]], 32);
+
     char *ws = nullptr;
-    hipStream_t s = nullptr;
+    hipStream_t s = nullptr, cs = nullptr;  // kernels; copies of the next chunk
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t *h_packed = nullptr;
+    uint32_t *h_valid = nullptr;
+    uint64_t *h_roff = nullptr;  // relative read offsets of two chunks (pinned)
     tk_result *res = nullptr;
     auto cleanup = [&]() {
+        if (s) (void)hipStreamSynchronize(s);
+        if (cs) (void)hipStreamSynchronize(cs);
         if (ws) (void)hipFree(ws);
+        for (hipEvent_t &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (h_packed) (void)hipHostFree(h_packed);
+        if (h_valid) (void)hipHostFree(h_valid);
+        if (h_roff) (void)hipHostFree(h_roff);
+        if (cs) (void)hipStreamDestroy(cs);
         if (s) (void)hipStreamDestroy(s);
     };
     auto dev_fail = [&](const char *what, hipError_t e) {
@@ -1108,6 +1220,16 @@ tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_
             return dev_fail(what, e_);      \
     } while (0)
     TK_PH(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+    TK_PH(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+    for (hipEvent_t &e : ev)
+        TK_PH(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    TK_PH(hipHostMalloc(reinterpret_cast<void **>(&h_roff), 2 * (cr_max + 1) * sizeof(uint64_t)), "hipHostMalloc");
+    if (screen && wfirst[n_chunks]) {
+        TK_PH(hipHostMalloc(reinterpret_cast<void **>(&h_packed), wfirst[n_chunks] * sizeof(uint64_t)),
+              "hipHostMalloc(packed)");
+        TK_PH(hipHostMalloc(reinterpret_cast<void **>(&h_valid), wfirst[n_chunks] * sizeof(uint32_t)),
+              "hipHostMalloc(valid)");
+    }
     TK_PH(hipMalloc(&ws, total), "hipMalloc(workspace)");
     DevCounters *ctr = reinterpret_cast<DevCounters *>(ws + o_ctr);  // [0] windows, collected; [1] chunk compaction
     uint32_t *misc = reinterpret_cast<uint32_t *>(ws + o_misc);        // [0] SAC size, [1] selected
@@ -1118,6 +1240,8 @@ tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_
     uint64_t *d_offs = reinterpret_cast<uint64_t *>(ws + o_offs);
     uint64_t *packed = reinterpret_cast<uint64_t *>(ws + o_packed);
     uint32_t *valid = reinterpret_cast<uint32_t *>(ws + o_valid), *starts = reinterpret_cast<uint32_t *>(ws + o_starts);
+    uint64_t *packed2[2] = {packed, reinterpret_cast<uint64_t *>(ws + o_packed2)};
+    uint32_t *valid2[2] = {valid, reinterpret_cast<uint32_t *>(ws + o_valid2)};
     uint64_t *keys_a = reinterpret_cast<uint64_t *>(ws + o_ka), *keys_b = reinterpret_cast<uint64_t *>(ws + o_kb);
     uint64_t *run_k = reinterpret_cast<uint64_t *>(ws + o_rk);
     uint32_t *run_c = reinterpret_cast<uint32_t *>(ws + o_rc);
@@ -1140,38 +1264,97 @@ tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_
     ba.table_bits = o.table_bits;
     ba.n_blocks = n_blocks;
     ba.filter = filter;
-    std::vector<uint64_t> roff(cr_max + 1);
-    // one chunk to the device and packed; count windows on the first pass
-    auto load_chunk = [&](uint64_t q, bool count) -> hipError_t {
+    // Chunk q's reads and relative read offsets go to the device on the copy
+    // stream (offsets staged in pinned slot q % 2) while the kernel stream
+    // still screens the chunk before; pack then runs on the kernel stream.
+    // ev[0]: chunk copied; ev[1]: chunk packed (its reads are consumed, so
+    // the next chunk may overwrite them; the host waits for it, whatever the
+    // runtime does with pageable sources); ev[2 + q % 2]: the offsets of
+    // slot q % 2 are on the device.
+    auto send_chunk = [&](uint64_t q) -> hipError_t {
         const uint64_t r0 = cuts[q], r1 = cuts[q + 1], b0 = offsets[r0], nb = offsets[r1] - b0;
+        uint64_t *ro = h_roff + (q % 2) * (cr_max + 1);
+        hipError_t e = hipEventSynchronize(ev[2 + q % 2]);  // slot free (chunk q - 2 sent)
+        if (e != hipSuccess)
+            return e;
         for (uint64_t r = r0; r <= r1; r++)
-            roff[r - r0] = offsets[r] - b0;
-        hipError_t e;
-        if (nb && (e = hipMemcpyAsync(d_bases, bases + b0, nb, hipMemcpyHostToDevice, s)) != hipSuccess)
+            ro[r - r0] = offsets[r] - b0;
+        if ((e = hipEventSynchronize(ev[1])) != hipSuccess)
             return e;
-        if ((e = hipMemcpyAsync(d_offs, roff.data(), (r1 - r0 + 1) * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+        if (nb && (e = hipMemcpyAsync(d_bases, bases + b0, nb, hipMemcpyHostToDevice, cs)) != hipSuccess)
             return e;
-        if ((e = zero_bytes(starts, CW * 4, s)) != hipSuccess)
+        if ((e = hipMemcpyAsync(d_offs, ro, (r1 - r0 + 1) * 8, hipMemcpyHostToDevice, cs)) != hipSuccess)
             return e;
+        if ((e = hipEventRecord(ev[2 + q % 2], cs)) != hipSuccess)
+            return e;
+        return hipEventRecord(ev[0], cs);
+    };
+    auto pack_chunk = [&](uint64_t q, bool count) -> hipError_t {
+        const uint64_t nb = offsets[cuts[q + 1]] - offsets[cuts[q]];
+        hipError_t e = hipStreamWaitEvent(s, ev[0], 0);
+        if (e != hipSuccess || (e = zero_bytes(starts, CW * 4, s)) != hipSuccess)
+            return e;
+        ba.packed = packed;
+        ba.valid = valid;
         ba.n_words = ceil_div(nb, 32);
-        e = launch_pack(d_bases, d_offs, nb, r1 - r0, k, packed, valid, starts, count ? &ctr[0].n_windows : nullptr,
-                        s);
+        e = launch_pack(d_bases, d_offs, nb, cuts[q + 1] - cuts[q], k, packed, valid, starts,
+                        count ? &ctr[0].n_windows : nullptr, s);
         if (e == hipSuccess)
-            e = hipStreamSynchronize(s);  // roff is reused by the next chunk
+            e = hipEventRecord(ev[1], s);
         return e;
     };
-    // pass 1: every window of every chunk into the filter
+    // pass 1: every window of every chunk into the filter; the next chunk's
+    // reads travel while this one is screened; the packed words are kept
     if (screen) {
+        if (n_chunks)
+            TK_PH(send_chunk(0), "pass 1");
         for (uint64_t q = 0; q < n_chunks; q++) {
-            TK_PH(load_chunk(q, true), "pass 1");
+            TK_PH(pack_chunk(q, true), "pass 1");
+            const uint64_t nw = wfirst[q + 1] - wfirst[q];
             TK_PH(launch_screen(ba, persistent_grid(ba.n_words * 32), s), "screen");
+            if (nw) {
+                TK_PH(hipMemcpyAsync(h_packed + wfirst[q], packed, nw * 8, hipMemcpyDeviceToHost, s), "keep");
+                TK_PH(hipMemcpyAsync(h_valid + wfirst[q], valid, nw * 4, hipMemcpyDeviceToHost, s), "keep");
+            }
+            if (q + 1 < n_chunks)
+                TK_PH(send_chunk(q + 1), "pass 1");
         }
+        // the pinned words are complete before the second pass reads them
+        TK_PH(hipEventRecord(ev[1], s), "record");
+        TK_PH(hipStreamWaitEvent(cs, ev[1], 0), "wait");
     }
+    // second pass input of chunk q: packed words and validity bits from
+    // pinned memory into buffer q % 2 (screen), or the reads, packed again
+    auto second_pass_input = [&](uint64_t q) -> hipError_t {
+        const uint64_t nw = wfirst[q + 1] - wfirst[q];
+        hipError_t e;
+        if (nw && (e = hipMemcpyAsync(packed2[q % 2], h_packed + wfirst[q], nw * 8, hipMemcpyHostToDevice, cs)) !=
+                      hipSuccess)
+            return e;
+        if (nw && (e = hipMemcpyAsync(valid2[q % 2], h_valid + wfirst[q], nw * 4, hipMemcpyHostToDevice, cs)) !=
+                      hipSuccess)
+            return e;
+        return hipEventRecord(ev[q % 2], cs);
+    };
     // pass 2: per chunk, collect, sort, compact, merge into the SAC
     uint64_t n_sac = 0, n_coll = 0;
     int cur = 0;
+    if (screen && n_chunks)
+        TK_PH(second_pass_input(0), "pass 2");
     for (uint64_t q = 0; q < n_chunks; q++) {
-        TK_PH(load_chunk(q, !screen), "pass 2");
+        if (screen) {
+            // buffer (q + 1) % 2 was last read by chunk q - 1, whose collect
+            // finished before its survivor count was read back
+            if (q + 1 < n_chunks)
+                TK_PH(second_pass_input(q + 1), "pass 2");
+            TK_PH(hipStreamWaitEvent(s, ev[q % 2], 0), "wait");
+            ba.packed = packed2[q % 2];
+            ba.valid = valid2[q % 2];
+            ba.n_words = wfirst[q + 1] - wfirst[q];
+        } else {
+            TK_PH(send_chunk(q), "pass 2");
+            TK_PH(pack_chunk(q, true), "pass 2");
+        }
         TK_PH(zero_bytes(&ctr[1], sizeof(DevCounters), s), "zero");
         TK_PH(launch_collect(ba, screen, keys_a, CB, &ctr[1].n_collected, persistent_grid(ba.n_words * 32), s),
               "collect");
@@ -1228,10 +1411,8 @@ tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_
     res->counts = static_cast<uint32_t *>(malloc((n_out ? n_out : 1) * sizeof(uint32_t)));
     if (!res->keys || !res->counts)
         return dev_fail("result allocation", hipErrorOutOfMemory);
-    if (n_out) {
-        TK_PH(hipMemcpyAsync(res->keys, tmp_k, n_out * kb, hipMemcpyDeviceToHost, s), "copy keys");
-        TK_PH(hipMemcpyAsync(res->counts, tmp_c, n_out * 4, hipMemcpyDeviceToHost, s), "copy counts");
-    }
+    TK_PH(staged_copy(res->keys, tmp_k, n_out * kb, false, s), "copy keys");
+    TK_PH(staged_copy(res->counts, tmp_c, n_out * 4, false, s), "copy counts");
     TK_PH(hipStreamSynchronize(s), "sync");
 #undef TK_PH
     cleanup();

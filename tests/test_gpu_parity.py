@@ -317,6 +317,22 @@ def test_host_entry_point(tk, oracle_lib):
         assert r.n_windows == ora.n_windows
 
 
+@pytest.mark.parametrize("k,c", [(31, 1), (63, 1), (31, 2)])
+def test_host_entry_point_beyond_one_staging_slice(tk, k, c):
+    """Reads (90 MB) and records (up to 0.3 GB at c = 1) larger than one
+    64 MB staging slice of the host copies: the host entry point returns
+    exactly the device entry point's records."""
+    lib = readsim.large_library(scale=0.06)
+    case(f"host entry point, staged copies, k={k} c={c} n_bases={lib.n_bases}")
+    h = tk.tk_count(lib.bases, lib.offsets, k, c)
+    keys, counts, r = gpu_count(tk, lib.bases, lib.offsets, k, c)
+    assert h.keys.shape == keys.shape and np.array_equal(h.keys, keys)
+    assert np.array_equal(h.counts, counts)
+    assert (h.n_windows, h.n_collected, h.n_distinct) == (r.n_windows, r.n_collected, r.n_distinct)
+    if c == 1:
+        assert keys.nbytes > 64 << 20
+
+
 @pytest.mark.parametrize("opts", [None, GLOBAL])
 def test_repeat_runs_identical(tk, opts):
     """The screen's outcome does not depend on the order atomics land in."""
