@@ -6,8 +6,11 @@
 // that adds up the counts of keys present in both.
 //
 // merge     : merge path of two sorted record lists with unique keys (the
-//             SAC first on equal keys); every thread finds its own start on
-//             its diagonal by binary search and merges MG_ITEMS outputs.
+//             SAC first on equal keys), a tile of MG_TILE outputs per
+//             workgroup: the tiles' splits are found first (one binary
+//             search per tile), then each workgroup stages its two input
+//             ranges in LDS, every thread merges MG_ITEMS outputs there, and
+//             the tile is written back coalesced.
 // heads     : flag of every merged record whose key differs from the one
 //             before (a key occurs at most twice: once per list).
 // reduce    : after an exclusive scan of the flags, every head writes its
@@ -22,43 +25,84 @@ namespace {
 
 constexpr int MG_THREADS = 256;
 constexpr int MG_ITEMS = 8;
+constexpr int MG_TILE = MG_THREADS * MG_ITEMS;
 
 template <typename K>
 __device__ __forceinline__ bool key_le(const K &a, const K &b) {
     return !(b < a);
 }
 
-template <typename K>
-__global__ __launch_bounds__(MG_THREADS) void merge_kernel(const K *__restrict__ ak, const uint32_t *__restrict__ ac,
-                                                           uint64_t na, const K *__restrict__ bk,
-                                                           const uint32_t *__restrict__ bc, uint64_t nb,
-                                                           K *__restrict__ ck, uint32_t *__restrict__ cc) {
-    const uint64_t n = na + nb;
-    const uint64_t d = ((uint64_t)blockIdx.x * MG_THREADS + threadIdx.x) * MG_ITEMS;
-    if (d >= n)
-        return;
-    // split of diagonal d: i items from A, d - i from B, A first on ties
+// Split of diagonal d of the merge of A (na) and B (nb): the number of A
+// records among the first d outputs, A first on equal keys.
+template <typename K, typename AtA, typename AtB>
+__device__ __forceinline__ uint64_t merge_split(uint64_t na, uint64_t nb, uint64_t d, AtA at_a, AtB at_b) {
     uint64_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
     while (lo < hi) {
         const uint64_t mid = lo + (hi - lo) / 2;
-        if (key_le(ak[mid], bk[d - mid - 1]))
+        if (key_le<K>(at_a(mid), at_b(d - mid - 1)))
             lo = mid + 1;
         else
             hi = mid;
     }
-    uint64_t i = lo, j = d - lo;
-    const uint64_t e = min(d + MG_ITEMS, n);
-    for (uint64_t o = d; o < e; o++) {
-        const bool take_a = j >= nb || (i < na && key_le(ak[i], bk[j]));
-        if (take_a) {
-            ck[o] = ak[i];
-            cc[o] = ac[i];
-            i++;
-        } else {
-            ck[o] = bk[j];
-            cc[o] = bc[j];
-            j++;
+    return lo;
+}
+
+// splits[t]: split of diagonal min(t * MG_TILE, na + nb), t <= n_tiles
+template <typename K>
+__global__ __launch_bounds__(256) void merge_splits_kernel(const K *__restrict__ ak, uint64_t na,
+                                                           const K *__restrict__ bk, uint64_t nb, uint64_t n_tiles,
+                                                           uint64_t *__restrict__ splits) {
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t > n_tiles)
+        return;
+    const uint64_t d = min(t * (uint64_t)MG_TILE, na + nb);
+    splits[t] = merge_split<K>(na, nb, d, [&](uint64_t i) { return ak[i]; }, [&](uint64_t j) { return bk[j]; });
+}
+
+template <typename K>
+__global__ __launch_bounds__(MG_THREADS) void merge_kernel(const K *__restrict__ ak, const uint32_t *__restrict__ ac,
+                                                           uint64_t na, const K *__restrict__ bk,
+                                                           const uint32_t *__restrict__ bc, uint64_t nb,
+                                                           const uint64_t *__restrict__ splits,
+                                                           K *__restrict__ ck, uint32_t *__restrict__ cc) {
+    __shared__ K s_k[MG_TILE];  // the tile's inputs: its A records, then its B records
+    __shared__ uint32_t s_c[MG_TILE];
+    __shared__ K s_ok[MG_TILE];  // the tile's outputs
+    __shared__ uint32_t s_oc[MG_TILE];
+    const int tid = threadIdx.x;
+    const uint64_t d0 = (uint64_t)blockIdx.x * MG_TILE, d1 = min(d0 + MG_TILE, na + nb);
+    const uint64_t i0 = splits[blockIdx.x], i1 = splits[blockIdx.x + 1];
+    const uint32_t la = (uint32_t)(i1 - i0), lb = (uint32_t)((d1 - i1) - (d0 - i0));  // la + lb = d1 - d0
+    const uint64_t j0 = d0 - i0;
+    // the tile's A records, then its B records
+    for (uint32_t u = tid; u < la; u += MG_THREADS) {
+        s_k[u] = ak[i0 + u];
+        s_c[u] = ac[i0 + u];
+    }
+    for (uint32_t u = tid; u < lb; u += MG_THREADS) {
+        s_k[la + u] = bk[j0 + u];
+        s_c[la + u] = bc[j0 + u];
+    }
+    __syncthreads();
+    const uint32_t n = la + lb, t0 = (uint32_t)tid * MG_ITEMS;
+    if (t0 < n) {
+        uint32_t i = (uint32_t)merge_split<K>(la, lb, t0, [&](uint64_t x) { return s_k[x]; },
+                                              [&](uint64_t y) { return s_k[la + y]; });
+        uint32_t j = t0 - i;
+        const uint32_t m = min((uint32_t)MG_ITEMS, n - t0);  // outputs of this thread
+        for (uint32_t u = 0; u < m; u++) {
+            const bool take_a = j >= lb || (i < la && key_le(s_k[i], s_k[la + j]));
+            const uint32_t x = take_a ? i : la + j;
+            s_ok[t0 + u] = s_k[x];
+            s_oc[t0 + u] = s_c[x];
+            i += take_a ? 1u : 0u;
+            j += take_a ? 0u : 1u;
         }
+    }
+    __syncthreads();
+    for (uint32_t u = tid; u < n; u += MG_THREADS) {
+        ck[d0 + u] = s_ok[u];
+        cc[d0 + u] = s_oc[u];
     }
 }
 
@@ -140,11 +184,17 @@ hipError_t merge_compact_impl(const K *ak, const uint32_t *ac, uint64_t na, cons
     const uint64_t n = na + nb;
     if (n == 0)
         return launch_exclusive_scan(flag, flag, 0, scan_tmp, n_out, stream);  // writes 0
-    const uint64_t per_block = (uint64_t)MG_THREADS * MG_ITEMS;
-    merge_kernel<K><<<dim3((unsigned)ceil_div(n, per_block)), dim3(MG_THREADS), 0, stream>>>(ak, ac, na, bk, bc, nb,
-                                                                                            tk_, tc);
+    // the tiles' splits live in the flag array until the heads overwrite it
+    // (it holds 2 n >= 2 (n_tiles + 1) words)
+    const uint64_t n_tiles = ceil_div(n, (uint64_t)MG_TILE);
+    uint64_t *splits = reinterpret_cast<uint64_t *>(flag);
+    merge_splits_kernel<K><<<dim3((unsigned)ceil_div(n_tiles + 1, 256)), dim3(256), 0, stream>>>(ak, na, bk, nb,
+                                                                                                n_tiles, splits);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
+        return e;
+    merge_kernel<K><<<dim3((unsigned)n_tiles), dim3(MG_THREADS), 0, stream>>>(ak, ac, na, bk, bc, nb, splits, tk_, tc);
+    if ((e = hipGetLastError()) != hipSuccess)
         return e;
     heads_kernel<K><<<grid_for(n), 256, 0, stream>>>(tk_, n, flag);
     if ((e = hipGetLastError()) != hipSuccess)
