@@ -9,6 +9,11 @@ HIP stream and keeps its device buffers -- input bases and offsets and the
 counting workspace -- for the whole life of the server, sized once for the
 budget, so admitting a job never allocates device memory.  Two workers let
 one batch's host-to-device copy and result copy overlap the other's kernels.
+Jobs reach the device through pinned host buffers of the same size (one
+host copy per job into its slice, then one transfer per batch, offsets
+rebased on the host), and results come back through a pinned buffer per
+worker (grown to the largest batch's records) into ordinary host arrays:
+copies from pageable memory ran at about 4 GB/s.
 
 Results are host arrays, identical to what a single ``tk_count_device``
 call on the job alone returns.
@@ -98,6 +103,10 @@ class Server:
                 ws=torch.empty(ws, dtype=torch.uint8, device=self.device),
                 bases=torch.empty(max(self.max_bases, 1), dtype=torch.uint8, device=self.device),
                 offsets=torch.empty(self.max_reads + 1 + self.max_libs, dtype=torch.int64, device=self.device),
+                h_bases=torch.empty(max(self.max_bases, 1), dtype=torch.uint8, pin_memory=True),
+                h_offsets=torch.empty(self.max_reads + 1 + self.max_libs, dtype=torch.int64, pin_memory=True),
+                h_keys=None,
+                h_counts=None,
                 inbox=queue.Queue(),
             )
             t = threading.Thread(target=self._work, args=(w,), daemon=True, name=f"tk-worker-{i}")
@@ -175,6 +184,16 @@ class Server:
                         fut.set_exception(e)
             self._idle.put(w)
 
+    def _pinned(self, w, name, n, dtype):
+        """Worker w's pinned host buffer `name` of at least n elements
+        (grown by half again when too small)."""
+        buf = w[name]
+        if buf is None or buf.numel() < n:
+            w[name] = None
+            buf = self.torch.empty(max(n + n // 2, 1 << 16), dtype=dtype, pin_memory=True)
+            w[name] = buf
+        return buf
+
     def _run(self, w, batch, t_start):
         torch = self.torch
         jobs = [j for j, _ in batch]
@@ -183,24 +202,42 @@ class Server:
             lb.append(lb[-1] + int(j.bases.size))
             lr.append(lr[-1] + int(j.offsets.size - 1))
         stream = w["stream"]
+        # every job into its slice of the pinned input buffers, its offsets
+        # rebased to its first base (the previous batch's transfer from these
+        # buffers ended with that batch's stream synchronisation)
+        # (host copies through torch, which runs them on its thread pool
+        # without holding the interpreter lock, so both workers' copies and
+        # the dispatcher proceed together)
+        hb, ho = w["h_bases"], w["h_offsets"]
+        ho[:1].zero_()
+        for q, j in enumerate(jobs):
+            if j.bases.size:
+                hb[lb[q]:lb[q + 1]].copy_(torch.from_numpy(j.bases))
+            if lr[q + 1] > lr[q]:
+                off = torch.from_numpy(j.offsets[1:].astype(np.uint64, copy=False).view(np.int64))
+                torch.add(off, lb[q], out=ho[lr[q] + 1:lr[q + 1] + 1])
         with torch.cuda.stream(stream):
             db = w["bases"][:lb[-1]]
             do = w["offsets"][:lr[-1] + 1]
-            # every job straight into its slice of the resident buffers; its
-            # offsets rebased to its first base on the device
-            do[:1].zero_()
-            for q, j in enumerate(jobs):
-                if j.bases.size:
-                    db[lb[q]:lb[q + 1]].copy_(torch.from_numpy(j.bases))
-                if lr[q + 1] > lr[q]:
-                    seg = do[lr[q] + 1:lr[q + 1] + 1]
-                    seg.copy_(torch.from_numpy(j.offsets[1:].astype(np.uint64, copy=False).view(np.int64)))
-                    if lb[q]:
-                        seg.add_(lb[q])
+            db.copy_(w["h_bases"][:lb[-1]], non_blocking=True)
+            do.copy_(w["h_offsets"][:lr[-1] + 1], non_blocking=True)
             res = tk_count_batch_device(db, do, lb, lr, jobs[0].k, [j.c for j in jobs], self.opts,
                                         workspace=w["ws"], stream=stream)
-            host = [(r.keys.cpu().numpy().view(np.uint64).reshape(r.n, r.key_words),
-                     r.counts.cpu().numpy().view(np.uint32), r) for r in res]
+            hk = self._pinned(w, "h_keys", sum(int(r.keys.numel()) for r in res), torch.int64)
+            hc = self._pinned(w, "h_counts", sum(int(r.counts.numel()) for r in res), torch.int32)
+            back, ok, oc = [], 0, 0
+            for r in res:
+                nk, nc = int(r.keys.numel()), int(r.counts.numel())
+                pk, pc = hk[ok:ok + nk].view(r.keys.shape), hc[oc:oc + nc]
+                pk.copy_(r.keys, non_blocking=True)
+                pc.copy_(r.counts, non_blocking=True)
+                back.append((pk, pc, r))
+                ok += nk
+                oc += nc
+            stream.synchronize()
+            # own copies: the pinned buffer serves the worker's next batch
+            host = [(pk.clone().numpy().view(np.uint64).reshape(r.n, r.key_words), pc.clone().numpy().view(np.uint32),
+                     r) for pk, pc, r in back]
         t_done = time.perf_counter()
         for (keys, counts, r), (job, fut) in zip(host, batch):
             fut.set_result(JobResult(keys, counts, r.n_windows, r.n_collected, r.n_distinct, r.n_singletons,
