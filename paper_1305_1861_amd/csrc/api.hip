@@ -413,75 +413,104 @@ void parallel_memcpy(void *dst, const void *src, size_t bytes) {
 
 }  // namespace
 
-// Copy between pageable host memory and device memory through two pinned
-// staging slices: the DMA of one slice overlaps the host-side copy of the
-// other.  Host to device: returns once every slice is on its way (ordered on
-// `stream`, before anything enqueued later); device to host: returns once
-// the data is in dst.  Pageable copies by the runtime alone ran at about
-// 4 GB/s here.
-hipError_t staged_copy(void *dst, const void *src, size_t bytes, bool to_device, hipStream_t stream) {
+class Stager {
+  public:
+    static constexpr size_t SLICE = size_t(64) << 20;
+    Stager() = default;
+    Stager(const Stager &) = delete;
+    Stager &operator=(const Stager &) = delete;
+    ~Stager() { (void)release(); }
+    hipError_t copy(void *dst, const void *src, size_t bytes, bool to_device, hipStream_t stream);
+    hipError_t release();
+
+  private:
+    hipError_t reserve(size_t slice);
+    void *pin_[2] = {nullptr, nullptr};
+    hipEvent_t ev_[2] = {nullptr, nullptr};
+    size_t cap_ = 0;
+};
+
+// Copies between pageable host memory and device memory through two pinned
+// staging slices: the DMA of one slice overlaps the multi-threaded host copy
+// of the other (the runtime's own pageable copies ran at about 4 GB/s here).
+// A slice is reused only after its last DMA has finished, whatever stream
+// that DMA was on.  Host to device: returns once the last slice's DMA is
+// enqueued on `stream` (later work on that stream sees the data); device to
+// host: returns once the data is in dst.
+hipError_t Stager::reserve(size_t slice) {
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; i++)
+        if (!ev_[i])
+            e = hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming);
+    if (e != hipSuccess || cap_ >= slice)
+        return e;
+    for (int i = 0; i < 2; i++) {
+        if ((e = hipEventSynchronize(ev_[i])) != hipSuccess)
+            return e;
+        if (pin_[i])
+            (void)hipHostFree(pin_[i]);
+        pin_[i] = nullptr;
+    }
+    cap_ = 0;
+    for (int i = 0; i < 2; i++)
+        if ((e = hipHostMalloc(&pin_[i], slice)) != hipSuccess)
+            return e;
+    cap_ = slice;
+    return hipSuccess;
+}
+
+hipError_t Stager::copy(void *dst, const void *src, size_t bytes, bool to_device, hipStream_t stream) {
     if (!bytes)
         return hipSuccess;
-    constexpr size_t SLICE = size_t(64) << 20;
-    void *pin[2] = {nullptr, nullptr};
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    hipError_t e = hipSuccess;
+    hipError_t e = reserve(std::min(bytes, SLICE));
+    if (e != hipSuccess)
+        return e;
     const size_t n_slices = (bytes + SLICE - 1) / SLICE;
-    const size_t nbuf = std::min<size_t>(2, n_slices);
-    for (size_t i = 0; i < nbuf && e == hipSuccess; i++) {
-        e = hipHostMalloc(&pin[i], std::min(bytes, SLICE));
-        if (e == hipSuccess)
-            e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
-    }
-    auto slice = [&](size_t i, size_t &off, size_t &len) {
-        off = i * SLICE;
-        len = std::min(SLICE, bytes - off);
+    auto drain = [&](size_t i) -> hipError_t {  // device to host: slice i from its slot to dst
+        const size_t off = i * SLICE, len = std::min(SLICE, bytes - off);
+        hipError_t w = hipEventSynchronize(ev_[i % 2]);
+        if (w == hipSuccess)
+            parallel_memcpy(static_cast<char *>(dst) + off, pin_[i % 2], len);
+        return w;
     };
-    for (size_t i = 0; i < n_slices && e == hipSuccess; i++) {
-        size_t off, len;
-        slice(i, off, len);
+    for (size_t i = 0; i < n_slices; i++) {
+        const size_t off = i * SLICE, len = std::min(SLICE, bytes - off);
         const int b = (int)(i % 2);
+        if ((e = hipEventSynchronize(ev_[b])) != hipSuccess)  // the slot's last DMA
+            return e;
         if (to_device) {
-            // the slot is free once the DMA of slice i - 2 has finished
-            if ((e = hipEventSynchronize(ev[b])) != hipSuccess)
-                break;
-            parallel_memcpy(pin[b], static_cast<const char *>(src) + off, len);
-            if ((e = hipMemcpyAsync(static_cast<char *>(dst) + off, pin[b], len, hipMemcpyHostToDevice, stream)) !=
-                hipSuccess)
-                break;
-            e = hipEventRecord(ev[b], stream);
+            parallel_memcpy(pin_[b], static_cast<const char *>(src) + off, len);
+            if ((e = hipMemcpyAsync(static_cast<char *>(dst) + off, pin_[b], len, hipMemcpyHostToDevice, stream)) !=
+                    hipSuccess ||
+                (e = hipEventRecord(ev_[b], stream)) != hipSuccess)
+                return e;
         } else {
-            if ((e = hipMemcpyAsync(pin[b], static_cast<const char *>(src) + off, len, hipMemcpyDeviceToHost,
+            if ((e = hipMemcpyAsync(pin_[b], static_cast<const char *>(src) + off, len, hipMemcpyDeviceToHost,
                                     stream)) != hipSuccess ||
-                (e = hipEventRecord(ev[b], stream)) != hipSuccess)
-                break;
-            if (i > 0) {  // slice i - 1 is drained while slice i travels
-                size_t po, pl;
-                slice(i - 1, po, pl);
-                if ((e = hipEventSynchronize(ev[1 - b])) != hipSuccess)
-                    break;
-                parallel_memcpy(static_cast<char *>(dst) + po, pin[1 - b], pl);
-            }
+                (e = hipEventRecord(ev_[b], stream)) != hipSuccess)
+                return e;
+            if (i > 0 && (e = drain(i - 1)) != hipSuccess)  // slice i - 1 while slice i travels
+                return e;
         }
     }
-    if (e == hipSuccess && !to_device) {
-        size_t po, pl;
-        slice(n_slices - 1, po, pl);
-        e = hipEventSynchronize(ev[(n_slices - 1) % 2]);
-        if (e == hipSuccess)
-            parallel_memcpy(static_cast<char *>(dst) + po, pin[(n_slices - 1) % 2], pl);
-    }
-    // the staging slices are released only after their last DMA
-    for (size_t i = 0; i < 2; i++) {
-        if (ev[i]) {
-            const hipError_t w = hipEventSynchronize(ev[i]);
+    return to_device ? hipSuccess : drain(n_slices - 1);
+}
+
+hipError_t Stager::release() {
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2; i++) {
+        if (ev_[i]) {
+            const hipError_t w = hipEventSynchronize(ev_[i]);  // the slot's last DMA
             if (e == hipSuccess)
                 e = w;
-            (void)hipEventDestroy(ev[i]);
+            (void)hipEventDestroy(ev_[i]);
+            ev_[i] = nullptr;
         }
-        if (pin[i])
-            (void)hipHostFree(pin[i]);
+        if (pin_[i])
+            (void)hipHostFree(pin_[i]);
+        pin_[i] = nullptr;
     }
+    cap_ = 0;
     return e;
 }
 
@@ -1039,7 +1068,9 @@ tk_status tk_count(const uint8_t *bases, const uint64_t *offsets, uint64_t n_rea
     void *d_ws = nullptr;
     tk_result *res = nullptr;
     hipStream_t s = nullptr;
+    Stager stage;  // pinned slices of the host copies
     auto cleanup = [&]() {
+        (void)stage.release();
         if (d_bases) (void)hipFree(d_bases);
         if (d_offsets) (void)hipFree(d_offsets);
         if (d_ws) (void)hipFree(d_ws);
@@ -1065,7 +1096,7 @@ tk_status tk_count(const uint8_t *bases, const uint64_t *offsets, uint64_t n_rea
         return dev_fail("hipMalloc(offsets)", e);
     if ((e = hipMalloc(&d_ws, p.total ? p.total : 256)) != hipSuccess)
         return dev_fail("hipMalloc(workspace)", e);
-    if ((e = staged_copy(d_bases, bases, n_bases, true, s)) != hipSuccess)
+    if ((e = stage.copy(d_bases, bases, n_bases, true, s)) != hipSuccess)
         return dev_fail("copy of the reads", e);
     if ((e = hipMemcpyAsync(d_offsets, offsets, (n_reads + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s)) !=
         hipSuccess)
@@ -1092,9 +1123,9 @@ tk_status tk_count(const uint8_t *bases, const uint64_t *offsets, uint64_t n_rea
         free(res);
         return fail(TK_ENOMEM, "result allocation failed");
     }
-    if ((e = staged_copy(res->keys, dev.keys, dev.n * dev.key_words * sizeof(uint64_t), false, s)) != hipSuccess)
+    if ((e = stage.copy(res->keys, dev.keys, dev.n * dev.key_words * sizeof(uint64_t), false, s)) != hipSuccess)
         return dev_fail("copy of the keys", e);
-    if ((e = staged_copy(res->counts, dev.counts, dev.n * sizeof(uint32_t), false, s)) != hipSuccess)
+    if ((e = stage.copy(res->counts, dev.counts, dev.n * sizeof(uint32_t), false, s)) != hipSuccess)
         return dev_fail("copy of the counts", e);
     if ((e = hipStreamSynchronize(s)) != hipSuccess)
         return dev_fail("hipStreamSynchronize", e);
@@ -1189,8 +1220,10 @@ tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_
     uint64_t *h_packed = nullptr;
     uint32_t *h_valid = nullptr;
     uint64_t *h_roff = nullptr;  // relative read offsets of two chunks (pinned)
+    Stager up;                   // pinned slices of the reads' and the answer's copies
     tk_result *res = nullptr;
     auto cleanup = [&]() {
+        (void)up.release();
         if (s) (void)hipStreamSynchronize(s);
         if (cs) (void)hipStreamSynchronize(cs);
         if (ws) (void)hipFree(ws);
@@ -1281,7 +1314,7 @@ tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_
             ro[r - r0] = offsets[r] - b0;
         if ((e = hipEventSynchronize(ev[1])) != hipSuccess)
             return e;
-        if (nb && (e = hipMemcpyAsync(d_bases, bases + b0, nb, hipMemcpyHostToDevice, cs)) != hipSuccess)
+        if ((e = up.copy(d_bases, bases + b0, nb, true, cs)) != hipSuccess)
             return e;
         if ((e = hipMemcpyAsync(d_offs, ro, (r1 - r0 + 1) * 8, hipMemcpyHostToDevice, cs)) != hipSuccess)
             return e;
@@ -1411,8 +1444,8 @@ tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_
     res->counts = static_cast<uint32_t *>(malloc((n_out ? n_out : 1) * sizeof(uint32_t)));
     if (!res->keys || !res->counts)
         return dev_fail("result allocation", hipErrorOutOfMemory);
-    TK_PH(staged_copy(res->keys, tmp_k, n_out * kb, false, s), "copy keys");
-    TK_PH(staged_copy(res->counts, tmp_c, n_out * 4, false, s), "copy counts");
+    TK_PH(up.copy(res->keys, tmp_k, n_out * kb, false, s), "copy keys");
+    TK_PH(up.copy(res->counts, tmp_c, n_out * 4, false, s), "copy counts");
     TK_PH(hipStreamSynchronize(s), "sync");
 #undef TK_PH
     cleanup();
