@@ -64,7 +64,8 @@ class Server:
     larger job is refused); ``max_batch_reads`` bounds its reads;
     ``max_batch_libs`` its number of jobs.  Device memory per worker: the
     input buffers plus the workspace of the largest batch these bounds
-    allow.
+    allow.  Pinned host memory per worker: input buffers of the same size,
+    and a result buffer grown to the largest batch's records seen so far.
     """
 
     def __init__(self, max_batch_bases: int = 1 << 28, max_batch_reads: int = 1 << 22, max_batch_libs: int = 64,
