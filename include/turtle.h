@@ -204,7 +204,9 @@ TK_API const char *tk_last_error(void);
  *   k       : 1..63;  c : threshold >= 1;  opts : NULL for defaults.
  * On success *out receives a library-allocated result whose keys/counts are
  * host arrays; release it with tk_result_free.  Device memory is allocated
- * and freed inside the call on the current HIP device.
+ * and freed inside the call on the current HIP device; the reads and the
+ * records cross PCIe through two pinned 64 MB host slices, also released
+ * before the call returns.
  */
 TK_API tk_status tk_count(const uint8_t *bases, const uint64_t *offsets,
                    uint64_t n_reads, int k, uint32_t c,
@@ -289,6 +291,10 @@ TK_API tk_status tk_count_batch_device(const uint8_t *d_bases, const uint64_t *d
  * Device memory is bounded by the chunk size and the SAC capacity, not by
  * the library size; the result does not depend on chunk_bases and equals
  * tk_count's with TK_FLAG_GLOBAL_FILTER (same filter, same statistics).
+ * Host memory: when c >= 2 every chunk is packed once, in pass 1, and its
+ * packed words and validity bits (0.5 byte per base) wait in pinned host
+ * memory for pass 2; host copies go through two pinned 64 MB slices.  Both
+ * are released before the call returns.
  * *out is allocated as in tk_count (free with tk_result_free);
  * *device_bytes (may be NULL) receives the device memory used.
  * Errors: as tk_count; TK_ENOMEM also when the SAC outgrows sac_capacity.
