@@ -334,23 +334,25 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                     // read together, then the first-plane atomics of the
                     // words that need them are issued together, so that a
                     // key waits for LDS three times rather than nine
-                    uint64_t m[4], t[4], o[4];
+                    uint64_t m[4], o[4];
+                    uint32_t need = 0;  // bit w: word w lacks some of its bits in the second plane
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
                         m[w] = s_table[(h >> (w * tbits)) & tmask];
-                        t[w] = b[(4 + w) * blocks_cut];
+                        const uint64_t t = b[(4 + w) * blocks_cut];
+                        need |= (uint32_t)((t & m[w]) != m[w]) << w;
                     }
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
                         o[w] = m[w];
-                        if ((t[w] & m[w]) != m[w])
+                        if ((need >> w) & 1u)
                             o[w] = atomicOr((unsigned long long *)(b + w * blocks_cut), (unsigned long long)m[w]);
                     }
                     bool seen = true;
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
                         const uint64_t hit = o[w] & m[w];
-                        if ((t[w] & m[w]) != m[w] && hit)
+                        if (((need >> w) & 1u) && hit)
                             atomicOr((unsigned long long *)(b + (4 + w) * blocks_cut), (unsigned long long)hit);
                         seen &= hit == m[w];
                     }
@@ -968,6 +970,36 @@ __global__ void fb_fold(const DevCounters *__restrict__ c, unsigned long long *_
 
 // ---- gather: records of every bucket, in bucket order, into place ---------
 
+// One wave copies n records from src to dst, four per lane in flight: every
+// load of a round is issued before its stores.
+template <typename R>
+__device__ __forceinline__ void gather_records(const R *__restrict__ gk, const uint32_t *__restrict__ gc, uint64_t src,
+                                               uint64_t dst, uint32_t n, R *__restrict__ ok,
+                                               uint32_t *__restrict__ oc) {
+    constexpr int U = 4;
+    const uint32_t lane = lane_id();
+    for (uint32_t i0 = 0; i0 < n; i0 += U * WAVE) {
+        R kv[U];
+        uint32_t cv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint32_t i = i0 + (uint32_t)u * WAVE + lane;
+            if (i < n) {
+                kv[u] = gk[src + i];
+                cv[u] = gc[src + i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint32_t i = i0 + (uint32_t)u * WAVE + lane;
+            if (i < n) {
+                ok[dst + i] = kv[u];
+                oc[dst + i] = cv[u];
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void gather_kernel(const uint32_t *__restrict__ rec_start,
                                                      const uint32_t *__restrict__ rec_nout,
                                                      const uint32_t *__restrict__ rec_off, uint64_t n_buckets,
@@ -981,15 +1013,11 @@ __global__ __launch_bounds__(256) void gather_kernel(const uint32_t *__restrict_
     if (!n)
         return;
     const uint64_t src = rec_start[b], dst = rec_off[b];
-    for (uint32_t i = lane_id(); i < n; i += WAVE) {
-        out_counts[dst + i] = gap_counts[src + i];
-        if (key_words == 1) {
-            out_keys[dst + i] = gap_keys[src + i];
-        } else {
-            const ulonglong2 *s = reinterpret_cast<const ulonglong2 *>(gap_keys);
-            reinterpret_cast<ulonglong2 *>(out_keys)[dst + i] = s[src + i];
-        }
-    }
+    if (key_words == 1)
+        gather_records(gap_keys, gap_counts, src, dst, n, out_keys, out_counts);
+    else
+        gather_records(reinterpret_cast<const ulonglong2 *>(gap_keys), gap_counts, src, dst, n,
+                       reinterpret_cast<ulonglong2 *>(out_keys), out_counts);
 }
 
 // Per-library counters; one thread per library.
