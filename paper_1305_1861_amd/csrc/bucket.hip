@@ -5,17 +5,25 @@
 // filter of one bucket fits in LDS and is touched by one workgroup only -- the
 // GPU counterpart of the paper's per-consumer filters (§2.1, parallelization:
 // a k-mer always meets the same filter because it is routed by a function of
-// its value).  Within a bucket (§2.1 PBF, sorting and compaction, Algorithm 1):
-//   screen : for each window, old = atomicOr(S[w], m_w); atomicOr(T[w], old & m_w)
-//   collect: a window survives iff all its pattern bits hold in T
-//   sort   : LSD radix sort of the survivors on the bits below the bucket
-//            digit (keys in registers, LDS as exchange buffer)
+// its value).  Within a group of whole buckets (§2.1 PBF, sorting and
+// compaction, Algorithm 1):
+//   screen : per window and pattern word, old = atomicOr(S[w], m_w) and
+//            atomicOr(T[w], old & m_w) -- skipped when T[w] already holds
+//            m_w, since bits are only ever set and T is a subset of S;
+//   collect: a window survives iff all its pattern bits hold in T (decided
+//            in the screen for the windows that found them all set);
+//   sort   : one MSD pass on the top bits of (bucket - first bucket, key
+//            bits below the bucket digit) into 4096 bins, then the bins that
+//            hold different keys ordered one wave per bin (LSD passes only
+//            for groups whose bins are too large for that);
 //   compact: run-length compaction, threshold c, (key, count) records written
-//            at the bucket's start index (gathered into place afterwards).
+//            at the group's first window index (gathered into place after).
 //
-// A persistent workgroup streams through a contiguous range of buckets.  A
-// bucket with more windows than fit in registers is recorded for the
-// fallback path (global-memory kernels with the same filter semantics).
+// Groups are planned before the launch (plan_groups: whole buckets of one
+// library within the register and filter capacity); persistent workgroups
+// take chunks of groups from a counter.  A bucket with more windows than fit
+// in registers is listed for the fallback path (global-memory kernels with
+// the same filter semantics).
 #include "device.hpp"
 #include "internal.hpp"
 
