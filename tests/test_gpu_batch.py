@@ -122,6 +122,26 @@ def test_many_small_libraries(tk, oracle_lib):
         check_library(oracle_lib, b, o, 31, 2, keys, counts, r)
 
 
+def test_thousands_of_tiny_libraries(tk, oracle_lib):
+    """3000 libraries: every third one empty, the others one to five reads
+    (some repeated, so that k-mers recur), thresholds 1, 2 and 3 in turn."""
+    rng = np.random.default_rng(31)
+    libs, cs = [], []
+    for j in range(3000):
+        if j % 3 == 0:
+            libs.append((np.zeros(0, np.uint8), np.zeros(1, np.uint64)))
+        else:
+            b, o = readsim.random_reads(20000 + j, int(rng.integers(1, 6)), 0, 60, n_rate=0.01)
+            reads = readsim.to_strings(b, o)
+            libs.append(readsim.from_strings(reads + reads[: int(rng.integers(0, len(reads) + 1))]))
+        cs.append(1 + j % 3)
+    case("3000 tiny libraries k=21")
+    out = run_batch(tk, libs, 21, cs)
+    assert len(out) == len(libs)
+    for (b, o), c, (keys, counts, r) in zip(libs, cs, out):
+        check_library(oracle_lib, b, o, 21, c, keys, counts, r)
+
+
 @pytest.mark.parametrize("part_bits", [2, 6])
 def test_batch_oversized_buckets(tk, oracle_lib, part_bits):
     """Oversized buckets in several libraries at once go through the
