@@ -8,7 +8,15 @@ times its count in one tile, which the oracle computes on the tile alone;
 with c = 2 every k-mer of the tile is in the answer.  Most buckets hold
 more windows than a workgroup (each k-mer occurs T times), so the run also
 drives the global-memory fallback at full size.  Device memory: 4.3 GB of
-reads and a 162 GB workspace."""
+reads and a 162 GB workspace.
+
+A second case takes two-word keys (k = 63) past 2^31 windows, so that
+their 64-bit word offsets pass 2^32: one read of 3e9 bases, a random tile
+of 10^6 bases repeated R = 3000 times.  Window p is the tile's cyclic
+k-mer at p mod 10^6, so a key's count is R times its multiplicity among
+the tile's cyclic windows less its multiplicity among the k - 1 windows
+that wrap (those occur R - 1 times); the oracle counts both on short
+strings.  Device memory: 3 GB of reads and a 186 GB workspace."""
 import gc
 import sys
 
@@ -66,3 +74,42 @@ def test_largest_accepted_library(tk, oracle_lib):
     assert keys.size == ora.lo.size
     assert np.array_equal(keys, ora.lo)
     assert np.array_equal(counts.astype(np.uint64), ora.count * np.uint64(T))
+
+
+def test_longest_read_two_word_keys(tk, oracle_lib):
+    import torch
+    P, R, k = 1_000_000, 3000, 63
+    rng = np.random.default_rng(6363)
+    tile = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, P)]
+    cyc = np.concatenate([tile, tile[:k - 1]])  # every cyclic window once
+    wrap = cyc[P - k + 1:]                     # the k - 1 windows that wrap
+    one = lambda x: np.array([0, x.size], np.uint64)  # noqa: E731
+    m = oracle_lib.kmer_count(cyc, one(cyc), k, 1)
+    w = oracle_lib.kmer_count(wrap, one(wrap), k, 1)
+    mk = (m.hi.astype(object) << 64) | m.lo.astype(object)
+    wk = (w.hi.astype(object) << 64) | w.lo.astype(object)
+    pos = np.searchsorted(mk, wk)
+    assert (mk[pos] == wk).all()
+    want = m.count * np.uint64(R)
+    np.subtract.at(want, pos, w.count)
+    n_bases = P * R
+    case(f"longest read: k={k}, n_bases={n_bases}, tile distinct={m.lo.size}")
+    gc.collect()
+    torch.cuda.empty_cache()
+    db = torch.from_numpy(np.tile(tile, R)).cuda()
+    do = torch.tensor([0, n_bases], dtype=torch.int64).cuda()
+    ws = torch.empty(tk.tk_workspace_size(n_bases, 1, k, C), dtype=torch.uint8, device="cuda")
+    case(f"longest read: workspace {ws.numel() / 1e9:.1f} GB, counting")
+    r = tk.tk_count_device(db, do, k, C, workspace=ws)
+    torch.cuda.synchronize()
+    keys = r.keys.cpu().numpy().view(np.uint64).reshape(-1, 2).copy()
+    counts = r.counts.cpu().numpy().view(np.uint32).copy()
+    n_windows = r.n_windows
+    case(f"longest read: {keys.shape[0]} records, {r.n_fallback} oversized buckets")
+    del r, ws, db, do
+    gc.collect()
+    torch.cuda.empty_cache()
+    assert n_windows == n_bases - k + 1 > 1 << 31
+    assert keys.shape[0] == m.lo.size
+    assert np.array_equal(keys[:, 0], m.hi) and np.array_equal(keys[:, 1], m.lo)
+    assert np.array_equal(counts.astype(np.uint64), want)
