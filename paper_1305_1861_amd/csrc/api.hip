@@ -401,12 +401,20 @@ void parallel_memcpy(void *dst, const void *src, size_t bytes) {
     }
     std::vector<std::thread> pool;
     const size_t step = (bytes + parts - 1) / parts;
+    auto part = [=](size_t a, size_t b) {
+        memcpy(static_cast<char *>(dst) + a, static_cast<const char *>(src) + a, b - a);
+    };
     for (size_t i = 1; i < parts; i++) {
         const size_t a = i * step, b = std::min(bytes, a + step);
-        if (a < b)
-            pool.emplace_back([=] { memcpy(static_cast<char *>(dst) + a, static_cast<const char *>(src) + a, b - a); });
+        if (a >= b)
+            continue;
+        try {  // no exception may cross the C boundary: a part without a thread is copied here
+            pool.emplace_back(part, a, b);
+        } catch (...) {
+            part(a, b);
+        }
     }
-    memcpy(dst, src, std::min(bytes, step));
+    part(0, std::min(bytes, step));
     for (auto &t : pool)
         t.join();
 }
