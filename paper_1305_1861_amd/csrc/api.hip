@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <tuple>
 #include <vector>
@@ -916,6 +917,23 @@ tk_status run_count(const uint8_t *d_bases, const uint64_t *d_offsets, const Pla
 
 using namespace tk;
 
+namespace {
+
+// Entry points return a status: a C++ exception (a host allocation that
+// fails, a thread that cannot start) never leaves the library.
+template <typename F>
+tk_status guarded(F &&body) {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(TK_ENOMEM, "host memory allocation failed");
+    } catch (...) {
+        return fail(TK_EDEVICE, "unexpected host-side error");
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 tk_status tk_default_options(tk_options *opts) {
@@ -945,520 +963,538 @@ const char *tk_last_error(void) { return g_err; }
 
 tk_status tk_workspace_size(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const tk_options *opts,
                             size_t *bytes) {
-    if (!bytes)
-        return fail(TK_EINVAL, "bytes is NULL");
-    Plan p;
-    tk_status st = make_plan(n_bases, n_reads, k, c, opts, &p);
-    if (st != TK_OK)
-        return st;
-    *bytes = p.total;
-    return TK_OK;
+    return guarded([&]() -> tk_status {
+        if (!bytes)
+            return fail(TK_EINVAL, "bytes is NULL");
+        Plan p;
+        tk_status st = make_plan(n_bases, n_reads, k, c, opts, &p);
+        if (st != TK_OK)
+            return st;
+        *bytes = p.total;
+        return TK_OK;
+    });
 }
 
 tk_status tk_bloom_blocks(uint64_t n_bases, uint64_t n_reads, int k, const tk_options *opts, uint64_t *n_blocks) {
-    if (!n_blocks)
-        return fail(TK_EINVAL, "n_blocks is NULL");
-    if (k < 1 || k > 63)
-        return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
-    Opts o;
-    tk_status st = resolve(opts, &o);
-    if (st != TK_OK)
-        return st;
-    *n_blocks = bloom_blocks_for(n_bases, n_reads, k, o);
-    return TK_OK;
+    return guarded([&]() -> tk_status {
+        if (!n_blocks)
+            return fail(TK_EINVAL, "n_blocks is NULL");
+        if (k < 1 || k > 63)
+            return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
+        Opts o;
+        tk_status st = resolve(opts, &o);
+        if (st != TK_OK)
+            return st;
+        *n_blocks = bloom_blocks_for(n_bases, n_reads, k, o);
+        return TK_OK;
+    });
 }
 
 tk_status tk_part_bits(uint64_t n_bases, uint64_t n_reads, int k, const tk_options *opts, int *part_bits) {
-    if (!part_bits)
-        return fail(TK_EINVAL, "part_bits is NULL");
-    if (k < 1 || k > 63)
-        return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
-    Opts o;
-    tk_status st = resolve(opts, &o);
-    if (st != TK_OK)
-        return st;
-    *part_bits = part_bits_for(n_bases, n_reads, k, o);
-    return TK_OK;
+    return guarded([&]() -> tk_status {
+        if (!part_bits)
+            return fail(TK_EINVAL, "part_bits is NULL");
+        if (k < 1 || k > 63)
+            return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
+        Opts o;
+        tk_status st = resolve(opts, &o);
+        if (st != TK_OK)
+            return st;
+        *part_bits = part_bits_for(n_bases, n_reads, k, o);
+        return TK_OK;
+    });
 }
 
 tk_status tk_pattern_table(const tk_options *opts, uint64_t *masks, uint64_t capacity) {
-    Opts o;
-    tk_status st = resolve(opts, &o);
-    if (st != TK_OK)
-        return st;
-    const auto &t = pattern_table(o.seed, o.table_bits, o.bits);
-    if (!masks || capacity < t.size())
-        return fail(TK_EINVAL, "pattern table needs %zu entries", t.size());
-    memcpy(masks, t.data(), t.size() * sizeof(uint64_t));
-    return TK_OK;
+    return guarded([&]() -> tk_status {
+        Opts o;
+        tk_status st = resolve(opts, &o);
+        if (st != TK_OK)
+            return st;
+        const auto &t = pattern_table(o.seed, o.table_bits, o.bits);
+        if (!masks || capacity < t.size())
+            return fail(TK_EINVAL, "pattern table needs %zu entries", t.size());
+        memcpy(masks, t.data(), t.size() * sizeof(uint64_t));
+        return TK_OK;
+    });
 }
 
 tk_status tk_count_device(const uint8_t *d_bases, const uint64_t *d_offsets, uint64_t n_bases, uint64_t n_reads,
                           int k, uint32_t c, const tk_options *opts, void *d_workspace, size_t ws_bytes,
                           void *stream, tk_result *out) {
-    if (!out)
-        return fail(TK_EINVAL, "out is NULL");
-    if (!d_offsets)
-        return fail(TK_EINVAL, "offsets is NULL");
-    if (n_bases && !d_bases)
-        return fail(TK_EINVAL, "bases is NULL");
-    if (!d_workspace)
-        return fail(TK_EINVAL, "workspace is NULL");
-    if ((uintptr_t)d_workspace & 255u)
-        return fail(TK_EINVAL, "workspace must be 256-byte aligned");
-    Plan p;
-    tk_status st = make_plan(n_bases, n_reads, k, c, opts, &p);
-    if (st != TK_OK)
-        return st;
-    if (ws_bytes < p.total)
-        return fail(TK_EINVAL, "workspace of %zu bytes is below the %zu needed", ws_bytes, p.total);
-    return run_count(d_bases, d_offsets, p, static_cast<char *>(d_workspace), static_cast<hipStream_t>(stream),
-                     out);
+    return guarded([&]() -> tk_status {
+        if (!out)
+            return fail(TK_EINVAL, "out is NULL");
+        if (!d_offsets)
+            return fail(TK_EINVAL, "offsets is NULL");
+        if (n_bases && !d_bases)
+            return fail(TK_EINVAL, "bases is NULL");
+        if (!d_workspace)
+            return fail(TK_EINVAL, "workspace is NULL");
+        if ((uintptr_t)d_workspace & 255u)
+            return fail(TK_EINVAL, "workspace must be 256-byte aligned");
+        Plan p;
+        tk_status st = make_plan(n_bases, n_reads, k, c, opts, &p);
+        if (st != TK_OK)
+            return st;
+        if (ws_bytes < p.total)
+            return fail(TK_EINVAL, "workspace of %zu bytes is below the %zu needed", ws_bytes, p.total);
+        return run_count(d_bases, d_offsets, p, static_cast<char *>(d_workspace), static_cast<hipStream_t>(stream),
+                         out);
+    });
 }
 
 tk_status tk_batch_workspace_size(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *lib_reads, int k,
                                   const uint32_t *c, const tk_options *opts, size_t *bytes) {
-    if (!bytes)
-        return fail(TK_EINVAL, "bytes is NULL");
-    Plan p;
-    tk_status st = make_plan(n_libs, lib_bases, lib_reads, k, c, opts, &p);
-    if (st != TK_OK)
-        return st;
-    *bytes = p.total;
-    return TK_OK;
+    return guarded([&]() -> tk_status {
+        if (!bytes)
+            return fail(TK_EINVAL, "bytes is NULL");
+        Plan p;
+        tk_status st = make_plan(n_libs, lib_bases, lib_reads, k, c, opts, &p);
+        if (st != TK_OK)
+            return st;
+        *bytes = p.total;
+        return TK_OK;
+    });
 }
 
 tk_status tk_count_batch_device(const uint8_t *d_bases, const uint64_t *d_offsets, uint64_t n_libs,
                                 const uint64_t *lib_bases, const uint64_t *lib_reads, int k, const uint32_t *c,
                                 const tk_options *opts, void *d_workspace, size_t ws_bytes, void *stream,
                                 tk_result *out) {
-    if (!out)
-        return fail(TK_EINVAL, "out is NULL");
-    if (!d_offsets)
-        return fail(TK_EINVAL, "offsets is NULL");
-    if (!d_workspace)
-        return fail(TK_EINVAL, "workspace is NULL");
-    if ((uintptr_t)d_workspace & 255u)
-        return fail(TK_EINVAL, "workspace must be 256-byte aligned");
-    Plan p;
-    tk_status st = make_plan(n_libs, lib_bases, lib_reads, k, c, opts, &p);
-    if (st != TK_OK)
-        return st;
-    if (p.n_bases && !d_bases)
-        return fail(TK_EINVAL, "bases is NULL");
-    if (ws_bytes < p.total)
-        return fail(TK_EINVAL, "workspace of %zu bytes is below the %zu needed", ws_bytes, p.total);
-    return run_count(d_bases, d_offsets, p, static_cast<char *>(d_workspace), static_cast<hipStream_t>(stream),
-                     out);
+    return guarded([&]() -> tk_status {
+        if (!out)
+            return fail(TK_EINVAL, "out is NULL");
+        if (!d_offsets)
+            return fail(TK_EINVAL, "offsets is NULL");
+        if (!d_workspace)
+            return fail(TK_EINVAL, "workspace is NULL");
+        if ((uintptr_t)d_workspace & 255u)
+            return fail(TK_EINVAL, "workspace must be 256-byte aligned");
+        Plan p;
+        tk_status st = make_plan(n_libs, lib_bases, lib_reads, k, c, opts, &p);
+        if (st != TK_OK)
+            return st;
+        if (p.n_bases && !d_bases)
+            return fail(TK_EINVAL, "bases is NULL");
+        if (ws_bytes < p.total)
+            return fail(TK_EINVAL, "workspace of %zu bytes is below the %zu needed", ws_bytes, p.total);
+        return run_count(d_bases, d_offsets, p, static_cast<char *>(d_workspace), static_cast<hipStream_t>(stream),
+                         out);
+    });
 }
 
 tk_status tk_count(const uint8_t *bases, const uint64_t *offsets, uint64_t n_reads, int k, uint32_t c,
                    const tk_options *opts, tk_result **out) {
-    if (!out)
-        return fail(TK_EINVAL, "out is NULL");
-    if (!offsets)
-        return fail(TK_EINVAL, "offsets is NULL");
-    if (offsets[0] != 0)
-        return fail(TK_EINVAL, "offsets[0] must be 0");
-    for (uint64_t r = 0; r < n_reads; r++)
-        if (offsets[r + 1] < offsets[r])
-            return fail(TK_EINVAL, "offsets decrease at read %llu", (unsigned long long)r);
-    const uint64_t n_bases = offsets[n_reads];
-    if (n_bases && !bases)
-        return fail(TK_EINVAL, "bases is NULL");
-    Plan p;
-    tk_status st = make_plan(n_bases, n_reads, k, c, opts, &p);
-    if (st != TK_OK)
-        return st;
-
-    uint8_t *d_bases = nullptr;
-    uint64_t *d_offsets = nullptr;
-    void *d_ws = nullptr;
-    tk_result *res = nullptr;
-    hipStream_t s = nullptr;
-    Stager stage;  // pinned slices of the host copies
-    auto cleanup = [&]() {
-        (void)stage.release();
-        if (d_bases) (void)hipFree(d_bases);
-        if (d_offsets) (void)hipFree(d_offsets);
-        if (d_ws) (void)hipFree(d_ws);
-        if (s) (void)hipStreamDestroy(s);
-    };
-    auto dev_fail = [&](const char *what, hipError_t e) {
-        cleanup();
-        if (res) {
+    return guarded([&]() -> tk_status {
+        if (!out)
+            return fail(TK_EINVAL, "out is NULL");
+        if (!offsets)
+            return fail(TK_EINVAL, "offsets is NULL");
+        if (offsets[0] != 0)
+            return fail(TK_EINVAL, "offsets[0] must be 0");
+        for (uint64_t r = 0; r < n_reads; r++)
+            if (offsets[r + 1] < offsets[r])
+                return fail(TK_EINVAL, "offsets decrease at read %llu", (unsigned long long)r);
+        const uint64_t n_bases = offsets[n_reads];
+        if (n_bases && !bases)
+            return fail(TK_EINVAL, "bases is NULL");
+        Plan p;
+        tk_status st = make_plan(n_bases, n_reads, k, c, opts, &p);
+        if (st != TK_OK)
+            return st;
+    
+        uint8_t *d_bases = nullptr;
+        uint64_t *d_offsets = nullptr;
+        void *d_ws = nullptr;
+        tk_result *res = nullptr;
+        hipStream_t s = nullptr;
+        Stager stage;  // pinned slices of the host copies
+        auto cleanup = [&]() {
+            (void)stage.release();
+            if (d_bases) (void)hipFree(d_bases);
+            if (d_offsets) (void)hipFree(d_offsets);
+            if (d_ws) (void)hipFree(d_ws);
+            if (s) (void)hipStreamDestroy(s);
+        };
+        auto dev_fail = [&](const char *what, hipError_t e) {
+            cleanup();
+            if (res) {
+                free(res->keys);
+                free(res->counts);
+                free(res);
+            }
+            if (e == hipErrorOutOfMemory)
+                return fail(TK_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+            return fail(TK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+        };
+        hipError_t e;
+        if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+            return dev_fail("hipStreamCreate", e);
+        if ((e = hipMalloc(&d_bases, n_bases ? n_bases : 1)) != hipSuccess)
+            return dev_fail("hipMalloc(bases)", e);
+        if ((e = hipMalloc(&d_offsets, (n_reads + 1) * sizeof(uint64_t))) != hipSuccess)
+            return dev_fail("hipMalloc(offsets)", e);
+        if ((e = hipMalloc(&d_ws, p.total ? p.total : 256)) != hipSuccess)
+            return dev_fail("hipMalloc(workspace)", e);
+        if ((e = stage.copy(d_bases, bases, n_bases, true, s)) != hipSuccess)
+            return dev_fail("copy of the reads", e);
+        if ((e = hipMemcpyAsync(d_offsets, offsets, (n_reads + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            return dev_fail("hipMemcpy(offsets)", e);
+    
+        tk_result dev{};
+        st = run_count(d_bases, d_offsets, p, static_cast<char *>(d_ws), s, &dev);
+        if (st != TK_OK) {
+            cleanup();
+            return st;
+        }
+        res = static_cast<tk_result *>(calloc(1, sizeof(tk_result)));
+        if (!res) {
+            cleanup();
+            return fail(TK_ENOMEM, "result allocation failed");
+        }
+        *res = dev;
+        res->keys = static_cast<uint64_t *>(malloc((dev.n ? dev.n : 1) * dev.key_words * sizeof(uint64_t)));
+        res->counts = static_cast<uint32_t *>(malloc((dev.n ? dev.n : 1) * sizeof(uint32_t)));
+        if (!res->keys || !res->counts) {
+            cleanup();
             free(res->keys);
             free(res->counts);
             free(res);
+            return fail(TK_ENOMEM, "result allocation failed");
         }
-        if (e == hipErrorOutOfMemory)
-            return fail(TK_ENOMEM, "%s: %s", what, hipGetErrorString(e));
-        return fail(TK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-    };
-    hipError_t e;
-    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
-        return dev_fail("hipStreamCreate", e);
-    if ((e = hipMalloc(&d_bases, n_bases ? n_bases : 1)) != hipSuccess)
-        return dev_fail("hipMalloc(bases)", e);
-    if ((e = hipMalloc(&d_offsets, (n_reads + 1) * sizeof(uint64_t))) != hipSuccess)
-        return dev_fail("hipMalloc(offsets)", e);
-    if ((e = hipMalloc(&d_ws, p.total ? p.total : 256)) != hipSuccess)
-        return dev_fail("hipMalloc(workspace)", e);
-    if ((e = stage.copy(d_bases, bases, n_bases, true, s)) != hipSuccess)
-        return dev_fail("copy of the reads", e);
-    if ((e = hipMemcpyAsync(d_offsets, offsets, (n_reads + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s)) !=
-        hipSuccess)
-        return dev_fail("hipMemcpy(offsets)", e);
-
-    tk_result dev{};
-    st = run_count(d_bases, d_offsets, p, static_cast<char *>(d_ws), s, &dev);
-    if (st != TK_OK) {
+        if ((e = stage.copy(res->keys, dev.keys, dev.n * dev.key_words * sizeof(uint64_t), false, s)) != hipSuccess)
+            return dev_fail("copy of the keys", e);
+        if ((e = stage.copy(res->counts, dev.counts, dev.n * sizeof(uint32_t), false, s)) != hipSuccess)
+            return dev_fail("copy of the counts", e);
+        if ((e = hipStreamSynchronize(s)) != hipSuccess)
+            return dev_fail("hipStreamSynchronize", e);
         cleanup();
-        return st;
-    }
-    res = static_cast<tk_result *>(calloc(1, sizeof(tk_result)));
-    if (!res) {
-        cleanup();
-        return fail(TK_ENOMEM, "result allocation failed");
-    }
-    *res = dev;
-    res->keys = static_cast<uint64_t *>(malloc((dev.n ? dev.n : 1) * dev.key_words * sizeof(uint64_t)));
-    res->counts = static_cast<uint32_t *>(malloc((dev.n ? dev.n : 1) * sizeof(uint32_t)));
-    if (!res->keys || !res->counts) {
-        cleanup();
-        free(res->keys);
-        free(res->counts);
-        free(res);
-        return fail(TK_ENOMEM, "result allocation failed");
-    }
-    if ((e = stage.copy(res->keys, dev.keys, dev.n * dev.key_words * sizeof(uint64_t), false, s)) != hipSuccess)
-        return dev_fail("copy of the keys", e);
-    if ((e = stage.copy(res->counts, dev.counts, dev.n * sizeof(uint32_t), false, s)) != hipSuccess)
-        return dev_fail("copy of the counts", e);
-    if ((e = hipStreamSynchronize(s)) != hipSuccess)
-        return dev_fail("hipStreamSynchronize", e);
-    cleanup();
-    *out = res;
-    return TK_OK;
+        *out = res;
+        return TK_OK;
+    });
 }
 
 tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_t n_reads, int k, uint32_t c,
                           uint64_t chunk_bases, uint64_t sac_capacity, const tk_options *opts, tk_result **out,
                           size_t *device_bytes) {
-    if (!out)
-        return fail(TK_EINVAL, "out is NULL");
-    if (!offsets)
-        return fail(TK_EINVAL, "offsets is NULL");
-    if (offsets[0] != 0)
-        return fail(TK_EINVAL, "offsets[0] must be 0");
-    for (uint64_t r = 0; r < n_reads; r++)
-        if (offsets[r + 1] < offsets[r])
-            return fail(TK_EINVAL, "offsets decrease at read %llu", (unsigned long long)r);
-    if (k < 1 || k > 63)
-        return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
-    if (c == 0)
-        return fail(TK_EINVAL, "threshold c must be >= 1");
-    if (chunk_bases == 0)
-        return fail(TK_EINVAL, "chunk_bases must be >= 1");
-    const uint64_t n_bases = offsets[n_reads];
-    if (n_bases && !bases)
-        return fail(TK_EINVAL, "bases is NULL");
-    if (n_bases >= (1ull << 32))
-        return fail(TK_EOVERFLOW, "n_bases = %llu must be below 2^32", (unsigned long long)n_bases);
-    Opts o;
-    tk_status st = resolve(opts, &o);
-    if (st != TK_OK)
-        return st;
-    if (o.shard_count > 1)
-        return fail(TK_EINVAL, "key-range shards need the partitioned path");
-    const int kw = k <= 31 ? 1 : 2;
-    const size_t kb = 8 * (size_t)kw;
-    const bool screen = c >= 2;
-    // chunks: consecutive reads of at most chunk_bases bases (a longer read
-    // alone)
-    std::vector<uint64_t> cuts{0};
-    uint64_t cb_max = 0, cr_max = 0;
-    for (uint64_t r0 = 0; r0 < n_reads;) {
-        uint64_t r1 = r0 + 1;
-        while (r1 < n_reads && offsets[r1 + 1] - offsets[r0] <= chunk_bases)
-            r1++;
-        cb_max = std::max(cb_max, offsets[r1] - offsets[r0]);
-        cr_max = std::max(cr_max, r1 - r0);
-        cuts.push_back(r1);
-        r0 = r1;
-    }
-    const uint64_t n_chunks = cuts.size() - 1;
-    const uint64_t CB = std::max<uint64_t>(cb_max, 1), CW = ceil_div(CB, 32);
-    const uint64_t sac_cap = sac_capacity ? sac_capacity : std::max<uint64_t>(n_bases, 1);
-    const uint64_t n_blocks = screen ? bloom_blocks_for(n_bases, n_reads, k, o) : 0;
-    const uint64_t merged = sac_cap + CB;  // records of one merge
-    // device memory
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t r = off;
-        off = align_up(off + bytes, 256);
-        return r;
-    };
-    const size_t o_ctr = take(2 * sizeof(DevCounters)), o_misc = take(64), o_table = take(sizeof(uint64_t) << o.table_bits);
-    const size_t o_filter = take(n_blocks * 64), o_bases = take(CB), o_offs = take((cr_max + 1) * sizeof(uint64_t));
-    const size_t o_packed = take(CW * 8), o_valid = take(CW * 4), o_starts = take(CW * 4);
-    // second packed/valid buffer: the next chunk's words arrive while this
-    // chunk is collected (second pass)
-    const size_t o_packed2 = screen ? take(CW * 8) : 0, o_valid2 = screen ? take(CW * 4) : 0;
-    const size_t o_ka = take(CB * kb), o_kb = take(CB * kb), o_rk = take(CB * kb), o_rc = take(CB * 4);
-    const size_t sort_bytes = radix_scratch_bytes(CB, kw), cmp_bytes = compact_scratch_bytes(CB);
-    const size_t o_sort = take(sort_bytes), o_cmp = take(cmp_bytes);
-    const size_t o_sk[2] = {take(merged * kb), take(merged * kb)}, o_sc[2] = {take(merged * 4), take(merged * 4)};
-    const size_t o_tk = take(merged * kb), o_tc = take(merged * 4), o_flag = take(2 * merged * 4);
-    const size_t o_scan = take(scan_scratch_words(2 * merged) * 4);
-    const size_t total = off;
-    if (device_bytes)
-        *device_bytes = total;
-
-    // packed words and validity bits of every chunk, kept in pinned host
-    // memory between the passes (0.5 B per base instead of the 1 B per base
-    // of the reads, and no pageable staging in the second pass)
-    std::vector<uint64_t> wfirst(n_chunks + 1, 0);  // first word of every chunk in the pinned arrays
-    for (uint64_t q = 0; q < n_chunks; q++)
-        wfirst[q + 1] = wfirst[q] + ceil_div(offsets[cuts[q + 1]] - offsets[cuts[q]], 32);
-
-    char *ws = nullptr;
-    hipStream_t s = nullptr, cs = nullptr;  // kernels; copies of the next chunk
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    uint64_t *h_packed = nullptr;
-    uint32_t *h_valid = nullptr;
-    uint64_t *h_roff = nullptr;  // relative read offsets of two chunks (pinned)
-    Stager up;                   // pinned slices of the reads' and the answer's copies
-    tk_result *res = nullptr;
-    auto cleanup = [&]() {
-        (void)up.release();
-        if (s) (void)hipStreamSynchronize(s);
-        if (cs) (void)hipStreamSynchronize(cs);
-        if (ws) (void)hipFree(ws);
-        for (hipEvent_t &e : ev)
-            if (e) (void)hipEventDestroy(e);
-        if (h_packed) (void)hipHostFree(h_packed);
-        if (h_valid) (void)hipHostFree(h_valid);
-        if (h_roff) (void)hipHostFree(h_roff);
-        if (cs) (void)hipStreamDestroy(cs);
-        if (s) (void)hipStreamDestroy(s);
-    };
-    auto dev_fail = [&](const char *what, hipError_t e) {
-        cleanup();
-        if (res) {
-            free(res->keys);
-            free(res->counts);
-            free(res);
+    return guarded([&]() -> tk_status {
+        if (!out)
+            return fail(TK_EINVAL, "out is NULL");
+        if (!offsets)
+            return fail(TK_EINVAL, "offsets is NULL");
+        if (offsets[0] != 0)
+            return fail(TK_EINVAL, "offsets[0] must be 0");
+        for (uint64_t r = 0; r < n_reads; r++)
+            if (offsets[r + 1] < offsets[r])
+                return fail(TK_EINVAL, "offsets decrease at read %llu", (unsigned long long)r);
+        if (k < 1 || k > 63)
+            return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
+        if (c == 0)
+            return fail(TK_EINVAL, "threshold c must be >= 1");
+        if (chunk_bases == 0)
+            return fail(TK_EINVAL, "chunk_bases must be >= 1");
+        const uint64_t n_bases = offsets[n_reads];
+        if (n_bases && !bases)
+            return fail(TK_EINVAL, "bases is NULL");
+        if (n_bases >= (1ull << 32))
+            return fail(TK_EOVERFLOW, "n_bases = %llu must be below 2^32", (unsigned long long)n_bases);
+        Opts o;
+        tk_status st = resolve(opts, &o);
+        if (st != TK_OK)
+            return st;
+        if (o.shard_count > 1)
+            return fail(TK_EINVAL, "key-range shards need the partitioned path");
+        const int kw = k <= 31 ? 1 : 2;
+        const size_t kb = 8 * (size_t)kw;
+        const bool screen = c >= 2;
+        // chunks: consecutive reads of at most chunk_bases bases (a longer read
+        // alone)
+        std::vector<uint64_t> cuts{0};
+        uint64_t cb_max = 0, cr_max = 0;
+        for (uint64_t r0 = 0; r0 < n_reads;) {
+            uint64_t r1 = r0 + 1;
+            while (r1 < n_reads && offsets[r1 + 1] - offsets[r0] <= chunk_bases)
+                r1++;
+            cb_max = std::max(cb_max, offsets[r1] - offsets[r0]);
+            cr_max = std::max(cr_max, r1 - r0);
+            cuts.push_back(r1);
+            r0 = r1;
         }
-        if (e == hipErrorOutOfMemory)
-            return fail(TK_ENOMEM, "%s: %s", what, hipGetErrorString(e));
-        return fail(TK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-    };
-#define TK_PH(call, what)                   \
-    do {                                    \
-        hipError_t e_ = (call);             \
-        if (e_ != hipSuccess)               \
-            return dev_fail(what, e_);      \
-    } while (0)
-    TK_PH(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
-    TK_PH(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
-    for (hipEvent_t &e : ev)
-        TK_PH(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
-    TK_PH(hipHostMalloc(reinterpret_cast<void **>(&h_roff), 2 * (cr_max + 1) * sizeof(uint64_t)), "hipHostMalloc");
-    if (screen && wfirst[n_chunks]) {
-        TK_PH(hipHostMalloc(reinterpret_cast<void **>(&h_packed), wfirst[n_chunks] * sizeof(uint64_t)),
-              "hipHostMalloc(packed)");
-        TK_PH(hipHostMalloc(reinterpret_cast<void **>(&h_valid), wfirst[n_chunks] * sizeof(uint32_t)),
-              "hipHostMalloc(valid)");
-    }
-    TK_PH(hipMalloc(&ws, total), "hipMalloc(workspace)");
-    DevCounters *ctr = reinterpret_cast<DevCounters *>(ws + o_ctr);  // [0] windows, collected; [1] chunk compaction
-    uint32_t *misc = reinterpret_cast<uint32_t *>(ws + o_misc);        // [0] SAC size, [1] selected
-    unsigned long long *stats = reinterpret_cast<unsigned long long *>(ws + o_misc + 16);
-    uint64_t *table = reinterpret_cast<uint64_t *>(ws + o_table);
-    uint64_t *filter = reinterpret_cast<uint64_t *>(ws + o_filter);
-    uint8_t *d_bases = reinterpret_cast<uint8_t *>(ws + o_bases);
-    uint64_t *d_offs = reinterpret_cast<uint64_t *>(ws + o_offs);
-    uint64_t *packed = reinterpret_cast<uint64_t *>(ws + o_packed);
-    uint32_t *valid = reinterpret_cast<uint32_t *>(ws + o_valid), *starts = reinterpret_cast<uint32_t *>(ws + o_starts);
-    uint64_t *packed2[2] = {packed, reinterpret_cast<uint64_t *>(ws + o_packed2)};
-    uint32_t *valid2[2] = {valid, reinterpret_cast<uint32_t *>(ws + o_valid2)};
-    uint64_t *keys_a = reinterpret_cast<uint64_t *>(ws + o_ka), *keys_b = reinterpret_cast<uint64_t *>(ws + o_kb);
-    uint64_t *run_k = reinterpret_cast<uint64_t *>(ws + o_rk);
-    uint32_t *run_c = reinterpret_cast<uint32_t *>(ws + o_rc);
-    uint64_t *sac_k[2] = {reinterpret_cast<uint64_t *>(ws + o_sk[0]), reinterpret_cast<uint64_t *>(ws + o_sk[1])};
-    uint32_t *sac_c[2] = {reinterpret_cast<uint32_t *>(ws + o_sc[0]), reinterpret_cast<uint32_t *>(ws + o_sc[1])};
-    uint64_t *tmp_k = reinterpret_cast<uint64_t *>(ws + o_tk);
-    uint32_t *tmp_c = reinterpret_cast<uint32_t *>(ws + o_tc), *flag = reinterpret_cast<uint32_t *>(ws + o_flag);
-    uint32_t *scan_tmp = reinterpret_cast<uint32_t *>(ws + o_scan);
-    TK_PH(zero_bytes(ws, o_table, s), "zero");  // counters and misc
-    if (screen) {
-        const auto &tab = pattern_table(o.seed, o.table_bits, o.bits);
-        TK_PH(hipMemcpyAsync(table, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s), "table");
-        TK_PH(zero_bytes(filter, n_blocks * 64, s), "zero filter");
-    }
-    BloomArgs ba{};
-    ba.packed = packed;
-    ba.valid = valid;
-    ba.k = k;
-    ba.table = table;
-    ba.table_bits = o.table_bits;
-    ba.n_blocks = n_blocks;
-    ba.filter = filter;
-    // Chunk q's reads and relative read offsets go to the device on the copy
-    // stream (offsets staged in pinned slot q % 2) while the kernel stream
-    // still screens the chunk before; pack then runs on the kernel stream.
-    // ev[0]: chunk copied; ev[1]: chunk packed (its reads are consumed, so
-    // the next chunk may overwrite them; the host waits for it, whatever the
-    // runtime does with pageable sources); ev[2 + q % 2]: the offsets of
-    // slot q % 2 are on the device.
-    auto send_chunk = [&](uint64_t q) -> hipError_t {
-        const uint64_t r0 = cuts[q], r1 = cuts[q + 1], b0 = offsets[r0], nb = offsets[r1] - b0;
-        uint64_t *ro = h_roff + (q % 2) * (cr_max + 1);
-        hipError_t e = hipEventSynchronize(ev[2 + q % 2]);  // slot free (chunk q - 2 sent)
-        if (e != hipSuccess)
-            return e;
-        for (uint64_t r = r0; r <= r1; r++)
-            ro[r - r0] = offsets[r] - b0;
-        if ((e = hipEventSynchronize(ev[1])) != hipSuccess)
-            return e;
-        if ((e = up.copy(d_bases, bases + b0, nb, true, cs)) != hipSuccess)
-            return e;
-        if ((e = hipMemcpyAsync(d_offs, ro, (r1 - r0 + 1) * 8, hipMemcpyHostToDevice, cs)) != hipSuccess)
-            return e;
-        if ((e = hipEventRecord(ev[2 + q % 2], cs)) != hipSuccess)
-            return e;
-        return hipEventRecord(ev[0], cs);
-    };
-    auto pack_chunk = [&](uint64_t q, bool count) -> hipError_t {
-        const uint64_t nb = offsets[cuts[q + 1]] - offsets[cuts[q]];
-        hipError_t e = hipStreamWaitEvent(s, ev[0], 0);
-        if (e != hipSuccess || (e = zero_bytes(starts, CW * 4, s)) != hipSuccess)
-            return e;
+        const uint64_t n_chunks = cuts.size() - 1;
+        const uint64_t CB = std::max<uint64_t>(cb_max, 1), CW = ceil_div(CB, 32);
+        const uint64_t sac_cap = sac_capacity ? sac_capacity : std::max<uint64_t>(n_bases, 1);
+        const uint64_t n_blocks = screen ? bloom_blocks_for(n_bases, n_reads, k, o) : 0;
+        const uint64_t merged = sac_cap + CB;  // records of one merge
+        // device memory
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            size_t r = off;
+            off = align_up(off + bytes, 256);
+            return r;
+        };
+        const size_t o_ctr = take(2 * sizeof(DevCounters)), o_misc = take(64), o_table = take(sizeof(uint64_t) << o.table_bits);
+        const size_t o_filter = take(n_blocks * 64), o_bases = take(CB), o_offs = take((cr_max + 1) * sizeof(uint64_t));
+        const size_t o_packed = take(CW * 8), o_valid = take(CW * 4), o_starts = take(CW * 4);
+        // second packed/valid buffer: the next chunk's words arrive while this
+        // chunk is collected (second pass)
+        const size_t o_packed2 = screen ? take(CW * 8) : 0, o_valid2 = screen ? take(CW * 4) : 0;
+        const size_t o_ka = take(CB * kb), o_kb = take(CB * kb), o_rk = take(CB * kb), o_rc = take(CB * 4);
+        const size_t sort_bytes = radix_scratch_bytes(CB, kw), cmp_bytes = compact_scratch_bytes(CB);
+        const size_t o_sort = take(sort_bytes), o_cmp = take(cmp_bytes);
+        const size_t o_sk[2] = {take(merged * kb), take(merged * kb)}, o_sc[2] = {take(merged * 4), take(merged * 4)};
+        const size_t o_tk = take(merged * kb), o_tc = take(merged * 4), o_flag = take(2 * merged * 4);
+        const size_t o_scan = take(scan_scratch_words(2 * merged) * 4);
+        const size_t total = off;
+        if (device_bytes)
+            *device_bytes = total;
+    
+        // packed words and validity bits of every chunk, kept in pinned host
+        // memory between the passes (0.5 B per base instead of the 1 B per base
+        // of the reads, and no pageable staging in the second pass)
+        std::vector<uint64_t> wfirst(n_chunks + 1, 0);  // first word of every chunk in the pinned arrays
+        for (uint64_t q = 0; q < n_chunks; q++)
+            wfirst[q + 1] = wfirst[q] + ceil_div(offsets[cuts[q + 1]] - offsets[cuts[q]], 32);
+    
+        char *ws = nullptr;
+        hipStream_t s = nullptr, cs = nullptr;  // kernels; copies of the next chunk
+        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+        uint64_t *h_packed = nullptr;
+        uint32_t *h_valid = nullptr;
+        uint64_t *h_roff = nullptr;  // relative read offsets of two chunks (pinned)
+        Stager up;                   // pinned slices of the reads' and the answer's copies
+        tk_result *res = nullptr;
+        auto cleanup = [&]() {
+            (void)up.release();
+            if (s) (void)hipStreamSynchronize(s);
+            if (cs) (void)hipStreamSynchronize(cs);
+            if (ws) (void)hipFree(ws);
+            for (hipEvent_t &e : ev)
+                if (e) (void)hipEventDestroy(e);
+            if (h_packed) (void)hipHostFree(h_packed);
+            if (h_valid) (void)hipHostFree(h_valid);
+            if (h_roff) (void)hipHostFree(h_roff);
+            if (cs) (void)hipStreamDestroy(cs);
+            if (s) (void)hipStreamDestroy(s);
+        };
+        auto dev_fail = [&](const char *what, hipError_t e) {
+            cleanup();
+            if (res) {
+                free(res->keys);
+                free(res->counts);
+                free(res);
+            }
+            if (e == hipErrorOutOfMemory)
+                return fail(TK_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+            return fail(TK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+        };
+    #define TK_PH(call, what)                   \
+        do {                                    \
+            hipError_t e_ = (call);             \
+            if (e_ != hipSuccess)               \
+                return dev_fail(what, e_);      \
+        } while (0)
+        TK_PH(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+        TK_PH(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+        for (hipEvent_t &e : ev)
+            TK_PH(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+        TK_PH(hipHostMalloc(reinterpret_cast<void **>(&h_roff), 2 * (cr_max + 1) * sizeof(uint64_t)), "hipHostMalloc");
+        if (screen && wfirst[n_chunks]) {
+            TK_PH(hipHostMalloc(reinterpret_cast<void **>(&h_packed), wfirst[n_chunks] * sizeof(uint64_t)),
+                  "hipHostMalloc(packed)");
+            TK_PH(hipHostMalloc(reinterpret_cast<void **>(&h_valid), wfirst[n_chunks] * sizeof(uint32_t)),
+                  "hipHostMalloc(valid)");
+        }
+        TK_PH(hipMalloc(&ws, total), "hipMalloc(workspace)");
+        DevCounters *ctr = reinterpret_cast<DevCounters *>(ws + o_ctr);  // [0] windows, collected; [1] chunk compaction
+        uint32_t *misc = reinterpret_cast<uint32_t *>(ws + o_misc);        // [0] SAC size, [1] selected
+        unsigned long long *stats = reinterpret_cast<unsigned long long *>(ws + o_misc + 16);
+        uint64_t *table = reinterpret_cast<uint64_t *>(ws + o_table);
+        uint64_t *filter = reinterpret_cast<uint64_t *>(ws + o_filter);
+        uint8_t *d_bases = reinterpret_cast<uint8_t *>(ws + o_bases);
+        uint64_t *d_offs = reinterpret_cast<uint64_t *>(ws + o_offs);
+        uint64_t *packed = reinterpret_cast<uint64_t *>(ws + o_packed);
+        uint32_t *valid = reinterpret_cast<uint32_t *>(ws + o_valid), *starts = reinterpret_cast<uint32_t *>(ws + o_starts);
+        uint64_t *packed2[2] = {packed, reinterpret_cast<uint64_t *>(ws + o_packed2)};
+        uint32_t *valid2[2] = {valid, reinterpret_cast<uint32_t *>(ws + o_valid2)};
+        uint64_t *keys_a = reinterpret_cast<uint64_t *>(ws + o_ka), *keys_b = reinterpret_cast<uint64_t *>(ws + o_kb);
+        uint64_t *run_k = reinterpret_cast<uint64_t *>(ws + o_rk);
+        uint32_t *run_c = reinterpret_cast<uint32_t *>(ws + o_rc);
+        uint64_t *sac_k[2] = {reinterpret_cast<uint64_t *>(ws + o_sk[0]), reinterpret_cast<uint64_t *>(ws + o_sk[1])};
+        uint32_t *sac_c[2] = {reinterpret_cast<uint32_t *>(ws + o_sc[0]), reinterpret_cast<uint32_t *>(ws + o_sc[1])};
+        uint64_t *tmp_k = reinterpret_cast<uint64_t *>(ws + o_tk);
+        uint32_t *tmp_c = reinterpret_cast<uint32_t *>(ws + o_tc), *flag = reinterpret_cast<uint32_t *>(ws + o_flag);
+        uint32_t *scan_tmp = reinterpret_cast<uint32_t *>(ws + o_scan);
+        TK_PH(zero_bytes(ws, o_table, s), "zero");  // counters and misc
+        if (screen) {
+            const auto &tab = pattern_table(o.seed, o.table_bits, o.bits);
+            TK_PH(hipMemcpyAsync(table, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s), "table");
+            TK_PH(zero_bytes(filter, n_blocks * 64, s), "zero filter");
+        }
+        BloomArgs ba{};
         ba.packed = packed;
         ba.valid = valid;
-        ba.n_words = ceil_div(nb, 32);
-        e = launch_pack(d_bases, d_offs, nb, cuts[q + 1] - cuts[q], k, packed, valid, starts,
-                        count ? &ctr[0].n_windows : nullptr, s);
-        if (e == hipSuccess)
-            e = hipEventRecord(ev[1], s);
-        return e;
-    };
-    // pass 1: every window of every chunk into the filter; the next chunk's
-    // reads travel while this one is screened; the packed words are kept
-    if (screen) {
-        if (n_chunks)
-            TK_PH(send_chunk(0), "pass 1");
-        for (uint64_t q = 0; q < n_chunks; q++) {
-            TK_PH(pack_chunk(q, true), "pass 1");
-            const uint64_t nw = wfirst[q + 1] - wfirst[q];
-            TK_PH(launch_screen(ba, persistent_grid(ba.n_words * 32), s), "screen");
-            if (nw) {
-                TK_PH(hipMemcpyAsync(h_packed + wfirst[q], packed, nw * 8, hipMemcpyDeviceToHost, s), "keep");
-                TK_PH(hipMemcpyAsync(h_valid + wfirst[q], valid, nw * 4, hipMemcpyDeviceToHost, s), "keep");
-            }
-            if (q + 1 < n_chunks)
-                TK_PH(send_chunk(q + 1), "pass 1");
-        }
-        // the pinned words are complete before the second pass reads them
-        TK_PH(hipEventRecord(ev[1], s), "record");
-        TK_PH(hipStreamWaitEvent(cs, ev[1], 0), "wait");
-    }
-    // second pass input of chunk q: packed words and validity bits from
-    // pinned memory into buffer q % 2 (screen), or the reads, packed again
-    auto second_pass_input = [&](uint64_t q) -> hipError_t {
-        const uint64_t nw = wfirst[q + 1] - wfirst[q];
-        hipError_t e;
-        if (nw && (e = hipMemcpyAsync(packed2[q % 2], h_packed + wfirst[q], nw * 8, hipMemcpyHostToDevice, cs)) !=
-                      hipSuccess)
+        ba.k = k;
+        ba.table = table;
+        ba.table_bits = o.table_bits;
+        ba.n_blocks = n_blocks;
+        ba.filter = filter;
+        // Chunk q's reads and relative read offsets go to the device on the copy
+        // stream (offsets staged in pinned slot q % 2) while the kernel stream
+        // still screens the chunk before; pack then runs on the kernel stream.
+        // ev[0]: chunk copied; ev[1]: chunk packed (its reads are consumed, so
+        // the next chunk may overwrite them; the host waits for it, whatever the
+        // runtime does with pageable sources); ev[2 + q % 2]: the offsets of
+        // slot q % 2 are on the device.
+        auto send_chunk = [&](uint64_t q) -> hipError_t {
+            const uint64_t r0 = cuts[q], r1 = cuts[q + 1], b0 = offsets[r0], nb = offsets[r1] - b0;
+            uint64_t *ro = h_roff + (q % 2) * (cr_max + 1);
+            hipError_t e = hipEventSynchronize(ev[2 + q % 2]);  // slot free (chunk q - 2 sent)
+            if (e != hipSuccess)
+                return e;
+            for (uint64_t r = r0; r <= r1; r++)
+                ro[r - r0] = offsets[r] - b0;
+            if ((e = hipEventSynchronize(ev[1])) != hipSuccess)
+                return e;
+            if ((e = up.copy(d_bases, bases + b0, nb, true, cs)) != hipSuccess)
+                return e;
+            if ((e = hipMemcpyAsync(d_offs, ro, (r1 - r0 + 1) * 8, hipMemcpyHostToDevice, cs)) != hipSuccess)
+                return e;
+            if ((e = hipEventRecord(ev[2 + q % 2], cs)) != hipSuccess)
+                return e;
+            return hipEventRecord(ev[0], cs);
+        };
+        auto pack_chunk = [&](uint64_t q, bool count) -> hipError_t {
+            const uint64_t nb = offsets[cuts[q + 1]] - offsets[cuts[q]];
+            hipError_t e = hipStreamWaitEvent(s, ev[0], 0);
+            if (e != hipSuccess || (e = zero_bytes(starts, CW * 4, s)) != hipSuccess)
+                return e;
+            ba.packed = packed;
+            ba.valid = valid;
+            ba.n_words = ceil_div(nb, 32);
+            e = launch_pack(d_bases, d_offs, nb, cuts[q + 1] - cuts[q], k, packed, valid, starts,
+                            count ? &ctr[0].n_windows : nullptr, s);
+            if (e == hipSuccess)
+                e = hipEventRecord(ev[1], s);
             return e;
-        if (nw && (e = hipMemcpyAsync(valid2[q % 2], h_valid + wfirst[q], nw * 4, hipMemcpyHostToDevice, cs)) !=
-                      hipSuccess)
-            return e;
-        return hipEventRecord(ev[q % 2], cs);
-    };
-    // pass 2: per chunk, collect, sort, compact, merge into the SAC
-    uint64_t n_sac = 0, n_coll = 0;
-    int cur = 0;
-    if (screen && n_chunks)
-        TK_PH(second_pass_input(0), "pass 2");
-    for (uint64_t q = 0; q < n_chunks; q++) {
+        };
+        // pass 1: every window of every chunk into the filter; the next chunk's
+        // reads travel while this one is screened; the packed words are kept
         if (screen) {
-            // buffer (q + 1) % 2 was last read by chunk q - 1, whose collect
-            // finished before its survivor count was read back
-            if (q + 1 < n_chunks)
-                TK_PH(second_pass_input(q + 1), "pass 2");
-            TK_PH(hipStreamWaitEvent(s, ev[q % 2], 0), "wait");
-            ba.packed = packed2[q % 2];
-            ba.valid = valid2[q % 2];
-            ba.n_words = wfirst[q + 1] - wfirst[q];
-        } else {
-            TK_PH(send_chunk(q), "pass 2");
-            TK_PH(pack_chunk(q, true), "pass 2");
+            if (n_chunks)
+                TK_PH(send_chunk(0), "pass 1");
+            for (uint64_t q = 0; q < n_chunks; q++) {
+                TK_PH(pack_chunk(q, true), "pass 1");
+                const uint64_t nw = wfirst[q + 1] - wfirst[q];
+                TK_PH(launch_screen(ba, persistent_grid(ba.n_words * 32), s), "screen");
+                if (nw) {
+                    TK_PH(hipMemcpyAsync(h_packed + wfirst[q], packed, nw * 8, hipMemcpyDeviceToHost, s), "keep");
+                    TK_PH(hipMemcpyAsync(h_valid + wfirst[q], valid, nw * 4, hipMemcpyDeviceToHost, s), "keep");
+                }
+                if (q + 1 < n_chunks)
+                    TK_PH(send_chunk(q + 1), "pass 1");
+            }
+            // the pinned words are complete before the second pass reads them
+            TK_PH(hipEventRecord(ev[1], s), "record");
+            TK_PH(hipStreamWaitEvent(cs, ev[1], 0), "wait");
         }
-        TK_PH(zero_bytes(&ctr[1], sizeof(DevCounters), s), "zero");
-        TK_PH(launch_collect(ba, screen, keys_a, CB, &ctr[1].n_collected, persistent_grid(ba.n_words * 32), s),
-              "collect");
-        unsigned long long n_surv = 0;
-        TK_PH(hipMemcpyAsync(&n_surv, &ctr[1].n_collected, 8, hipMemcpyDeviceToHost, s), "read");
+        // second pass input of chunk q: packed words and validity bits from
+        // pinned memory into buffer q % 2 (screen), or the reads, packed again
+        auto second_pass_input = [&](uint64_t q) -> hipError_t {
+            const uint64_t nw = wfirst[q + 1] - wfirst[q];
+            hipError_t e;
+            if (nw && (e = hipMemcpyAsync(packed2[q % 2], h_packed + wfirst[q], nw * 8, hipMemcpyHostToDevice, cs)) !=
+                          hipSuccess)
+                return e;
+            if (nw && (e = hipMemcpyAsync(valid2[q % 2], h_valid + wfirst[q], nw * 4, hipMemcpyHostToDevice, cs)) !=
+                          hipSuccess)
+                return e;
+            return hipEventRecord(ev[q % 2], cs);
+        };
+        // pass 2: per chunk, collect, sort, compact, merge into the SAC
+        uint64_t n_sac = 0, n_coll = 0;
+        int cur = 0;
+        if (screen && n_chunks)
+            TK_PH(second_pass_input(0), "pass 2");
+        for (uint64_t q = 0; q < n_chunks; q++) {
+            if (screen) {
+                // buffer (q + 1) % 2 was last read by chunk q - 1, whose collect
+                // finished before its survivor count was read back
+                if (q + 1 < n_chunks)
+                    TK_PH(second_pass_input(q + 1), "pass 2");
+                TK_PH(hipStreamWaitEvent(s, ev[q % 2], 0), "wait");
+                ba.packed = packed2[q % 2];
+                ba.valid = valid2[q % 2];
+                ba.n_words = wfirst[q + 1] - wfirst[q];
+            } else {
+                TK_PH(send_chunk(q), "pass 2");
+                TK_PH(pack_chunk(q, true), "pass 2");
+            }
+            TK_PH(zero_bytes(&ctr[1], sizeof(DevCounters), s), "zero");
+            TK_PH(launch_collect(ba, screen, keys_a, CB, &ctr[1].n_collected, persistent_grid(ba.n_words * 32), s),
+                  "collect");
+            unsigned long long n_surv = 0;
+            TK_PH(hipMemcpyAsync(&n_surv, &ctr[1].n_collected, 8, hipMemcpyDeviceToHost, s), "read");
+            TK_PH(hipStreamSynchronize(s), "sync");
+            n_coll += n_surv;
+            uint64_t *srt = nullptr;
+            int passes = 0;
+            TK_PH(radix_sort(keys_a, keys_b, n_surv, kw, 2 * k, ws + o_sort, sort_bytes, s, &srt, &passes), "sort");
+            TK_PH(compact(srt, n_surv, kw, 1, run_k, run_c, ws + o_cmp, cmp_bytes, &ctr[1], s), "compact");
+            unsigned long long n_runs = 0;
+            TK_PH(hipMemcpyAsync(&n_runs, &ctr[1].n_out, 8, hipMemcpyDeviceToHost, s), "read");
+            TK_PH(hipStreamSynchronize(s), "sync");
+            TK_PH(merge_compact(sac_k[cur], sac_c[cur], n_sac, run_k, run_c, n_runs, kw, tmp_k, tmp_c, flag, scan_tmp,
+                                sac_k[1 - cur], sac_c[1 - cur], &misc[0], s),
+                  "merge");
+            uint32_t ns = 0;
+            TK_PH(hipMemcpyAsync(&ns, &misc[0], 4, hipMemcpyDeviceToHost, s), "read");
+            TK_PH(hipStreamSynchronize(s), "sync");
+            n_sac = ns;
+            cur = 1 - cur;
+            if (n_sac > sac_cap) {
+                cleanup();
+                return fail(TK_ENOMEM, "%llu counted k-mers exceed the sorted-and-compacted array of %llu",
+                            (unsigned long long)n_sac, (unsigned long long)sac_cap);
+            }
+        }
+        // the answer: records with count >= c
+        TK_PH(select_records(sac_k[cur], sac_c[cur], n_sac, kw, c, flag, scan_tmp, tmp_k, tmp_c, &misc[1], stats, s),
+              "select");
+        uint32_t n_out = 0;
+        unsigned long long st2[2] = {0, 0}, n_win = 0;
+        TK_PH(hipMemcpyAsync(&n_out, &misc[1], 4, hipMemcpyDeviceToHost, s), "read");
+        TK_PH(hipMemcpyAsync(st2, stats, 16, hipMemcpyDeviceToHost, s), "read");
+        TK_PH(hipMemcpyAsync(&n_win, &ctr[0].n_windows, 8, hipMemcpyDeviceToHost, s), "read");
         TK_PH(hipStreamSynchronize(s), "sync");
-        n_coll += n_surv;
-        uint64_t *srt = nullptr;
-        int passes = 0;
-        TK_PH(radix_sort(keys_a, keys_b, n_surv, kw, 2 * k, ws + o_sort, sort_bytes, s, &srt, &passes), "sort");
-        TK_PH(compact(srt, n_surv, kw, 1, run_k, run_c, ws + o_cmp, cmp_bytes, &ctr[1], s), "compact");
-        unsigned long long n_runs = 0;
-        TK_PH(hipMemcpyAsync(&n_runs, &ctr[1].n_out, 8, hipMemcpyDeviceToHost, s), "read");
-        TK_PH(hipStreamSynchronize(s), "sync");
-        TK_PH(merge_compact(sac_k[cur], sac_c[cur], n_sac, run_k, run_c, n_runs, kw, tmp_k, tmp_c, flag, scan_tmp,
-                            sac_k[1 - cur], sac_c[1 - cur], &misc[0], s),
-              "merge");
-        uint32_t ns = 0;
-        TK_PH(hipMemcpyAsync(&ns, &misc[0], 4, hipMemcpyDeviceToHost, s), "read");
-        TK_PH(hipStreamSynchronize(s), "sync");
-        n_sac = ns;
-        cur = 1 - cur;
-        if (n_sac > sac_cap) {
+        res = static_cast<tk_result *>(calloc(1, sizeof(tk_result)));
+        if (!res) {
             cleanup();
-            return fail(TK_ENOMEM, "%llu counted k-mers exceed the sorted-and-compacted array of %llu",
-                        (unsigned long long)n_sac, (unsigned long long)sac_cap);
+            return fail(TK_ENOMEM, "result allocation failed");
         }
-    }
-    // the answer: records with count >= c
-    TK_PH(select_records(sac_k[cur], sac_c[cur], n_sac, kw, c, flag, scan_tmp, tmp_k, tmp_c, &misc[1], stats, s),
-          "select");
-    uint32_t n_out = 0;
-    unsigned long long st2[2] = {0, 0}, n_win = 0;
-    TK_PH(hipMemcpyAsync(&n_out, &misc[1], 4, hipMemcpyDeviceToHost, s), "read");
-    TK_PH(hipMemcpyAsync(st2, stats, 16, hipMemcpyDeviceToHost, s), "read");
-    TK_PH(hipMemcpyAsync(&n_win, &ctr[0].n_windows, 8, hipMemcpyDeviceToHost, s), "read");
-    TK_PH(hipStreamSynchronize(s), "sync");
-    res = static_cast<tk_result *>(calloc(1, sizeof(tk_result)));
-    if (!res) {
+        res->n = n_out;
+        res->k = (uint32_t)k;
+        res->key_words = (uint32_t)kw;
+        res->n_windows = n_win;
+        res->n_collected = n_coll;
+        res->n_distinct = n_sac;
+        res->n_singletons = st2[0];
+        res->n_below_c = st2[1];
+        res->bloom_blocks = n_blocks;
+        res->part_bits = -1;
+        res->keys = static_cast<uint64_t *>(malloc((n_out ? n_out : 1) * kb));
+        res->counts = static_cast<uint32_t *>(malloc((n_out ? n_out : 1) * sizeof(uint32_t)));
+        if (!res->keys || !res->counts)
+            return dev_fail("result allocation", hipErrorOutOfMemory);
+        TK_PH(up.copy(res->keys, tmp_k, n_out * kb, false, s), "copy keys");
+        TK_PH(up.copy(res->counts, tmp_c, n_out * 4, false, s), "copy counts");
+        TK_PH(hipStreamSynchronize(s), "sync");
+    #undef TK_PH
         cleanup();
-        return fail(TK_ENOMEM, "result allocation failed");
-    }
-    res->n = n_out;
-    res->k = (uint32_t)k;
-    res->key_words = (uint32_t)kw;
-    res->n_windows = n_win;
-    res->n_collected = n_coll;
-    res->n_distinct = n_sac;
-    res->n_singletons = st2[0];
-    res->n_below_c = st2[1];
-    res->bloom_blocks = n_blocks;
-    res->part_bits = -1;
-    res->keys = static_cast<uint64_t *>(malloc((n_out ? n_out : 1) * kb));
-    res->counts = static_cast<uint32_t *>(malloc((n_out ? n_out : 1) * sizeof(uint32_t)));
-    if (!res->keys || !res->counts)
-        return dev_fail("result allocation", hipErrorOutOfMemory);
-    TK_PH(up.copy(res->keys, tmp_k, n_out * kb, false, s), "copy keys");
-    TK_PH(up.copy(res->counts, tmp_c, n_out * 4, false, s), "copy counts");
-    TK_PH(hipStreamSynchronize(s), "sync");
-#undef TK_PH
-    cleanup();
-    *out = res;
-    return TK_OK;
+        *out = res;
+        return TK_OK;
+    });
 }
 
 void tk_result_free(tk_result *res) {
@@ -1472,84 +1508,94 @@ void tk_result_free(tk_result *res) {
 tk_status tk_pack_device(const uint8_t *d_bases, const uint64_t *d_offsets, uint64_t n_bases, uint64_t n_reads,
                          int k, uint64_t *d_packed, uint32_t *d_valid, uint32_t *d_scratch,
                          uint64_t *d_n_windows, void *stream) {
-    if (k < 1 || k > 63)
-        return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
-    if (n_bases >= (1ull << 32))
-        return fail(TK_EOVERFLOW, "n_bases must be below 2^32");
-    if (!d_offsets || !d_n_windows || (n_bases && (!d_bases || !d_packed || !d_valid || !d_scratch)))
-        return fail(TK_EINVAL, "NULL device pointer");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint64_t n_words = ceil_div(n_bases, 32);
-    TK_HIP(zero_bytes(d_n_windows, 8, s));
-    if ((uintptr_t)d_n_windows & 7u || (uintptr_t)d_scratch & 3u)
-        return fail(TK_EINVAL, "misaligned device pointer");
-    TK_HIP(zero_bytes(d_scratch, n_words * 4, s));
-    TK_HIP(launch_pack(d_bases, d_offsets, n_bases, n_reads, k, d_packed, d_valid, d_scratch,
-                       reinterpret_cast<unsigned long long *>(d_n_windows), s));
-    return TK_OK;
+    return guarded([&]() -> tk_status {
+        if (k < 1 || k > 63)
+            return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
+        if (n_bases >= (1ull << 32))
+            return fail(TK_EOVERFLOW, "n_bases must be below 2^32");
+        if (!d_offsets || !d_n_windows || (n_bases && (!d_bases || !d_packed || !d_valid || !d_scratch)))
+            return fail(TK_EINVAL, "NULL device pointer");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const uint64_t n_words = ceil_div(n_bases, 32);
+        TK_HIP(zero_bytes(d_n_windows, 8, s));
+        if ((uintptr_t)d_n_windows & 7u || (uintptr_t)d_scratch & 3u)
+            return fail(TK_EINVAL, "misaligned device pointer");
+        TK_HIP(zero_bytes(d_scratch, n_words * 4, s));
+        TK_HIP(launch_pack(d_bases, d_offsets, n_bases, n_reads, k, d_packed, d_valid, d_scratch,
+                           reinterpret_cast<unsigned long long *>(d_n_windows), s));
+        return TK_OK;
+    });
 }
 
 tk_status tk_sort_scratch_size(uint64_t n, int key_words, size_t *bytes) {
-    if (!bytes || (key_words != 1 && key_words != 2))
-        return fail(TK_EINVAL, "bad arguments");
-    *bytes = radix_scratch_bytes(n, key_words);
-    return TK_OK;
+    return guarded([&]() -> tk_status {
+        if (!bytes || (key_words != 1 && key_words != 2))
+            return fail(TK_EINVAL, "bad arguments");
+        *bytes = radix_scratch_bytes(n, key_words);
+        return TK_OK;
+    });
 }
 
 tk_status tk_sort_keys_device(uint64_t *d_keys, uint64_t *d_alt, uint64_t n, int key_words, int key_bits,
                               void *d_scratch, size_t scratch_bytes, void *stream, uint64_t **d_sorted_out) {
-    if (key_words != 1 && key_words != 2)
-        return fail(TK_EINVAL, "key_words must be 1 or 2");
-    if (key_bits < 0 || key_bits > 64 * key_words)
-        return fail(TK_EINVAL, "key_bits out of range");
-    if (!d_sorted_out || (n && (!d_keys || !d_alt || !d_scratch)))
-        return fail(TK_EINVAL, "NULL pointer");
-    if (n >= (1ull << 32))
-        return fail(TK_EOVERFLOW, "at most 2^32 - 1 keys");
-    if (scratch_bytes < radix_scratch_bytes(n, key_words))
-        return fail(TK_EINVAL, "scratch too small");
-    int passes = 0;
-    TK_HIP(radix_sort(d_keys, d_alt, n, key_words, key_bits, d_scratch, scratch_bytes,
-                      static_cast<hipStream_t>(stream), d_sorted_out, &passes));
-    return TK_OK;
+    return guarded([&]() -> tk_status {
+        if (key_words != 1 && key_words != 2)
+            return fail(TK_EINVAL, "key_words must be 1 or 2");
+        if (key_bits < 0 || key_bits > 64 * key_words)
+            return fail(TK_EINVAL, "key_bits out of range");
+        if (!d_sorted_out || (n && (!d_keys || !d_alt || !d_scratch)))
+            return fail(TK_EINVAL, "NULL pointer");
+        if (n >= (1ull << 32))
+            return fail(TK_EOVERFLOW, "at most 2^32 - 1 keys");
+        if (scratch_bytes < radix_scratch_bytes(n, key_words))
+            return fail(TK_EINVAL, "scratch too small");
+        int passes = 0;
+        TK_HIP(radix_sort(d_keys, d_alt, n, key_words, key_bits, d_scratch, scratch_bytes,
+                          static_cast<hipStream_t>(stream), d_sorted_out, &passes));
+        return TK_OK;
+    });
 }
 
 tk_status tk_compact_scratch_size(uint64_t n, size_t *bytes) {
-    if (!bytes)
-        return fail(TK_EINVAL, "bytes is NULL");
-    *bytes = align_up(sizeof(DevCounters), 256) + compact_scratch_bytes(n);
-    return TK_OK;
+    return guarded([&]() -> tk_status {
+        if (!bytes)
+            return fail(TK_EINVAL, "bytes is NULL");
+        *bytes = align_up(sizeof(DevCounters), 256) + compact_scratch_bytes(n);
+        return TK_OK;
+    });
 }
 
 tk_status tk_compact_device(const uint64_t *d_keys, uint64_t n, int key_words, uint32_t c, uint64_t *d_out_keys,
                             uint32_t *d_out_counts, void *d_scratch, size_t scratch_bytes, void *stream,
                             uint64_t stats[4]) {
-    if (key_words != 1 && key_words != 2)
-        return fail(TK_EINVAL, "key_words must be 1 or 2");
-    if (c == 0)
-        return fail(TK_EINVAL, "threshold c must be >= 1");
-    if (!stats || !d_scratch || (n && (!d_keys || !d_out_keys || !d_out_counts)))
-        return fail(TK_EINVAL, "NULL pointer");
-    if ((uintptr_t)d_scratch & 255u)
-        return fail(TK_EINVAL, "scratch must be 256-byte aligned");
-    if (n >= (1ull << 32))
-        return fail(TK_EOVERFLOW, "at most 2^32 - 1 keys");
-    const size_t head = align_up(sizeof(DevCounters), 256);
-    if (scratch_bytes < head + compact_scratch_bytes(n))
-        return fail(TK_EINVAL, "scratch too small");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    DevCounters *ctr = static_cast<DevCounters *>(d_scratch);
-    TK_HIP(zero_bytes(ctr, sizeof(DevCounters), s));
-    TK_HIP(compact(d_keys, n, key_words, c, d_out_keys, d_out_counts, static_cast<char *>(d_scratch) + head,
-                   scratch_bytes - head, ctr, s));
-    DevCounters h{};
-    TK_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
-    TK_HIP(hipStreamSynchronize(s));
-    stats[0] = h.n_out;
-    stats[1] = h.n_runs;
-    stats[2] = h.n_single;
-    stats[3] = h.n_below;
-    return TK_OK;
+    return guarded([&]() -> tk_status {
+        if (key_words != 1 && key_words != 2)
+            return fail(TK_EINVAL, "key_words must be 1 or 2");
+        if (c == 0)
+            return fail(TK_EINVAL, "threshold c must be >= 1");
+        if (!stats || !d_scratch || (n && (!d_keys || !d_out_keys || !d_out_counts)))
+            return fail(TK_EINVAL, "NULL pointer");
+        if ((uintptr_t)d_scratch & 255u)
+            return fail(TK_EINVAL, "scratch must be 256-byte aligned");
+        if (n >= (1ull << 32))
+            return fail(TK_EOVERFLOW, "at most 2^32 - 1 keys");
+        const size_t head = align_up(sizeof(DevCounters), 256);
+        if (scratch_bytes < head + compact_scratch_bytes(n))
+            return fail(TK_EINVAL, "scratch too small");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevCounters *ctr = static_cast<DevCounters *>(d_scratch);
+        TK_HIP(zero_bytes(ctr, sizeof(DevCounters), s));
+        TK_HIP(compact(d_keys, n, key_words, c, d_out_keys, d_out_counts, static_cast<char *>(d_scratch) + head,
+                       scratch_bytes - head, ctr, s));
+        DevCounters h{};
+        TK_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+        stats[0] = h.n_out;
+        stats[1] = h.n_runs;
+        stats[2] = h.n_single;
+        stats[3] = h.n_below;
+        return TK_OK;
+    });
 }
 
 }  // extern "C"
