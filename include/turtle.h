@@ -88,6 +88,8 @@ typedef enum {
     TK_EOVERFLOW = -4  /* input too large: n_bases must be < 2^32 so that
                           positions and counts fit 32 bits */
 } tk_status;
+/* Every failure is reported as a status (with a message in tk_last_error);
+ * no function lets a C++ exception out of the library. */
 
 /* Stages whose device time is reported when TK_FLAG_TIMING is set.  The
  * partitioned path (default) runs PACK, PARTITION, BUCKET, FALLBACK and
