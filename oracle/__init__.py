@@ -88,6 +88,12 @@ def _load():
         lib.oracle_approx.argtypes = [_u8p, _u64p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_uint64, _u64p, _u64p, _u64p, ctypes.c_uint64, _u64p, _u64p]
+        lib.oracle_keys_in_range.restype = ctypes.c_int
+        lib.oracle_keys_in_range.argtypes = [_u8p, _u64p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_uint64, ctypes.POINTER(_u64p), ctypes.POINTER(_u64p),
+                                             _u64p]
+        lib.oracle_free.restype = None
+        lib.oracle_free.argtypes = [ctypes.c_void_p]
         lib.oracle_bloom_model.restype = ctypes.c_int
         lib.oracle_bloom_model.argtypes = [_u8p, _u64p, ctypes.c_uint64, ctypes.c_int,
                                            ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
@@ -142,6 +148,32 @@ def kmer_count(bases, offsets, k: int, c: int) -> Counted:
     if r < 0:
         raise ValueError(f"oracle_kmer_count: status {r}")
     return Counted(hi[:r].copy(), lo[:r].copy(), cnt[:r].copy(), int(nw.value), int(nd.value))
+
+
+def keys_in_range(bases, offsets, k: int, range_bits: int, range_index: int):
+    """Canonical keys (hi, lo occurrence arrays, read order) of the windows
+    whose key has top ``range_bits`` bits (of its 2k-bit value) equal to
+    ``range_index``.  Range by range, a library too large for host memory
+    can be counted exactly: the answer is the concatenation over ranges, in
+    order, of ``sort_compact`` of each range's keys."""
+    b, o, n = _reads(bases, offsets)
+    ph, pl = _u64p(), _u64p()
+    m = ctypes.c_uint64(0)
+    lib = _load()
+    r = lib.oracle_keys_in_range(_p(b, _u8p), _p(o, _u64p), n, k, range_bits, range_index,
+                                 ctypes.byref(ph), ctypes.byref(pl), ctypes.byref(m))
+    if r != 0:
+        raise ValueError(f"oracle_keys_in_range: status {r}")
+    q = int(m.value)
+    try:
+        if q == 0:
+            return np.zeros(0, np.uint64), np.zeros(0, np.uint64)
+        hi = np.ctypeslib.as_array(ph, shape=(q,)).copy()
+        lo = np.ctypeslib.as_array(pl, shape=(q,)).copy()
+        return hi, lo
+    finally:
+        lib.oracle_free(ph)
+        lib.oracle_free(pl)
 
 
 def approx_words(n_bases: int, n_reads: int, k: int, beta: int) -> int:

@@ -259,6 +259,64 @@ int64_t oracle_kmer_count(const uint8_t *bases, const uint64_t *offsets,
 }
 
 /*
+ * The canonical keys of every window whose key lies in one range of the key
+ * space, for libraries too large to hold all their keys at once: range r of
+ * 2^range_bits is the set of keys whose top range_bits bits (of the 2k-bit
+ * value) equal r.  The ranges are ordered like the keys, so the exact answer
+ * of a library is the concatenation, in range order, of the sort-and-compact
+ * of each range's keys.  Occurrences come in read order then position
+ * order.  *hi and *lo receive malloc'ed arrays of *n entries (NULL when
+ * there are none); release them with oracle_free.
+ */
+int oracle_keys_in_range(const uint8_t *bases, const uint64_t *offsets,
+                         uint64_t n_reads, int k, int range_bits,
+                         uint64_t range_index, uint64_t **hi, uint64_t **lo,
+                         uint64_t *n)
+{
+    if (check_args(offsets, n_reads, k) != OR_OK || range_bits < 0 ||
+        range_bits > 2 * k || range_bits > 16 ||
+        range_index >= ((uint64_t)1 << range_bits) || !hi || !lo || !n)
+        return OR_EINVAL;
+    uint64_t cap = 0, m = 0;
+    uint64_t *h = NULL, *l = NULL;
+    for (uint64_t r = 0; r < n_reads; r++) {
+        for (uint64_t i = offsets[r]; i + (uint64_t)k <= offsets[r + 1]; i++) {
+            u128 key;
+            if (!window_key(bases + i, k, &key))
+                continue;
+            if (range_bits && (uint64_t)(key >> (2 * k - range_bits)) != range_index)
+                continue;
+            if (m == cap) {
+                uint64_t nc = cap ? 2 * cap : 4096;
+                uint64_t *nh = (uint64_t *)realloc(h, nc * sizeof(uint64_t));
+                if (nh)
+                    h = nh;
+                uint64_t *nl = nh ? (uint64_t *)realloc(l, nc * sizeof(uint64_t)) : NULL;
+                if (!nh || !nl) {
+                    free(h);
+                    free(l);
+                    return OR_ENOMEM;
+                }
+                l = nl;
+                cap = nc;
+            }
+            h[m] = (uint64_t)(key >> 64);
+            l[m] = (uint64_t)key;
+            m++;
+        }
+    }
+    *hi = h;
+    *lo = l;
+    *n = m;
+    return OR_OK;
+}
+
+void oracle_free(void *p)
+{
+    free(p);
+}
+
+/*
  * Exact counts of chosen keys over all windows of a library, for checking
  * sampled outputs of very large runs.  `q_hi`/`q_lo` must be sorted
  * ascending by (hi, lo) and distinct; counts[i] receives the number of

@@ -276,6 +276,36 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _check_device_reads(bases, offsets, n_bases_min: int = 0, n_offsets_min: int = 1):
+    """Reject arguments the library would otherwise trust: the C side reads
+    ``n_bases`` bytes of ``bases`` and ``n_reads + 1`` 8-byte ``offsets``."""
+    torch = _torch()
+    if not isinstance(bases, torch.Tensor) or not isinstance(offsets, torch.Tensor):
+        raise ValueError("bases and offsets must be torch tensors")
+    if bases.dtype != torch.uint8:
+        raise ValueError(f"bases must be uint8, not {bases.dtype}")
+    if offsets.dtype not in (torch.int64, getattr(torch, "uint64", torch.int64)):
+        raise ValueError(f"offsets must be int64 or uint64 (8-byte) values, not {offsets.dtype}")
+    if not bases.is_contiguous() or not offsets.is_contiguous():
+        raise ValueError("bases and offsets must be contiguous")
+    if offsets.numel() < n_offsets_min:
+        raise ValueError(f"offsets holds {offsets.numel()} values, at least {n_offsets_min} needed")
+    if bases.numel() < n_bases_min:
+        raise ValueError(f"bases holds {bases.numel()} bytes, at least {n_bases_min} needed")
+    if bases.device.type != "cuda" or offsets.device != bases.device:
+        raise ValueError("bases and offsets must be CUDA tensors on one device")
+
+
+def _check_workspace(workspace, need: int, device):
+    torch = _torch()
+    if not isinstance(workspace, torch.Tensor) or workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 tensor")
+    if workspace.numel() < need:
+        raise ValueError(f"workspace of {workspace.numel()} bytes is below the {need} needed")
+    if workspace.device != device:
+        raise ValueError("workspace must be on the device of the reads")
+
+
 def tk_count_device(bases, offsets, k: int, c: int, opts=None, workspace=None, stream=None) -> Counts:
     """Count a library held in device memory.
 
@@ -286,12 +316,14 @@ def tk_count_device(bases, offsets, k: int, c: int, opts=None, workspace=None, s
     """
     torch = _torch()
     lib = load_library()
+    _check_device_reads(bases, offsets)
     n_bases = int(bases.numel())
     n_reads = int(offsets.numel()) - 1
     o = _opts(opts)
     need = tk_workspace_size(n_bases, n_reads, k, c, o)
     if workspace is None:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=bases.device)
+    _check_workspace(workspace, need, bases.device)
     r = tk_result()
     _check(lib.tk_count_device(ctypes.c_void_p(bases.data_ptr()) if n_bases else None,
                                ctypes.c_void_p(offsets.data_ptr()), n_bases, n_reads, k, c,
@@ -340,10 +372,12 @@ def tk_count_batch_device(bases, offsets, lib_bases, lib_reads, k: int, c, opts=
     torch = _torch()
     lib = load_library()
     n_libs, lb, lr, cc = _batch_arrays(lib_bases, lib_reads, c)
+    _check_device_reads(bases, offsets, int(lb[-1]), int(lr[-1]) + 1)
     o = _opts(opts)
     need = tk_batch_workspace_size(lb, lr, k, cc, o)
     if workspace is None:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=bases.device)
+    _check_workspace(workspace, need, bases.device)
     res = (tk_result * n_libs)()
     n_bases = int(bases.numel())
     _check(lib.tk_count_batch_device(ctypes.c_void_p(bases.data_ptr()) if n_bases else None,

@@ -919,6 +919,19 @@ using namespace tk;
 
 namespace {
 
+// Runs a cleanup when the scope ends, also when a C++ exception (a failed
+// host allocation inside the counting path) unwinds it; the cleanup must be
+// safe to run more than once.
+template <typename F>
+struct OnExit {
+    F f;
+    ~OnExit() { f(); }
+};
+template <typename F>
+OnExit<F> on_exit(F f) {
+    return OnExit<F>{f};
+}
+
 // Entry points return a status: a C++ exception (a host allocation that
 // fails, a thread that cannot start) never leaves the library.
 template <typename F>
@@ -1110,13 +1123,19 @@ tk_status tk_count(const uint8_t *bases, const uint64_t *offsets, uint64_t n_rea
         tk_result *res = nullptr;
         hipStream_t s = nullptr;
         Stager stage;  // pinned slices of the host copies
-        auto cleanup = [&]() {
+        auto cleanup = [&]() {  // idempotent: also runs when the scope ends
             (void)stage.release();
+            if (s) (void)hipStreamSynchronize(s);
             if (d_bases) (void)hipFree(d_bases);
             if (d_offsets) (void)hipFree(d_offsets);
             if (d_ws) (void)hipFree(d_ws);
             if (s) (void)hipStreamDestroy(s);
+            d_bases = nullptr;
+            d_offsets = nullptr;
+            d_ws = nullptr;
+            s = nullptr;
         };
+        auto guard = on_exit(cleanup);
         auto dev_fail = [&](const char *what, hipError_t e) {
             cleanup();
             if (res) {
@@ -1265,19 +1284,28 @@ tk_status tk_count_phased(const uint8_t *bases, const uint64_t *offsets, uint64_
         uint64_t *h_roff = nullptr;  // relative read offsets of two chunks (pinned)
         Stager up;                   // pinned slices of the reads' and the answer's copies
         tk_result *res = nullptr;
-        auto cleanup = [&]() {
+        auto cleanup = [&]() {  // idempotent: also runs when the scope ends
             (void)up.release();
             if (s) (void)hipStreamSynchronize(s);
             if (cs) (void)hipStreamSynchronize(cs);
             if (ws) (void)hipFree(ws);
-            for (hipEvent_t &e : ev)
+            for (hipEvent_t &e : ev) {
                 if (e) (void)hipEventDestroy(e);
+                e = nullptr;
+            }
             if (h_packed) (void)hipHostFree(h_packed);
             if (h_valid) (void)hipHostFree(h_valid);
             if (h_roff) (void)hipHostFree(h_roff);
             if (cs) (void)hipStreamDestroy(cs);
             if (s) (void)hipStreamDestroy(s);
+            ws = nullptr;
+            h_packed = nullptr;
+            h_valid = nullptr;
+            h_roff = nullptr;
+            cs = nullptr;
+            s = nullptr;
         };
+        auto guard = on_exit(cleanup);
         auto dev_fail = [&](const char *what, hipError_t e) {
             cleanup();
             if (res) {

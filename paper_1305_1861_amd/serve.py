@@ -119,7 +119,28 @@ class Server:
         self._dispatcher.start()
 
     # -- client side ---------------------------------------------------------
+    @staticmethod
+    def check_job(job: Job):
+        """Refuse a malformed job before it can share a batch: its offsets
+        are rebased into the batch's arrays, so an offset past its own bases
+        would cut windows of the next job, and a bad k or c would fail the
+        whole batch."""
+        b, o = job.bases, job.offsets
+        if not isinstance(b, np.ndarray) or b.dtype != np.uint8 or b.ndim != 1:
+            raise ValueError("job.bases must be a 1-D uint8 array")
+        if not isinstance(o, np.ndarray) or o.dtype not in (np.uint64, np.int64) or o.ndim != 1 or o.size < 1:
+            raise ValueError("job.offsets must be a 1-D array of n_reads + 1 uint64 values")
+        if int(o[0]) != 0 or int(o[-1]) != b.size:
+            raise ValueError("job.offsets must start at 0 and end at bases.size")
+        if o.size > 1 and (np.diff(o.astype(np.int64)) < 0).any():
+            raise ValueError("job.offsets must not decrease")
+        if not (isinstance(job.k, (int, np.integer)) and 1 <= int(job.k) <= 63):
+            raise ValueError("job.k must be in [1, 63]")
+        if not (isinstance(job.c, (int, np.integer)) and int(job.c) >= 1):
+            raise ValueError("job.c must be >= 1")
+
     def submit(self, job: Job) -> Future:
+        self.check_job(job)
         if job.bases.size > self.max_bases or job.offsets.size - 1 > self.max_reads:
             raise ValueError("job larger than the server's batch budget")
         fut: Future = Future()

@@ -200,3 +200,47 @@ def test_shards_split_one_library_per_call(lib):
     one = tk.tk_workspace_size(10_000_000, 100_000, 31, 2)
     sh = tk.tk_workspace_size(10_000_000, 100_000, 31, 2, dict(shard_count=8, shard_index=3))
     assert one <= sh <= one + 8192
+
+
+# ---- binding-side checks of device arguments (rejected before the library
+# is called, so CPU tensors reach every check but the device one) ----
+
+def _t():
+    import torch
+    return torch
+
+
+@pytest.mark.parametrize("case", ["bases_dtype", "offsets_int32", "offsets_float", "noncontig", "empty_offsets"])
+def test_binding_rejects_bad_device_reads(lib, case):
+    torch = _t()
+    bases = torch.zeros(64, dtype=torch.uint8)
+    offsets = torch.tensor([0, 32, 64], dtype=torch.int64)
+    if case == "bases_dtype":
+        bases = bases.to(torch.int16)
+    elif case == "offsets_int32":
+        offsets = offsets.to(torch.int32)
+    elif case == "offsets_float":
+        offsets = offsets.to(torch.float64)
+    elif case == "noncontig":
+        bases = torch.zeros(128, dtype=torch.uint8)[::2]
+    elif case == "empty_offsets":
+        offsets = torch.zeros(0, dtype=torch.int64)
+    with pytest.raises(ValueError):
+        tk.tk_count_device(bases, offsets, 31, 2)
+    with pytest.raises(ValueError):
+        tk.tk_count_batch_device(bases, offsets, [0, 64], [0, 2], 31, 2)
+
+
+def test_binding_rejects_host_tensors(lib):
+    torch = _t()
+    with pytest.raises(ValueError, match="CUDA"):
+        tk.tk_count_device(torch.zeros(64, dtype=torch.uint8), torch.tensor([0, 64]), 31, 2)
+
+
+@pytest.mark.parametrize("lb,lr", [([0, 65], [0, 2]), ([0, 64], [0, 3]), ([0, 32, 70], [0, 1, 2])])
+def test_binding_rejects_short_batch_tensors(lib, lb, lr):
+    torch = _t()
+    bases = torch.zeros(64, dtype=torch.uint8)
+    offsets = torch.tensor([0, 32, 64], dtype=torch.int64)
+    with pytest.raises(ValueError, match="at least"):
+        tk.tk_count_batch_device(bases, offsets, lb, lr, 31, 2)
