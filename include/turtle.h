@@ -249,6 +249,34 @@ TK_API tk_status tk_count_device(const uint8_t *d_bases, const uint64_t *d_offse
                           tk_result *out);
 
 /*
+ * tk_count_device without any allocation, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The workspace is a static device array of
+ * TK_STATIC_WORKSPACE_BYTES (256 MiB) inside the library, one per device,
+ * held until the process ends; its address is looked up once per device.
+ * That bounds the library: about 7e6 bases for k <= 31 and 4e6 for k >= 32
+ * (tk_workspace_size <= TK_STATIC_WORKSPACE_BYTES); a larger one is refused
+ * with TK_EINVAL before anything runs.  Arguments as tk_count_device, plus:
+ *   d_out_keys   : device buffer of out_capacity * key_words uint64 (caller's);
+ *   d_out_counts : device buffer of out_capacity uint32 (caller's);
+ * On success the records are copied there (out->keys / out->counts are
+ * these pointers); more records than out_capacity (at most n_bases can
+ * occur) give TK_EINVAL and leave the buffers unspecified.  TK_FLAG_TIMING
+ * is refused (timing creates events).  The call allocates nothing: no
+ * hipMalloc, hipFree, event or stream.  Every call on a device shares that
+ * device's array and finds the previous call's contents, which the counting
+ * path clears or overwrites as it goes; calls on one device are serialised
+ * by a lock inside the library (the call returns only when its work on the
+ * stream is finished).  Other processes have arrays of their own.
+ */
+#define TK_STATIC_WORKSPACE_BYTES (256ull << 20)
+TK_API tk_status tk_count_device_static(const uint8_t *d_bases, const uint64_t *d_offsets,
+                                        uint64_t n_bases, uint64_t n_reads, int k, uint32_t c,
+                                        const tk_options *opts, uint64_t *d_out_keys,
+                                        uint32_t *d_out_counts, uint64_t out_capacity,
+                                        void *stream, tk_result *out);
+
+/*
  * Batches: several read libraries counted in one call, each with its own
  * buckets, Bloom filters, threshold and result -- the libraries are
  * independent counting jobs (§2.1 applied to each library) that share the

@@ -81,6 +81,8 @@ def load_library():
         "tk_count_device": (ctypes.c_int, [_vp, _vp, _u64, _u64, ctypes.c_int, _u32,
                                            P(tk_options), _vp, ctypes.c_size_t, _vp,
                                            P(tk_result)]),
+        "tk_count_device_static": (ctypes.c_int, [_vp, _vp, _u64, _u64, ctypes.c_int, _u32,
+                                                  P(tk_options), _vp, _vp, _u64, _vp, P(tk_result)]),
         "tk_batch_workspace_size": (ctypes.c_int, [_u64, _vp, _vp, ctypes.c_int, _vp, P(tk_options),
                                                    P(ctypes.c_size_t)]),
         "tk_count_batch_device": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, ctypes.c_int, _vp,
@@ -110,7 +112,7 @@ def load_library():
 def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["tk_default_options", "tk_strerror", "tk_last_error", "tk_count", "tk_result_free",
-            "tk_workspace_size", "tk_count_device", "tk_batch_workspace_size", "tk_count_batch_device",
+            "tk_workspace_size", "tk_count_device", "tk_count_device_static", "tk_batch_workspace_size", "tk_count_batch_device",
             "tk_count_phased", "tk_pattern_table", "tk_bloom_blocks", "tk_part_bits",
             "tk_pack_device", "tk_sort_scratch_size", "tk_sort_keys_device",
             "tk_compact_scratch_size", "tk_compact_device"]
@@ -339,6 +341,37 @@ def tk_count_device(bases, offsets, k: int, c: int, opts=None, workspace=None, s
     out = Counts(keys, counts, **_stats(r))
     out.workspace = workspace
     return out
+
+
+STATIC_WORKSPACE_BYTES = 256 << 20
+
+
+def tk_count_device_static(bases, offsets, k: int, c: int, out_keys, out_counts, opts=None,
+                           stream=None) -> Counts:
+    """Count a library held in device memory with the library's static
+    workspace (no device allocation anywhere in the call).  ``out_keys``:
+    CUDA int64 tensor of at least n_records * key_words entries;
+    ``out_counts``: CUDA int32 tensor of at least n_records entries (n_bases
+    entries always suffice).  Returned keys/counts view these tensors."""
+    torch = _torch()
+    lib = load_library()
+    _check_device_reads(bases, offsets)
+    n_bases = int(bases.numel())
+    n_reads = int(offsets.numel()) - 1
+    kw = 1 if k <= 31 else 2
+    for t, dt in ((out_keys, torch.int64), (out_counts, torch.int32)):
+        if not isinstance(t, torch.Tensor) or t.dtype != dt or not t.is_contiguous() or t.device != bases.device:
+            raise ValueError(f"output buffers must be contiguous {dt} tensors on the device of the reads")
+    cap = min(int(out_keys.numel()) // kw, int(out_counts.numel()))
+    o = _opts(opts)
+    r = tk_result()
+    _check(lib.tk_count_device_static(ctypes.c_void_p(bases.data_ptr()) if n_bases else None,
+                                      ctypes.c_void_p(offsets.data_ptr()), n_bases, n_reads, k, c, _optp(o),
+                                      ctypes.c_void_p(out_keys.data_ptr()), ctypes.c_void_p(out_counts.data_ptr()),
+                                      cap, _stream_handle(stream), ctypes.byref(r)),
+           "tk_count_device_static")
+    n = int(r.n)
+    return Counts(out_keys[:n * kw].view(n, kw), out_counts[:n], **_stats(r))
 
 
 def _batch_arrays(lib_bases, lib_reads, c):

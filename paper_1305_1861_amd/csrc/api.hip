@@ -919,6 +919,19 @@ using namespace tk;
 
 namespace {
 
+// Workspace of tk_count_device_static: a file-scope device array, one copy
+// per device, held until the process ends.  Host code never passes its name
+// to a kernel (on the host the name is only a stand-in); it uses the device
+// address from hipGetSymbolAddress, looked up once per device with that
+// device current.
+constexpr size_t STATIC_WORKSPACE_BYTES = TK_STATIC_WORKSPACE_BYTES;
+__device__ __align__(256) unsigned char scratch[STATIC_WORKSPACE_BYTES];
+
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu[STATIC_MAX_DEVICES];  // one call at a time per device
+void *g_static_ptr[STATIC_MAX_DEVICES];       // address of `scratch` on each device
+
+
 // Runs a cleanup when the scope ends, also when a C++ exception (a failed
 // host allocation inside the counting path) unwinds it; the cleanup must be
 // safe to run more than once.
@@ -1054,6 +1067,67 @@ tk_status tk_count_device(const uint8_t *d_bases, const uint64_t *d_offsets, uin
             return fail(TK_EINVAL, "workspace of %zu bytes is below the %zu needed", ws_bytes, p.total);
         return run_count(d_bases, d_offsets, p, static_cast<char *>(d_workspace), static_cast<hipStream_t>(stream),
                          out);
+    });
+}
+
+tk_status tk_count_device_static(const uint8_t *d_bases, const uint64_t *d_offsets, uint64_t n_bases,
+                                 uint64_t n_reads, int k, uint32_t c, const tk_options *opts, uint64_t *d_out_keys,
+                                 uint32_t *d_out_counts, uint64_t out_capacity, void *stream, tk_result *out) {
+    return guarded([&]() -> tk_status {
+        if (!out)
+            return fail(TK_EINVAL, "out is NULL");
+        if (!d_offsets)
+            return fail(TK_EINVAL, "offsets is NULL");
+        if (n_bases && !d_bases)
+            return fail(TK_EINVAL, "bases is NULL");
+        if (out_capacity && (!d_out_keys || !d_out_counts))
+            return fail(TK_EINVAL, "output buffers are NULL");
+        if (opts && (opts->flags & TK_FLAG_TIMING))
+            return fail(TK_EINVAL, "TK_FLAG_TIMING creates events: not available without allocation");
+        Plan p;
+        tk_status st = make_plan(n_bases, n_reads, k, c, opts, &p);
+        if (st != TK_OK)
+            return st;
+        if (p.total > STATIC_WORKSPACE_BYTES)
+            return fail(TK_EINVAL,
+                        "the library needs a workspace of %zu bytes; the static workspace holds %zu "
+                        "(use tk_count_device with a workspace of its own)",
+                        p.total, STATIC_WORKSPACE_BYTES);
+        int dev = -1;
+        TK_HIP(hipGetDevice(&dev));
+        if (dev < 0 || dev >= STATIC_MAX_DEVICES)
+            return fail(TK_EDEVICE, "device %d is beyond the %d the static workspace serves", dev,
+                        STATIC_MAX_DEVICES);
+        std::lock_guard<std::mutex> lock(g_static_mu[dev]);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        // whatever happens below, the stream's work on the array is finished
+        // before the next call on this device may start
+        auto drain = on_exit([&]() { (void)hipStreamSynchronize(s); });
+        if (!g_static_ptr[dev]) {
+            void *ptr = nullptr;
+            TK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr || ((uintptr_t)ptr & 255u))
+                return fail(TK_EDEVICE, "static workspace has no usable device address");
+            g_static_ptr[dev] = ptr;
+        }
+        tk_result dev_res{};
+        st = run_count(d_bases, d_offsets, p, static_cast<char *>(g_static_ptr[dev]), s, &dev_res);
+        if (st != TK_OK)
+            return st;
+        if (dev_res.n > out_capacity)
+            return fail(TK_EINVAL, "%llu records do not fit the output capacity of %llu",
+                        (unsigned long long)dev_res.n, (unsigned long long)out_capacity);
+        if (dev_res.n) {
+            TK_HIP(hipMemcpyAsync(d_out_keys, dev_res.keys, dev_res.n * dev_res.key_words * sizeof(uint64_t),
+                                  hipMemcpyDeviceToDevice, s));
+            TK_HIP(hipMemcpyAsync(d_out_counts, dev_res.counts, dev_res.n * sizeof(uint32_t),
+                                  hipMemcpyDeviceToDevice, s));
+        }
+        TK_HIP(hipStreamSynchronize(s));
+        dev_res.keys = d_out_keys;
+        dev_res.counts = d_out_counts;
+        *out = dev_res;
+        return TK_OK;
     });
 }
 
