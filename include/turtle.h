@@ -278,33 +278,38 @@ TK_API tk_status tk_count_device_static(const uint8_t *d_bases, const uint64_t *
 
 /*
  * Batches: several read libraries counted in one call, each with its own
- * buckets, Bloom filters, threshold and result -- the libraries are
+ * k, buckets, Bloom filters, threshold and result -- the libraries are
  * independent counting jobs (§2.1 applied to each library) that share the
  * kernels' launches.  Library j owns reads [lib_reads[j], lib_reads[j+1])
  * and bases [lib_bases[j], lib_bases[j+1]) of one bases/offsets pair as in
  * tk_count_device (offsets[lib_reads[j]] must equal lib_bases[j]);
  * lib_bases and lib_reads are HOST arrays of n_libs + 1 non-decreasing
- * values starting at 0, c a HOST array of n_libs thresholds (>= 1).  Each
- * library takes its bucket bits D from the size rule on its own bases and
- * reads (or options.part_bits).  Not available with TK_FLAG_GLOBAL_FILTER.
- * Errors: TK_EINVAL (bad boundaries, c = 0, k, options, a batch needing
+ * values starting at 0, k a HOST array of n_libs k-mer lengths (1..63), c a
+ * HOST array of n_libs thresholds (>= 1).  Each library takes its bucket
+ * bits D from the size rule on its own bases, reads and k (or
+ * options.part_bits).  The libraries with one-word keys (k <= 31) and those
+ * with two-word keys (k >= 32) are counted in two passes, one after the
+ * other on the stream, each in its own part of the workspace; a batch of one
+ * key width is one pass.  Not available with TK_FLAG_GLOBAL_FILTER, the
+ * approximate variants or key-range shards.
+ * Errors: TK_EINVAL (bad boundaries, c = 0, k, options, a pass needing
  * 2^31 buckets or more), TK_EOVERFLOW (n_bases >= 2^32).
  */
 TK_API tk_status tk_batch_workspace_size(uint64_t n_libs, const uint64_t *lib_bases,
-                                         const uint64_t *lib_reads, int k,
+                                         const uint64_t *lib_reads, const int *k,
                                          const uint32_t *c, const tk_options *opts,
                                          size_t *bytes);
 
 /*
  * Count a batch held in DEVICE memory.  out is a HOST array of n_libs
- * results; out[j] describes library j as tk_count_device describes its
- * single library (keys and counts are device pointers into the workspace,
- * stage_ms holds the timings of the whole call).  The call blocks until
- * every result is complete on the device.
+ * results; out[j] describes library j exactly as tk_count_device describes
+ * it counted alone (its own k and key_words; keys and counts are device
+ * pointers into the workspace; stage_ms holds the timings of the whole
+ * call).  The call blocks until every result is complete on the device.
  */
 TK_API tk_status tk_count_batch_device(const uint8_t *d_bases, const uint64_t *d_offsets,
                                        uint64_t n_libs, const uint64_t *lib_bases,
-                                       const uint64_t *lib_reads, int k, const uint32_t *c,
+                                       const uint64_t *lib_reads, const int *k, const uint32_t *c,
                                        const tk_options *opts, void *d_workspace,
                                        size_t ws_bytes, void *stream, tk_result *out);
 

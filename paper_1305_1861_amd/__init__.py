@@ -83,9 +83,9 @@ def load_library():
                                            P(tk_result)]),
         "tk_count_device_static": (ctypes.c_int, [_vp, _vp, _u64, _u64, ctypes.c_int, _u32,
                                                   P(tk_options), _vp, _vp, _u64, _vp, P(tk_result)]),
-        "tk_batch_workspace_size": (ctypes.c_int, [_u64, _vp, _vp, ctypes.c_int, _vp, P(tk_options),
+        "tk_batch_workspace_size": (ctypes.c_int, [_u64, _vp, _vp, _vp, _vp, P(tk_options),
                                                    P(ctypes.c_size_t)]),
-        "tk_count_batch_device": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, ctypes.c_int, _vp,
+        "tk_count_batch_device": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, _vp, _vp,
                                                  P(tk_options), _vp, ctypes.c_size_t, _vp, _vp]),
         "tk_count_phased": (ctypes.c_int, [_vp, _vp, _u64, ctypes.c_int, _u32, _u64, _u64, P(tk_options),
                                            P(P(tk_result)), P(ctypes.c_size_t)]),
@@ -374,40 +374,43 @@ def tk_count_device_static(bases, offsets, k: int, c: int, out_keys, out_counts,
     return Counts(out_keys[:n * kw].view(n, kw), out_counts[:n], **_stats(r))
 
 
-def _batch_arrays(lib_bases, lib_reads, c):
+def _batch_arrays(lib_bases, lib_reads, k, c):
     lb = np.ascontiguousarray(np.asarray(lib_bases, dtype=np.uint64))
     lr = np.ascontiguousarray(np.asarray(lib_reads, dtype=np.uint64))
     n_libs = lb.size - 1
     if n_libs < 1 or lr.size != lb.size:
         raise ValueError("lib_bases and lib_reads need n_libs + 1 entries each")
     cc = np.full(n_libs, c, np.uint32) if np.isscalar(c) else np.ascontiguousarray(np.asarray(c, dtype=np.uint32))
-    if cc.size != n_libs:
-        raise ValueError("c needs one threshold per library")
-    return n_libs, lb, lr, cc
+    kk = np.full(n_libs, k, np.int32) if np.isscalar(k) else np.ascontiguousarray(np.asarray(k, dtype=np.int32))
+    if cc.size != n_libs or kk.size != n_libs:
+        raise ValueError("k and c need one value (or one per library)")
+    return n_libs, lb, lr, kk, cc
 
 
-def tk_batch_workspace_size(lib_bases, lib_reads, k: int, c, opts=None) -> int:
-    """Workspace bytes of tk_count_batch_device for these library boundaries."""
-    n_libs, lb, lr, cc = _batch_arrays(lib_bases, lib_reads, c)
+def tk_batch_workspace_size(lib_bases, lib_reads, k, c, opts=None) -> int:
+    """Workspace bytes of tk_count_batch_device for these library boundaries
+    (``k`` and ``c``: one value or one per library)."""
+    n_libs, lb, lr, kk, cc = _batch_arrays(lib_bases, lib_reads, k, c)
     o = _opts(opts)
     out = ctypes.c_size_t(0)
-    _check(load_library().tk_batch_workspace_size(n_libs, lb.ctypes.data, lr.ctypes.data, k, cc.ctypes.data,
-                                                  _optp(o), ctypes.byref(out)), "tk_batch_workspace_size")
+    _check(load_library().tk_batch_workspace_size(n_libs, lb.ctypes.data, lr.ctypes.data, kk.ctypes.data,
+                                                  cc.ctypes.data, _optp(o), ctypes.byref(out)),
+           "tk_batch_workspace_size")
     return int(out.value)
 
 
-def tk_count_batch_device(bases, offsets, lib_bases, lib_reads, k: int, c, opts=None, workspace=None,
+def tk_count_batch_device(bases, offsets, lib_bases, lib_reads, k, c, opts=None, workspace=None,
                           stream=None) -> list:
     """Count a batch of libraries held in device memory (one bases/offsets
     pair; library j owns reads lib_reads[j]..lib_reads[j+1] and bases
-    lib_bases[j]..lib_bases[j+1]).  ``c``: one threshold or one per library.
-    Returns one Counts per library, viewing the workspace."""
+    lib_bases[j]..lib_bases[j+1]).  ``k`` and ``c``: one value or one per
+    library.  Returns one Counts per library, viewing the workspace."""
     torch = _torch()
     lib = load_library()
-    n_libs, lb, lr, cc = _batch_arrays(lib_bases, lib_reads, c)
+    n_libs, lb, lr, kk, cc = _batch_arrays(lib_bases, lib_reads, k, c)
     _check_device_reads(bases, offsets, int(lb[-1]), int(lr[-1]) + 1)
     o = _opts(opts)
-    need = tk_batch_workspace_size(lb, lr, k, cc, o)
+    need = tk_batch_workspace_size(lb, lr, kk, cc, o)
     if workspace is None:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=bases.device)
     _check_workspace(workspace, need, bases.device)
@@ -415,7 +418,7 @@ def tk_count_batch_device(bases, offsets, lib_bases, lib_reads, k: int, c, opts=
     n_bases = int(bases.numel())
     _check(lib.tk_count_batch_device(ctypes.c_void_p(bases.data_ptr()) if n_bases else None,
                                      ctypes.c_void_p(offsets.data_ptr()), n_libs, lb.ctypes.data, lr.ctypes.data,
-                                     k, cc.ctypes.data, _optp(o), ctypes.c_void_p(workspace.data_ptr()),
+                                     kk.ctypes.data, cc.ctypes.data, _optp(o), ctypes.c_void_p(workspace.data_ptr()),
                                      workspace.numel(), _stream_handle(stream), res),
            "tk_count_batch_device")
     base = workspace.data_ptr()

@@ -160,7 +160,8 @@ constexpr uint64_t MAX_BUCKET_GRID = 4096;
 struct Plan {
     int approx;            // 0 exact; 1 cTurtle; 2 single pass with "+1"
     uint64_t approx_words; // filter words of the approximate variants
-    int k, key_words;
+    int k, key_words;      // k: the largest k of the libraries
+    bool mixed_k;          // the libraries do not all have the same k
     uint32_t c;            // global path
     bool screen, global;   // screen: some library has c >= 2
     Opts opts;
@@ -190,53 +191,70 @@ struct Misc {
     uint32_t pad[3];
 };
 
-// Plan of one call over n_libs libraries: library j owns reads
-// [lib_reads[j], lib_reads[j + 1]) and bases [lib_bases[j], lib_bases[j + 1]).
-tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *lib_reads, int k, const uint32_t *c,
-                    const tk_options *o, Plan *p) {
-    if (k < 1 || k > 63)
-        return fail(TK_EINVAL, "k = %d outside [1, 63]", k);
-    if (n_libs == 0 || !lib_bases || !lib_reads || !c)
-        return fail(TK_EINVAL, "a batch needs at least one library and its boundaries and thresholds");
+// One library of a plan: window positions [pos0, pos1) of the bases array,
+// its number of reads, k and threshold.
+struct LibSpec {
+    uint64_t pos0, pos1, n_reads;
+    int k;
+    uint32_t c;
+};
+
+// Plan of one counting pass over the libraries `ls` (ordered by position,
+// all with keys of the same width) of one bases/offsets pair of n_bases
+// bases and n_reads reads.
+tk_status make_plan(const LibSpec *ls, uint64_t n_libs, uint64_t n_bases, uint64_t n_reads, const tk_options *o,
+                    Plan *p) {
+    if (n_libs == 0 || !ls)
+        return fail(TK_EINVAL, "a batch needs at least one library");
     if (n_libs >= (1ull << 24))
         return fail(TK_EINVAL, "%llu libraries are too many", (unsigned long long)n_libs);
-    if (lib_bases[0] != 0 || lib_reads[0] != 0)
-        return fail(TK_EINVAL, "library boundaries must start at 0");
-    for (uint64_t j = 0; j < n_libs; j++) {
-        if (lib_bases[j + 1] < lib_bases[j] || lib_reads[j + 1] < lib_reads[j])
-            return fail(TK_EINVAL, "library boundaries decrease at library %llu", (unsigned long long)j);
-        if (c[j] == 0)
-            return fail(TK_EINVAL, "threshold c of library %llu must be >= 1", (unsigned long long)j);
-    }
-    const uint64_t n_bases = lib_bases[n_libs], n_reads = lib_reads[n_libs];
     if (n_bases >= (1ull << 32))
         return fail(TK_EOVERFLOW, "n_bases = %llu must be below 2^32", (unsigned long long)n_bases);
     if (n_reads >= (1ull << 40))
         return fail(TK_EOVERFLOW, "n_reads = %llu too large", (unsigned long long)n_reads);
+    int kmax = 0;
+    uint64_t cap = 0;
+    for (uint64_t j = 0; j < n_libs; j++) {
+        if (ls[j].k < 1 || ls[j].k > 63)
+            return fail(TK_EINVAL, "k = %d outside [1, 63]", ls[j].k);
+        if (ls[j].c == 0)
+            return fail(TK_EINVAL, "threshold c must be >= 1");
+        if ((ls[j].k <= 31) != (ls[0].k <= 31))
+            return fail(TK_EINVAL, "one counting pass takes keys of one width");
+        if (ls[j].pos1 < ls[j].pos0 || ls[j].pos1 > n_bases || (j && ls[j].pos0 < ls[j - 1].pos1))
+            return fail(TK_EINVAL, "library %llu lies outside the bases or before the previous one",
+                        (unsigned long long)j);
+        kmax = std::max(kmax, ls[j].k);
+        cap += ls[j].pos1 - ls[j].pos0;  // windows <= bases
+    }
     tk_status st = resolve(o, &p->opts);
     if (st != TK_OK)
         return st;
+    const int k = kmax;
     p->k = k;
-    p->c = c[0];
+    p->mixed_k = false;
+    for (uint64_t j = 0; j < n_libs; j++)
+        p->mixed_k = p->mixed_k || ls[j].k != k;
+    p->c = ls[0].c;
     p->key_words = k <= 31 ? 1 : 2;
     p->key_bytes = 8 * (size_t)p->key_words;
     p->screen = false;
     for (uint64_t j = 0; j < n_libs; j++)
-        p->screen = p->screen || c[j] >= 2;
+        p->screen = p->screen || ls[j].c >= 2;
     p->approx = (p->opts.flags & TK_FLAG_CTURTLE) ? 1 : (p->opts.flags & TK_FLAG_SINGLE_PASS) ? 2 : 0;
     p->global = (p->opts.flags & TK_FLAG_GLOBAL_FILTER) || p->approx;
     if (p->global && n_libs != 1)
         return fail(TK_EINVAL, "the global-filter path and the approximate variants count one library per call");
     if (p->opts.shard_count > 1 && n_libs != 1)
         return fail(TK_EINVAL, "key-range shards split one library per call");
-    if (p->approx == 1 && c[0] != 2)
+    if (p->approx == 1 && p->c != 2)
         return fail(TK_EINVAL, "cTurtle reports k-mers seen more than once: c must be 2");
     if (p->approx)
         p->screen = true;
     p->n_bases = n_bases;
     p->n_reads = n_reads;
     p->n_words = ceil_div(n_bases, 32);
-    p->cap = n_bases;  // windows <= bases
+    p->cap = cap;
     p->n_blocks = (p->screen && p->global) ? bloom_blocks_for(n_bases, n_reads, k, p->opts) : 0;
     p->approx_words = 0;
     if (p->approx) {
@@ -256,10 +274,11 @@ tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *
         p->libs.resize(n_libs);
         for (uint64_t j = 0; j < n_libs; j++) {
             LibDesc &L = p->libs[j];
-            L.pos0 = lib_bases[j];
-            L.pos1 = lib_bases[j + 1];
-            L.c = c[j];
-            L.D = part_bits_for(L.pos1 - L.pos0, lib_reads[j + 1] - lib_reads[j], k, p->opts);
+            L.pos0 = ls[j].pos0;
+            L.pos1 = ls[j].pos1;
+            L.c = ls[j].c;
+            L.k = ls[j].k;
+            L.D = part_bits_for(L.pos1 - L.pos0, ls[j].n_reads, L.k, p->opts);
             L.D1 = std::min(L.D, 10);
             L.D2 = L.D - L.D1;
             L.nch1 = L.pos1 > L.pos0 ? (uint32_t)ceil_div(L.pos1 - (L.pos0 & ~31ull), chunk) : 0u;
@@ -278,7 +297,6 @@ tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *
                         (unsigned long long)n_bk);
         p->n_buckets = n_bk;
         p->part = PartPlan{};
-        p->part.k = k;
         p->part.n_libs = (uint32_t)n_libs;
         p->part.nch1 = (uint32_t)n_ch;
         p->part.n_hist1 = n_hist;
@@ -343,10 +361,65 @@ tk_status make_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *
 }
 
 tk_status make_plan(uint64_t n_bases, uint64_t n_reads, int k, uint32_t c, const tk_options *o, Plan *p) {
-    const uint64_t lb[2] = {0, n_bases}, lr[2] = {0, n_reads};
-    if (c == 0)
-        return fail(TK_EINVAL, "threshold c must be >= 1");
-    return make_plan(1, lb, lr, k, &c, o, p);
+    const LibSpec one{0, n_bases, n_reads, k, c};
+    return make_plan(&one, 1, n_bases, n_reads, o, p);
+}
+
+// A batch of libraries (library j: reads [lib_reads[j], lib_reads[j + 1]),
+// bases [lib_bases[j], lib_bases[j + 1])) in at most two counting passes,
+// one per key width, each in its own part of the workspace: member[q] lists
+// the libraries of pass q, ws_off[q] the start of its part.
+struct BatchPlan {
+    std::vector<Plan> plans;
+    std::vector<std::vector<uint32_t>> member;
+    std::vector<size_t> ws_off;
+    size_t total = 0;
+};
+
+tk_status make_batch_plan(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *lib_reads, const int *k,
+                          const uint32_t *c, const tk_options *o, BatchPlan *bp) {
+    if (n_libs == 0 || !lib_bases || !lib_reads || !k || !c)
+        return fail(TK_EINVAL, "a batch needs at least one library and its boundaries, k and thresholds");
+    if (n_libs >= (1ull << 24))
+        return fail(TK_EINVAL, "%llu libraries are too many", (unsigned long long)n_libs);
+    if (lib_bases[0] != 0 || lib_reads[0] != 0)
+        return fail(TK_EINVAL, "library boundaries must start at 0");
+    for (uint64_t j = 0; j < n_libs; j++) {
+        if (lib_bases[j + 1] < lib_bases[j] || lib_reads[j + 1] < lib_reads[j])
+            return fail(TK_EINVAL, "library boundaries decrease at library %llu", (unsigned long long)j);
+        if (c[j] == 0)
+            return fail(TK_EINVAL, "threshold c of library %llu must be >= 1", (unsigned long long)j);
+        if (k[j] < 1 || k[j] > 63)
+            return fail(TK_EINVAL, "k = %d of library %llu outside [1, 63]", k[j], (unsigned long long)j);
+    }
+    const uint64_t n_bases = lib_bases[n_libs], n_reads = lib_reads[n_libs];
+    bp->plans.clear();
+    bp->member.clear();
+    bp->ws_off.clear();
+    bp->total = 0;
+    for (int width = 1; width <= 2; width++) {
+        std::vector<LibSpec> ls;
+        std::vector<uint32_t> mem;
+        for (uint64_t j = 0; j < n_libs; j++) {
+            if ((k[j] <= 31 ? 1 : 2) != width)
+                continue;
+            ls.push_back(LibSpec{lib_bases[j], lib_bases[j + 1], lib_reads[j + 1] - lib_reads[j], k[j], c[j]});
+            mem.push_back((uint32_t)j);
+        }
+        if (ls.empty())
+            continue;
+        Plan p;
+        tk_status st = make_plan(ls.data(), ls.size(), n_bases, n_reads, o, &p);
+        if (st != TK_OK)
+            return st;
+        if (p.global)
+            return fail(TK_EINVAL, "batches run the partitioned path only");
+        bp->ws_off.push_back(bp->total);
+        bp->total = align_up(bp->total + p.total, 256);
+        bp->plans.push_back(std::move(p));
+        bp->member.push_back(std::move(mem));
+    }
+    return TK_OK;
 }
 
 __global__ void zero_vec(uint4 *__restrict__ p, uint64_t n) {
@@ -717,7 +790,8 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
 
     if ((st = tm.mark(TK_STAGE_PACK, s)) != TK_OK)
         return st;
-    TK_HIP(launch_pack(d_bases, d_offsets, p.n_bases, p.n_reads, p.k, packed, valid, starts, nullptr, s));
+    TK_HIP(launch_pack(d_bases, d_offsets, p.n_bases, p.n_reads, p.k, packed, valid, starts, nullptr, s,
+                       p.mixed_k ? d_libs : nullptr, L));
     if ((st = tm.end(TK_STAGE_PACK, s)) != TK_OK || (st = tm.mark(TK_STAGE_PARTITION, s)) != TK_OK)
         return st;
 
@@ -738,7 +812,6 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
     ba.libs = d_libs;
     ba.n_libs = L;
     ba.lib_keys = lib_keys;
-    ba.k = p.k;
     ba.beta = p.opts.beta;
     ba.table = table;
     ba.table_bits = p.opts.table_bits;
@@ -856,11 +929,11 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
             uint64_t *src = fbuf + gr.w0 * kw, *alt = sorted + gr.w0 * kw;
             uint64_t *srt = nullptr;
             int passes = 0;
-            TK_HIP(radix_sort(src, alt, n_surv, kw, 2 * p.k, ws + p.off_sort, p.sort_bytes, s, &srt, &passes));
+            TK_HIP(radix_sort(src, alt, n_surv, kw, 2 * lib.k, ws + p.off_sort, p.sort_bytes, s, &srt, &passes));
             uint64_t *dst = srt == src ? alt : src;
             TK_HIP(compact(srt, n_surv, kw, lib.c, dst, fb_counts + gr.w0, ws + p.off_compact, p.compact_bytes,
                            &lib_ctr[gr.lib], s));
-            TK_HIP(launch_fb_distribute(dst, fb_counts + gr.w0, &lib_ctr[gr.lib], d_ent + gr.e0, gr.ne, kw, p.k,
+            TK_HIP(launch_fb_distribute(dst, fb_counts + gr.w0, &lib_ctr[gr.lib], d_ent + gr.e0, gr.ne, kw, lib.k,
                                         lib.D, lib.bucket0, other, gap_counts, rec_nout,
                                         lib_stats + 4 * (size_t)gr.lib, s));
         }
@@ -888,7 +961,7 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
         tk_result &o = out[j];
         memset(&o, 0, sizeof o);
         o.n = h[j].n_out;
-        o.k = (uint32_t)p.k;
+        o.k = (uint32_t)p.libs[j].k;
         o.key_words = (uint32_t)kw;
         o.keys = sorted + (size_t)first[j] * kw;
         o.counts = out_counts + first[j];
@@ -1131,22 +1204,22 @@ tk_status tk_count_device_static(const uint8_t *d_bases, const uint64_t *d_offse
     });
 }
 
-tk_status tk_batch_workspace_size(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *lib_reads, int k,
-                                  const uint32_t *c, const tk_options *opts, size_t *bytes) {
+tk_status tk_batch_workspace_size(uint64_t n_libs, const uint64_t *lib_bases, const uint64_t *lib_reads,
+                                  const int *k, const uint32_t *c, const tk_options *opts, size_t *bytes) {
     return guarded([&]() -> tk_status {
         if (!bytes)
             return fail(TK_EINVAL, "bytes is NULL");
-        Plan p;
-        tk_status st = make_plan(n_libs, lib_bases, lib_reads, k, c, opts, &p);
+        BatchPlan bp;
+        tk_status st = make_batch_plan(n_libs, lib_bases, lib_reads, k, c, opts, &bp);
         if (st != TK_OK)
             return st;
-        *bytes = p.total;
+        *bytes = bp.total;
         return TK_OK;
     });
 }
 
 tk_status tk_count_batch_device(const uint8_t *d_bases, const uint64_t *d_offsets, uint64_t n_libs,
-                                const uint64_t *lib_bases, const uint64_t *lib_reads, int k, const uint32_t *c,
+                                const uint64_t *lib_bases, const uint64_t *lib_reads, const int *k, const uint32_t *c,
                                 const tk_options *opts, void *d_workspace, size_t ws_bytes, void *stream,
                                 tk_result *out) {
     return guarded([&]() -> tk_status {
@@ -1158,16 +1231,32 @@ tk_status tk_count_batch_device(const uint8_t *d_bases, const uint64_t *d_offset
             return fail(TK_EINVAL, "workspace is NULL");
         if ((uintptr_t)d_workspace & 255u)
             return fail(TK_EINVAL, "workspace must be 256-byte aligned");
-        Plan p;
-        tk_status st = make_plan(n_libs, lib_bases, lib_reads, k, c, opts, &p);
+        BatchPlan bp;
+        tk_status st = make_batch_plan(n_libs, lib_bases, lib_reads, k, c, opts, &bp);
         if (st != TK_OK)
             return st;
-        if (p.n_bases && !d_bases)
+        if (lib_bases[n_libs] && !d_bases)
             return fail(TK_EINVAL, "bases is NULL");
-        if (ws_bytes < p.total)
-            return fail(TK_EINVAL, "workspace of %zu bytes is below the %zu needed", ws_bytes, p.total);
-        return run_count(d_bases, d_offsets, p, static_cast<char *>(d_workspace), static_cast<hipStream_t>(stream),
-                         out);
+        if (ws_bytes < bp.total)
+            return fail(TK_EINVAL, "workspace of %zu bytes is below the %zu needed", ws_bytes, bp.total);
+        // one counting pass per key width, one after the other on the stream,
+        // each in its own part of the workspace
+        double ms[TK_STAGE_COUNT] = {0};
+        std::vector<tk_result> part;
+        for (size_t q = 0; q < bp.plans.size(); q++) {
+            part.assign(bp.member[q].size(), tk_result{});
+            st = run_partitioned(d_bases, d_offsets, bp.plans[q], static_cast<char *>(d_workspace) + bp.ws_off[q],
+                                 static_cast<hipStream_t>(stream), part.data());
+            if (st != TK_OK)
+                return st;
+            for (size_t i = 0; i < part.size(); i++)
+                out[bp.member[q][i]] = part[i];
+            for (int t = 0; t < TK_STAGE_COUNT; t++)
+                ms[t] += part.empty() ? 0.0 : part[0].stage_ms[t];
+        }
+        for (uint64_t j = 0; j < n_libs; j++)
+            memcpy(out[j].stage_ms, ms, sizeof ms);
+        return TK_OK;
     });
 }
 

@@ -271,10 +271,11 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             }
         }
         const int D = a.libs[jl].D;            // bucket bits of the library
+        const int kk = a.libs[jl].k;           // its k
         const uint32_t c = a.libs[jl].c;       // its threshold
         const bool screen = c >= 2;
         const uint32_t bucket0 = a.libs[jl].bucket0;
-        const int SB = 2 * a.k - D;  // key bits below the bucket digit
+        const int SB = 2 * kk - D;  // key bits below the bucket digit
 
         // ---- a group of whole buckets b0..b1 of one library (planned
         // before the launch; keys loaded by the previous iteration) ----
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         for (int i = 0; i < ITEMS; i++) {
             rb[i] = 0;
             if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb)
-                rb[i] = bucket_of(key[i], a.k, D) - d0;
+                rb[i] = bucket_of(key[i], kk, D) - d0;
         }
         // span of bucket ids in the group -> bits of the bucket part of the sort key
         const uint32_t span = R - 1;

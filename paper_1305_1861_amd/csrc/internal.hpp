@@ -28,11 +28,6 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Clears n bytes (n a multiple of 4, p 4-byte aligned) with fill kernels.
 hipError_t zero_bytes(void *p, size_t n, hipStream_t stream);
 
-// ---- pack.hip -------------------------------------------------------------
-// starts: n_words uint32, must be zero on entry.  n_windows may be null.
-hipError_t launch_pack(const uint8_t *bases, const uint64_t *offsets, uint64_t n_bases,
-                       uint64_t n_reads, int k, uint64_t *packed, uint32_t *valid,
-                       uint32_t *starts, unsigned long long *n_windows, hipStream_t stream);
 
 // ---- bloom.hip ------------------------------------------------------------
 struct BloomArgs {
@@ -62,7 +57,18 @@ struct LibDesc {
     uint32_t bucket0;     // first bucket id (2^D buckets per library)
     uint32_t c;           // threshold
     int D, D1, D2;        // bucket bits D = D1 (pass 1) + D2 (pass 2)
+    int k;                // k-mer length of the library
 };
+
+// ---- pack.hip -------------------------------------------------------------
+// starts: n_words uint32, must be zero on entry.  n_windows may be null.
+// libs (device, n_libs entries ordered by position): when given, the
+// validity bits of each library's positions use that library's k (k is
+// then unused) and positions outside the listed libraries stay clear.
+hipError_t launch_pack(const uint8_t *bases, const uint64_t *offsets, uint64_t n_bases,
+                       uint64_t n_reads, int k, uint64_t *packed, uint32_t *valid,
+                       uint32_t *starts, unsigned long long *n_windows, hipStream_t stream,
+                       const LibDesc *libs = nullptr, uint32_t n_libs = 0);
 
 // ---- partition.hip --------------------------------------------------------
 // Keys of every valid window, ordered by (library, top D bits): every bucket
@@ -76,8 +82,7 @@ uint64_t partition_chunk(int key_words);  // window positions (pass 1) or keys (
 struct PartPlan {
     const uint64_t *packed;
     const uint32_t *valid;
-    int k;
-    const LibDesc *libs;  // device
+    const LibDesc *libs;  // device; every library has its own k
     uint32_t n_libs;
     uint32_t nch1;        // pass-1 chunks of all libraries
     uint64_t n_hist1;     // pass-1 count entries of all libraries
@@ -101,7 +106,6 @@ struct BucketArgs {
     const LibDesc *libs;      // device
     uint32_t n_libs;
     const uint32_t *lib_keys; // first key of every library, number of keys (device)
-    int k;
     uint32_t beta;
     const uint64_t *table;
     uint32_t table_bits;

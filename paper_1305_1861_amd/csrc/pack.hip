@@ -125,9 +125,38 @@ __global__ void mark_read_starts(const uint64_t *__restrict__ offsets, uint64_t 
         atomicOr(&starts[p >> 5], 1u << (p & 31));
 }
 
+// Validity bits of word w when the libraries of a batch have different k:
+// each library overlapping the word (libraries ordered by position, maybe
+// with gaps) sets the bits of its own positions with its own k; positions of
+// no listed library stay clear.
+__device__ __forceinline__ uint32_t window_bits_libs(uint32_t bad, uint32_t st, int run0, uint64_t w,
+                                                     const LibDesc *__restrict__ libs, uint32_t n_libs) {
+    const uint64_t p0 = w * 32, p1 = p0 + 32;
+    // first library ending after p0
+    uint32_t lo = 0, hi = n_libs;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (libs[mid].pos1 <= p0)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    uint32_t v = 0;
+    for (uint32_t j = lo; j < n_libs && libs[j].pos0 < p1; j++) {
+        const uint64_t a = max(libs[j].pos0, p0), b = min(libs[j].pos1, p1);
+        if (a >= b)
+            continue;
+        const uint32_t na = (uint32_t)(a - p0), nb = (uint32_t)(b - p0);  // bits [na, nb)
+        const uint32_t mask = (nb == 32 ? ~0u : (1u << nb) - 1u) & (~0u << na);
+        v |= window_bits(bad, st, run0, libs[j].k) & mask;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(PACK_THREADS) void pack_kernel(const uint8_t *__restrict__ bases, uint64_t n_bases,
                                                             uint64_t n_words, bool aligned,
                                                             const uint32_t *__restrict__ starts, int k,
+                                                            const LibDesc *__restrict__ libs, uint32_t n_libs,
                                                             uint64_t *__restrict__ packed,
                                                             uint32_t *__restrict__ valid,
                                                             unsigned long long *__restrict__ n_windows) {
@@ -168,7 +197,8 @@ __global__ __launch_bounds__(PACK_THREADS) void pack_kernel(const uint8_t *__res
         const uint64_t st64 = (uint64_t)s_st[tid] | ((uint64_t)s_st[tid + 1] << 32);
         const int qb = bad64 ? 63 - __clzll(bad64) : -1;
         const int qs = st64 ? 63 - __clzll(st64) : -1;
-        vbits = window_bits(bad, st, 64 - max(qb + 1, qs), k);
+        const int run0 = 64 - max(qb + 1, qs);
+        vbits = libs ? window_bits_libs(bad, st, run0, w, libs, n_libs) : window_bits(bad, st, run0, k);
         valid[w] = vbits;
     }
     // valid windows of the block -> one atomic per block
@@ -192,7 +222,7 @@ __global__ __launch_bounds__(PACK_THREADS) void pack_kernel(const uint8_t *__res
 
 hipError_t launch_pack(const uint8_t *bases, const uint64_t *offsets, uint64_t n_bases, uint64_t n_reads, int k,
                        uint64_t *packed, uint32_t *valid, uint32_t *starts, unsigned long long *n_windows,
-                       hipStream_t stream) {
+                       hipStream_t stream, const LibDesc *libs, uint32_t n_libs) {
     const uint64_t n_words = ceil_div(n_bases, 32);
     if (n_words == 0)
         return hipSuccess;
@@ -206,7 +236,7 @@ hipError_t launch_pack(const uint8_t *bases, const uint64_t *offsets, uint64_t n
     const bool aligned = ((uintptr_t)bases & 15u) == 0;
     const uint64_t g = ceil_div(n_words, PACK_THREADS);
     pack_kernel<<<dim3((unsigned)g), dim3(PACK_THREADS), 0, stream>>>(bases, n_bases, n_words, aligned, starts, k,
-                                                                     packed, valid, n_windows);
+                                                                     libs, n_libs, packed, valid, n_windows);
     return hipGetLastError();
 }
 

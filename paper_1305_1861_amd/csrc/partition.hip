@@ -71,7 +71,6 @@ struct PassArgs {
     const uint64_t *packed;
     const uint32_t *valid;
     const void *keys_in;     // pass 2: the pass-1 output
-    int k;
     const LibDesc *libs;
     uint32_t n_libs;
     const uint32_t *seg;     // pass 2: start of every segment (nseg + 1)
@@ -90,6 +89,7 @@ struct Chunk {
     uint64_t c0, c1, lo, hidx;
     uint32_t hstride;
     int shift, bits;
+    int k;  // the library's k-mer length
 };
 
 template <typename K, bool FROM_WIN>
@@ -106,8 +106,9 @@ __device__ __forceinline__ bool chunk_of(const PassArgs &a, Chunk &ch) {
         ch.lo = L.pos0;
         ch.hidx = L.h1 + i;
         ch.hstride = L.nch1;
-        ch.shift = 2 * a.k - L.D1;
+        ch.shift = 2 * L.k - L.D1;
         ch.bits = L.D1;
+        ch.k = L.k;
         return true;
     }
     if (b >= a.cb[a.nseg])
@@ -120,8 +121,9 @@ __device__ __forceinline__ bool chunk_of(const PassArgs &a, Chunk &ch) {
     ch.lo = ch.c0;
     ch.hidx = a.eb[s] + i;
     ch.hstride = a.cb[s + 1] - a.cb[s];
-    ch.shift = 2 * a.k - a.libs[j].D;
+    ch.shift = 2 * a.libs[j].k - a.libs[j].D;
     ch.bits = a.libs[j].D2;
+    ch.k = a.libs[j].k;
     return true;
 }
 
@@ -164,7 +166,7 @@ __device__ __forceinline__ RawWin fetch_win(const PassArgs &a, uint64_t t0, uint
 }
 
 template <typename K>
-__device__ __forceinline__ uint32_t extract_win(const PassArgs &a, const RawWin &r, K (&key)[PtItems<K>::value]) {
+__device__ __forceinline__ uint32_t extract_win(const RawWin &r, int k, K (&key)[PtItems<K>::value]) {
     constexpr int ITEMS = PtItems<K>::value;
     constexpr int PER_WORD = 32 / ITEMS;
     const uint32_t first = (uint32_t)(threadIdx.x % PER_WORD) * ITEMS;
@@ -177,7 +179,7 @@ __device__ __forceinline__ uint32_t extract_win(const PassArgs &a, const RawWin 
         // consecutive windows: the first extracted whole, the others
         // rolled on by one base each
         typename KeyOf<std::is_same<K, Key2>::value>::Roll rl;
-        rl.init(r.w0, r.w1, r.w2, first, a.k);
+        rl.init(r.w0, r.w1, r.w2, first, k);
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             if (i)
@@ -211,11 +213,11 @@ __device__ __forceinline__ uint64_t codes_ending_at(const RawWin &r, int u) {
 }
 
 template <typename K, bool FROM_WIN>
-__device__ __forceinline__ uint32_t load_tile(const PassArgs &a, uint64_t t0, uint64_t t1, uint64_t lo,
+__device__ __forceinline__ uint32_t load_tile(const PassArgs &a, uint64_t t0, uint64_t t1, uint64_t lo, int k,
                                               K (&key)[PtItems<K>::value]) {
     constexpr int ITEMS = PtItems<K>::value;
     if (FROM_WIN)
-        return extract_win<K>(a, fetch_win<K>(a, t0, t1, lo), key);
+        return extract_win<K>(fetch_win<K>(a, t0, t1, lo), k, key);
     const int tid = threadIdx.x;
     uint32_t vm = 0;
     const K *__restrict__ in = static_cast<const K *>(a.keys_in);
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(PT_THREADS) void pt_hist(PassArgs a, uint32_t *__re
             RawWin nxt{0, 0, 0, 0, 0};
             if (tn < ch.c1)
                 nxt = fetch_win<K>(a, tn, min(tn + pt_tile<K>(), ch.c1), ch.lo);
-            if (cur.okmask && a.k >= 5) {
+            if (cur.okmask && ch.k >= 5) {
                 // The top bits of the canonical key, the smaller of the
                 // forward code and its reverse complement, are the smaller
                 // of the two codes' top bits.  So a window's digit (at most
@@ -264,7 +266,7 @@ __global__ __launch_bounds__(PT_THREADS) void pt_hist(PassArgs a, uint32_t *__re
                 const int first = (tid % PER_WORD) * ITEMS;
                 const uint32_t ok = (cur.vword >> first) & cur.okmask;
                 const uint64_t last5 = ~group_reverse(codes_ending_at(cur, first + ITEMS - 1));
-                const uint64_t first5 = codes_ending_at(cur, first + ITEMS + 4 - a.k);
+                const uint64_t first5 = codes_ending_at(cur, first + ITEMS + 4 - ch.k);
                 const int drop = 10 - ch.bits;
 #pragma unroll
                 for (int i = 0; i < ITEMS; i++) {
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(PT_THREADS) void pt_hist(PassArgs a, uint32_t *__re
                 const uint32_t first = (uint32_t)(tid % PER_WORD) * ITEMS;
                 const uint32_t ok = (cur.vword >> first) & cur.okmask;
                 typename KeyOf<std::is_same<K, Key2>::value>::Roll rl;
-                rl.init(cur.w0, cur.w1, cur.w2, first, a.k);
+                rl.init(cur.w0, cur.w1, cur.w2, first, ch.k);
 #pragma unroll
                 for (int i = 0; i < ITEMS; i++) {
                     if (i)
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(PT_THREADS) void pt_hist(PassArgs a, uint32_t *__re
     } else {
         for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += pt_tile<K>()) {
             K key[ITEMS];
-            const uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + pt_tile<K>(), ch.c1), ch.lo, key);
+            const uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + pt_tile<K>(), ch.c1), ch.lo, ch.k, key);
 #pragma unroll
             for (int i = 0; i < ITEMS; i++)
                 if ((vm >> i) & 1u)
@@ -339,7 +341,7 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint3
     __syncthreads();
     for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += TILE) {
         K key[ITEMS];
-        uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + (uint64_t)TILE, ch.c1), ch.lo, key);
+        uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + (uint64_t)TILE, ch.c1), ch.lo, ch.k, key);
         uint32_t rd[ITEMS];  // (rank << 10) | digit
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
@@ -563,7 +565,6 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
     PassArgs a{};
     a.packed = p.packed;
     a.valid = p.valid;
-    a.k = p.k;
     a.libs = p.libs;
     a.n_libs = p.n_libs;
     a.seg = seg;

@@ -1,22 +1,29 @@
 """Continuous batching of counting jobs on one GPU.
 
 A job is one read library (host ``bases``/``offsets`` arrays) with its k and
-threshold c.  Jobs wait in arrival order; a dispatcher takes the oldest job
-and every other waiting job of the same k, up to a budget of bases, and hands
-them to a free worker as one batch (``tk_count_batch_device``: every library
-keeps its own buckets, filters, threshold and result).  Each worker owns a
-HIP stream and keeps its device buffers -- input bases and offsets and the
-counting workspace -- for the whole life of the server, sized once for the
-budget, so admitting a job never allocates device memory.  Two workers let
-one batch's host-to-device copy and result copy overlap the other's kernels.
-Jobs reach the device through pinned host buffers of the same size (one
-host copy per job into its slice, then one transfer per batch, offsets
-rebased on the host), and results come back through a pinned buffer per
-worker (grown to the largest batch's records) into ordinary host arrays:
-copies from pageable memory ran at about 4 GB/s.
+threshold c.  Every job's device footprint is computed from the library's own
+sizing rules -- the workspace ``tk_batch_workspace_size`` gives for it plus
+its input bytes -- and a job is admitted only while the footprint of its
+batch fits the device memory a worker holds.  The server reserves that
+memory once, at start: ``hbm_bytes`` (by default 60 % of the device memory
+free at start) split evenly over the workers, each share one resident device
+arena that holds a batch's workspace (filters, key and sort buffers), its
+reads and its offsets, reused from batch to batch, so admitting a job never
+allocates device memory.
 
-Results are host arrays, identical to what a single ``tk_count_device``
-call on the job alone returns.
+Jobs wait in arrival order; when a worker is free, the dispatcher hands it
+the oldest waiting job plus every later waiting job that still fits the
+worker's arena (at most ``max_batch_libs`` jobs), whatever their k: one
+``tk_count_batch_device`` call counts the batch, every library with its own
+k, buckets, filters, threshold and result.  Each worker owns a HIP stream, so
+one batch's copies overlap the other's kernels.  Jobs reach the device
+through a pinned host buffer per worker (one host copy per job into its
+slice, then one transfer per batch, offsets rebased on the host), and
+results come back through pinned buffers into ordinary host arrays: copies
+from pageable memory ran at about 4 GB/s.
+
+Results are host arrays, identical to what a single ``tk_count_device`` call
+on the job alone returns.
 """
 from __future__ import annotations
 
@@ -29,6 +36,12 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _torch, load_library, tk_batch_workspace_size, tk_count_batch_device, tk_default_options
+
+_ALIGN = 256
+
+
+def _align(x: int) -> int:
+    return (x + _ALIGN - 1) // _ALIGN * _ALIGN
 
 
 @dataclass
@@ -51,6 +64,7 @@ class JobResult:
     t_submit: float
     t_start: float
     t_done: float
+    batch_jobs: int = 1  # jobs counted in the same call
 
     @property
     def latency_s(self) -> float:
@@ -60,40 +74,29 @@ class JobResult:
 class Server:
     """Counting server: ``submit(job)`` returns a Future of a JobResult.
 
-    ``max_batch_bases`` bounds the bases of one batch (and of one job: a
-    larger job is refused); ``max_batch_reads`` bounds its reads;
-    ``max_batch_libs`` its number of jobs.  Device memory per worker: the
-    input buffers plus the workspace of the largest batch these bounds
-    allow.  Pinned host memory per worker: input buffers of the same size,
-    and a result buffer grown to the largest batch's records seen so far.
+    ``hbm_bytes``: device memory the server holds (default: 60 % of what is
+    free at start), split evenly over ``workers``; a job whose footprint
+    exceeds one worker's share is refused at submission.
+    ``max_batch_libs``: jobs per batch.  ``linger_s``: how long the
+    dispatcher waits for more arrivals before handing out a batch.
     """
 
-    def __init__(self, max_batch_bases: int = 1 << 28, max_batch_reads: int = 1 << 22, max_batch_libs: int = 64,
-                 workers: int = 2, opts=None, device: str = "cuda:0", linger_s: float = 0.0):
+    def __init__(self, hbm_bytes: int | None = None, workers: int = 2, max_batch_libs: int = 64, opts=None,
+                 device: str = "cuda:0", linger_s: float = 0.0):
         torch = _torch()
         load_library()
         self.torch = torch
         self.device = torch.device(device)
-        self.max_bases = int(max_batch_bases)
-        self.max_reads = int(max_batch_reads)
+        if hbm_bytes is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            hbm_bytes = int(0.6 * free)
+        self.share = (int(hbm_bytes) // workers) // _ALIGN * _ALIGN
+        if self.share < (1 << 20):
+            raise ValueError("the server needs at least 1 MiB of device memory per worker")
         self.max_libs = int(max_batch_libs)
         self.opts = opts if opts is not None else tk_default_options()
         self.linger_s = linger_s
-        # workspace bound: the largest of one library of all the bases and of
-        # max_libs equal libraries sharing them, for the widest key
-        ws = 0
-        for k in (31, 63):
-            one = tk_batch_workspace_size([0, self.max_bases], [0, self.max_reads], k, [2], self.opts)
-            nb = np.linspace(0, self.max_bases, self.max_libs + 1).astype(np.uint64)
-            nr = np.linspace(0, self.max_reads, self.max_libs + 1).astype(np.uint64)
-            many = tk_batch_workspace_size(nb, nr, k, [2] * self.max_libs, self.opts)
-            ws = max(ws, one, many)
-        # a quarter more for other splits of the budget (bucket and chunk
-        # tables grow with rounding per library); a batch that still needs
-        # more fails with the library's workspace error
-        ws = int(ws * 1.25) // 256 * 256 + 256
-        self.ws_bytes = ws
-        self._pending: list[tuple[Job, Future]] = []
+        self._pending: list[tuple[Job, Future, int]] = []  # job, future, its own footprint
         self._cv = threading.Condition()
         self._idle: queue.Queue = queue.Queue()
         self._stop = False
@@ -101,13 +104,8 @@ class Server:
         for i in range(workers):
             w = dict(
                 stream=torch.cuda.Stream(device=self.device),
-                ws=torch.empty(ws, dtype=torch.uint8, device=self.device),
-                bases=torch.empty(max(self.max_bases, 1), dtype=torch.uint8, device=self.device),
-                offsets=torch.empty(self.max_reads + 1 + self.max_libs, dtype=torch.int64, device=self.device),
-                h_bases=torch.empty(max(self.max_bases, 1), dtype=torch.uint8, pin_memory=True),
-                h_offsets=torch.empty(self.max_reads + 1 + self.max_libs, dtype=torch.int64, pin_memory=True),
-                h_keys=None,
-                h_counts=None,
+                arena=torch.empty(self.share, dtype=torch.uint8, device=self.device),
+                h_bases=None, h_offsets=None, h_keys=None, h_counts=None,
                 inbox=queue.Queue(),
             )
             t = threading.Thread(target=self._work, args=(w,), daemon=True, name=f"tk-worker-{i}")
@@ -117,6 +115,17 @@ class Server:
             self._idle.put(w)
         self._dispatcher = threading.Thread(target=self._dispatch, daemon=True, name="tk-dispatch")
         self._dispatcher.start()
+
+    # -- footprints ------------------------------------------------------------
+    def footprint(self, jobs) -> int:
+        """Device bytes of one batch of these jobs: the library's workspace
+        for them, then their reads and offsets, in one arena."""
+        lb, lr = [0], [0]
+        for j in jobs:
+            lb.append(lb[-1] + int(j.bases.size))
+            lr.append(lr[-1] + int(j.offsets.size - 1))
+        ws = tk_batch_workspace_size(lb, lr, [int(j.k) for j in jobs], [int(j.c) for j in jobs], self.opts)
+        return _align(ws) + _align(lb[-1]) + 8 * (lr[-1] + 1)
 
     # -- client side ---------------------------------------------------------
     @staticmethod
@@ -141,12 +150,13 @@ class Server:
 
     def submit(self, job: Job) -> Future:
         self.check_job(job)
-        if job.bases.size > self.max_bases or job.offsets.size - 1 > self.max_reads:
-            raise ValueError("job larger than the server's batch budget")
+        fp = self.footprint([job])
+        if fp > self.share:
+            raise ValueError(f"job needs {fp} bytes of device memory; a worker holds {self.share}")
         fut: Future = Future()
         job.t_submit = job.t_submit or time.perf_counter()
         with self._cv:
-            self._pending.append((job, fut))
+            self._pending.append((job, fut, fp))
             self._cv.notify()
         return fut
 
@@ -160,22 +170,23 @@ class Server:
             w["thread"].join()
 
     # -- scheduling ------------------------------------------------------------
+    _SCAN = 256  # waiting jobs looked at per batch
+
     def _take_batch(self):
-        """Oldest waiting job plus later ones of the same k within budget."""
-        job0, _ = self._pending[0]
-        take, rest, bases, reads = [], [], 0, 0
-        for item in self._pending:
-            j = item[0]
-            fits = (j.k == job0.k and len(take) < self.max_libs and bases + j.bases.size <= self.max_bases
-                    and reads + j.offsets.size - 1 <= self.max_reads)
-            if fits:
+        """The oldest waiting job plus later ones while the batch's footprint
+        fits a worker's arena; jobs of every k share a batch."""
+        take, rest = [self._pending[0]], []
+        for i, item in enumerate(self._pending[1:], 1):
+            if len(take) >= self.max_libs or i >= self._SCAN or \
+                    sum(t[2] for t in take) + item[2] > 2 * self.share:
+                rest.append(item)
+                continue
+            if self.footprint([t[0] for t in take] + [item[0]]) <= self.share:
                 take.append(item)
-                bases += j.bases.size
-                reads += j.offsets.size - 1
             else:
                 rest.append(item)
         self._pending = rest
-        return take
+        return [(j, f) for j, f, _ in take]
 
     def _dispatch(self):
         while True:
@@ -192,7 +203,6 @@ class Server:
             w["inbox"].put(batch)
 
     def _work(self, w):
-        torch = self.torch
         while True:
             batch = w["inbox"].get()
             if batch is None:
@@ -223,14 +233,20 @@ class Server:
         for j in jobs:
             lb.append(lb[-1] + int(j.bases.size))
             lr.append(lr[-1] + int(j.offsets.size - 1))
+        ks, cs = [int(j.k) for j in jobs], [int(j.c) for j in jobs]
+        ws_bytes = _align(tk_batch_workspace_size(lb, lr, ks, cs, self.opts))
+        b_off = ws_bytes
+        o_off = b_off + _align(lb[-1])
+        assert o_off + 8 * (lr[-1] + 1) <= self.share, "admission let in a batch larger than the arena"
+        arena = w["arena"]
         stream = w["stream"]
         # every job into its slice of the pinned input buffers, its offsets
         # rebased to its first base (the previous batch's transfer from these
-        # buffers ended with that batch's stream synchronisation)
-        # (host copies through torch, which runs them on its thread pool
-        # without holding the interpreter lock, so both workers' copies and
-        # the dispatcher proceed together)
-        hb, ho = w["h_bases"], w["h_offsets"]
+        # buffers ended with that batch's stream synchronisation); torch runs
+        # the host copies on its thread pool without holding the interpreter
+        # lock, so both workers' copies and the dispatcher proceed together
+        hb = self._pinned(w, "h_bases", max(lb[-1], 1), torch.uint8)
+        ho = self._pinned(w, "h_offsets", lr[-1] + 1, torch.int64)
         ho[:1].zero_()
         for q, j in enumerate(jobs):
             if j.bases.size:
@@ -239,12 +255,12 @@ class Server:
                 off = torch.from_numpy(j.offsets[1:].astype(np.uint64, copy=False).view(np.int64))
                 torch.add(off, lb[q], out=ho[lr[q] + 1:lr[q + 1] + 1])
         with torch.cuda.stream(stream):
-            db = w["bases"][:lb[-1]]
-            do = w["offsets"][:lr[-1] + 1]
-            db.copy_(w["h_bases"][:lb[-1]], non_blocking=True)
-            do.copy_(w["h_offsets"][:lr[-1] + 1], non_blocking=True)
-            res = tk_count_batch_device(db, do, lb, lr, jobs[0].k, [j.c for j in jobs], self.opts,
-                                        workspace=w["ws"], stream=stream)
+            db = arena[b_off:b_off + lb[-1]]
+            do = arena[o_off:o_off + 8 * (lr[-1] + 1)].view(torch.int64)
+            db.copy_(hb[:lb[-1]], non_blocking=True)
+            do.copy_(ho[:lr[-1] + 1], non_blocking=True)
+            res = tk_count_batch_device(db, do, lb, lr, ks, cs, self.opts, workspace=arena[:ws_bytes],
+                                        stream=stream)
             hk = self._pinned(w, "h_keys", sum(int(r.keys.numel()) for r in res), torch.int64)
             hc = self._pinned(w, "h_counts", sum(int(r.counts.numel()) for r in res), torch.int32)
             back, ok, oc = [], 0, 0
@@ -263,4 +279,4 @@ class Server:
         t_done = time.perf_counter()
         for (keys, counts, r), (job, fut) in zip(host, batch):
             fut.set_result(JobResult(keys, counts, r.n_windows, r.n_collected, r.n_distinct, r.n_singletons,
-                                     job.t_submit, t_start, t_done))
+                                     job.t_submit, t_start, t_done, len(jobs)))

@@ -176,23 +176,58 @@ WORKLOADS = {
 }
 
 
+def _batched_draws(j: int, scale: float, base_seed: int):
+    """Generator, genome size and coverage of batched library j (the first
+    draws of its generator)."""
+    rng = rng_for(base_seed + j)
+    g = int(round(math.exp(rng.uniform(math.log(1e5), math.log(2e7))) * scale))
+    g = max(g, 200)
+    cov = rng.uniform(5.0, 60.0)
+    return rng, g, cov
+
+
+def batched_library_size(j: int, scale: float = 1.0, base_seed: int = 4000) -> tuple[int, int]:
+    """(n_bases, n_reads) of batched library j without generating it."""
+    _, g, cov = _batched_draws(j, scale, base_seed)
+    n = max(1, int(round(cov * g / 100)))
+    return 100 * n, n
+
+
+def batched_library(j: int, scale: float = 1.0, base_seed: int = 4000) -> Library:
+    """Library j of the batched workload: genome log-uniform in 0.1-20 Mbp,
+    coverage U[5, 60], 100 bp reads, 1 % substitutions, k=31, c=2, drawn
+    from seed ``base_seed + j``.  ``scale`` multiplies the genome size."""
+    rng, g, cov = _batched_draws(j, scale, base_seed)
+    genome = uniform_genome(rng, g)
+    n = max(1, int(round(cov * g / 100)))
+    b, o = sample_reads(rng, genome, n, 100, 0.01)
+    return Library(f"lib{j}-{g}bp-{cov:.1f}x", 31, 2, b, o)
+
+
 def batched_libraries(n_libs: int = 256, scale: float = 1.0, base_seed: int = 4000):
     """Libraries of uneven size: genome log-uniform in 0.1-20 Mbp, coverage U[5, 60].
 
     100 bp reads, 1 % substitutions, k=31, c=2; library ``j`` uses seed
     ``base_seed + j``.  ``scale`` multiplies every genome size.
     """
-    libs = []
+    return [batched_library(j, scale, base_seed) for j in range(n_libs)]
+
+
+def batched_waves(n_libs: int = 256, scale: float = 1.0, base_seed: int = 4000,
+                  wave_bases: int = 2_000_000_000) -> list[list[int]]:
+    """Consecutive batched libraries grouped into waves of at most
+    ``wave_bases`` bases each (a larger library forms a wave alone)."""
+    waves, cur, acc = [], [], 0
     for j in range(n_libs):
-        rng = rng_for(base_seed + j)
-        g = int(round(math.exp(rng.uniform(math.log(1e5), math.log(2e7))) * scale))
-        g = max(g, 200)
-        cov = rng.uniform(5.0, 60.0)
-        genome = uniform_genome(rng, g)
-        n = max(1, int(round(cov * g / 100)))
-        b, o = sample_reads(rng, genome, n, 100, 0.01)
-        libs.append(Library(f"lib{j}-{g}bp-{cov:.1f}x", 31, 2, b, o))
-    return libs
+        nb, _ = batched_library_size(j, scale, base_seed)
+        if cur and acc + nb > wave_bases:
+            waves.append(cur)
+            cur, acc = [], 0
+        cur.append(j)
+        acc += nb
+    if cur:
+        waves.append(cur)
+    return waves
 
 
 # ---------------------------------------------------------------------------

@@ -244,3 +244,20 @@ def test_binding_rejects_short_batch_tensors(lib, lb, lr):
     offsets = torch.tensor([0, 32, 64], dtype=torch.int64)
     with pytest.raises(ValueError, match="at least"):
         tk.tk_count_batch_device(bases, offsets, lb, lr, 31, 2)
+
+
+def test_batch_workspace_mixed_k(lib):
+    """Libraries of both key widths: two counting passes, each in its own
+    part of the workspace."""
+    lb, lr = [0, 5000, 9000, 20000], [0, 50, 90, 200]
+    one = tk.tk_batch_workspace_size(lb, lr, [21, 31, 31], 2)
+    two = tk.tk_batch_workspace_size(lb, lr, [55, 63, 33], 2)
+    mixed = tk.tk_batch_workspace_size(lb, lr, [21, 63, 31], 2)
+    assert mixed > 0 and mixed < one + two
+    assert mixed >= tk.tk_batch_workspace_size(lb, lr, [21, 31, 31], 2) * 0.5
+
+
+@pytest.mark.parametrize("k", [[31, 0, 31], [31, 64, 21], [-1, 21, 21]])
+def test_batch_bad_k_rejected(lib, k):
+    with pytest.raises(tk.TurtleError):
+        tk.tk_batch_workspace_size([0, 100, 200, 300], [0, 1, 2, 3], k, 2)

@@ -155,3 +155,53 @@ def test_batch_oversized_buckets(tk, oracle_lib, part_bits):
         check_library(oracle_lib, b, o, 31, 2, keys, counts, r, dict(part_bits=part_bits))
         n_fb += r.n_fallback
     assert n_fb >= 3
+
+
+def test_batch_mixed_k(tk, oracle_lib):
+    """One call over libraries of k = 21, 31, 55 and 63 interleaved (and a
+    few of every other width class): each library equals the oracle and its
+    own single-library call, key width included."""
+    import torch
+    ks = [21, 55, 31, 63, 21, 33, 5, 63, 31, 55]
+    libs, cs = [], []
+    for j, k in enumerate(ks):
+        if j == 4:
+            libs.append((np.zeros(0, np.uint8), np.zeros(1, np.uint64)))  # empty
+        elif j % 3 == 0:
+            lib = readsim.small_library(scale=0.03, seed=700 + j)
+            libs.append((lib.bases, lib.offsets))
+        else:
+            dup = readsim.random_reads(710 + j, 150, 0, 2 * k + 60, n_rate=0.01, lower_rate=0.02)
+            libs.append(readsim.from_strings(readsim.to_strings(*dup) * 2))
+        cs.append(1 + j % 3)
+    case(f"mixed-k batch k={ks} c={cs}")
+    out = run_batch(tk, libs, ks, cs)
+    assert len(out) == len(libs)
+    for (b, o), k, c, (keys, counts, r) in zip(libs, ks, cs, out):
+        assert r.k == k and r.key_words == (1 if k <= 31 else 2)
+        check_library(oracle_lib, b, o, k, c, keys, counts, r)
+        db = torch.from_numpy(b).cuda() if b.size else torch.zeros(1, dtype=torch.uint8).cuda()[:0]
+        do = torch.from_numpy(o.view(np.int64)).cuda()
+        s = tk.tk_count_device(db, do, k, c)
+        torch.cuda.synchronize()
+        assert np.array_equal(keys, s.keys.cpu().numpy().view(np.uint64).reshape(s.n, s.key_words))
+        assert np.array_equal(counts, s.counts.cpu().numpy().view(np.uint32))
+        assert (r.n_windows, r.n_collected, r.n_distinct, r.n_singletons, r.part_bits) == \
+            (s.n_windows, s.n_collected, s.n_distinct, s.n_singletons, s.part_bits)
+
+
+@pytest.mark.parametrize("ks", [(21, 31), (55, 63, 33)])
+def test_batch_mixed_k_one_width(tk, oracle_lib, ks):
+    """Different k with one key width: one counting pass, the validity bits
+    of every library packed with its own k."""
+    libs, kk = [], []
+    for j in range(9):
+        k = ks[j % len(ks)]
+        # libraries shorter than 32 bases and boundaries inside packed words
+        b, o = readsim.random_reads(760 + j, 1 + 37 * j, 0, 2 * k + 7, n_rate=0.01)
+        libs.append(readsim.from_strings(readsim.to_strings(b, o) * 2))
+        kk.append(k)
+    case(f"one-width mixed-k batch {kk}")
+    out = run_batch(tk, libs, kk, 2)
+    for (b, o), k, (keys, counts, r) in zip(libs, kk, out):
+        check_library(oracle_lib, b, o, k, 2, keys, counts, r)

@@ -54,16 +54,7 @@ def alone(tk, job):
             r)
 
 
-def test_served_results_identical_to_single_calls(tk, oracle_lib):
-    from paper_1305_1861_amd.serve import Server
-    jobs = jobs_mix()
-    case(f"served mix of {len(jobs)} jobs")
-    srv = Server(max_batch_bases=1 << 22, max_batch_reads=1 << 16, max_batch_libs=6, workers=2)
-    try:
-        futs = [srv.submit(j) for j in jobs]
-        results = [f.result(timeout=120) for f in futs]
-    finally:
-        srv.close()
+def check_alone(tk, jobs, results):
     for q, (job, res) in enumerate(zip(jobs, results)):
         keys, counts, r = alone(tk, job)
         assert np.array_equal(res.keys, keys), q
@@ -71,17 +62,79 @@ def test_served_results_identical_to_single_calls(tk, oracle_lib):
         assert (res.n_windows, res.n_collected, res.n_distinct, res.n_singletons) == \
             (r.n_windows, r.n_collected, r.n_distinct, r.n_singletons), q
         assert res.t_submit <= res.t_start <= res.t_done
+
+
+def test_served_results_identical_to_single_calls(tk, oracle_lib):
+    """Jobs of k = 21, 31 and 55 share batches (one worker that lingers, so
+    arrivals accumulate); each result equals the job counted alone."""
+    from paper_1305_1861_amd.serve import Server
+    jobs = jobs_mix()
+    case(f"served mix of {len(jobs)} jobs")
+    srv = Server(hbm_bytes=1 << 30, max_batch_libs=6, workers=1, linger_s=0.3)
+    try:
+        futs = [srv.submit(j) for j in jobs]
+        results = [f.result(timeout=120) for f in futs]
+    finally:
+        srv.close()
+    check_alone(tk, jobs, results)
+    batches = {}
+    for job, res in zip(jobs, results):
+        batches.setdefault((res.t_start, res.t_done), set()).add(job.k)
+    assert any(len(ks) > 1 for ks in batches.values()), batches
     job, res = jobs[1], results[1]
     ora = oracle_lib.kmer_count(job.bases, job.offsets, job.k, job.c)
     assert np.array_equal(res.keys[:, 0], ora.lo) and np.array_equal(res.counts.astype(np.uint64), ora.count)
 
 
-def test_server_refuses_oversized_job(tk):
-    from paper_1305_1861_amd.serve import Job, Server
-    srv = Server(max_batch_bases=1 << 12, max_batch_reads=64, max_batch_libs=2, workers=1)
+def test_served_two_workers_mixed(tk):
+    from paper_1305_1861_amd.serve import Server
+    jobs = jobs_mix()[::-1]
+    case("served mix, two workers")
+    srv = Server(hbm_bytes=1 << 30, max_batch_libs=4, workers=2)
     try:
-        b, o = readsim.random_reads(1, 100, 50, 60)
-        with pytest.raises(ValueError):
-            srv.submit(Job(b, o, 31))
+        results = [f.result(timeout=120) for f in [srv.submit(j) for j in jobs]]
     finally:
         srv.close()
+    check_alone(tk, jobs, results)
+
+
+def test_server_admits_by_footprint(tk):
+    """A worker's arena bounds every batch: a job larger than it is refused,
+    jobs that together exceed it are counted in several batches."""
+    from paper_1305_1861_amd.serve import Job, Server
+    share = 48 << 20
+    srv = Server(hbm_bytes=share, max_batch_libs=64, workers=1, linger_s=0.3)
+    try:
+        big = readsim.small_library(scale=0.3, seed=41)  # about 110 MB of workspace
+        with pytest.raises(ValueError, match="device memory"):
+            srv.submit(Job(big.bases, big.offsets, 31, 2))
+        libs = [readsim.small_library(scale=0.04, seed=50 + q) for q in range(8)]  # about 15 MB each
+        jobs = [Job(l.bases, l.offsets, (21, 55)[q % 2], 2) for q, l in enumerate(libs)]
+        assert srv.footprint(jobs) > share >= max(srv.footprint([j]) for j in jobs)
+        case("footprint admission")
+        results = [f.result(timeout=120) for f in [srv.submit(j) for j in jobs]]
+    finally:
+        srv.close()
+    check_alone(tk, jobs, results)
+    assert max(r.batch_jobs for r in results) < len(jobs)
+    assert len({(r.t_start, r.t_done) for r in results}) >= 2
+
+
+def test_malformed_job_refused_batch_mates_unchanged(tk):
+    from paper_1305_1861_amd.serve import Job, Server
+    jobs = jobs_mix()[:6]
+    srv = Server(hbm_bytes=1 << 30, max_batch_libs=8, workers=1, linger_s=0.3)
+    try:
+        futs = [srv.submit(j) for j in jobs[:3]]
+        bad = Job(jobs[0].bases, jobs[0].offsets.copy(), 31, 2)
+        bad.offsets[-1] += 5  # past its own bases: would cut windows of the next job
+        with pytest.raises(ValueError):
+            srv.submit(bad)
+        with pytest.raises(ValueError):
+            srv.submit(Job(jobs[1].bases, jobs[1].offsets, 31, 0))
+        futs += [srv.submit(j) for j in jobs[3:]]
+        case("malformed jobs refused")
+        results = [f.result(timeout=120) for f in futs]
+    finally:
+        srv.close()
+    check_alone(tk, jobs, results)
