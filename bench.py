@@ -26,7 +26,9 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_1305_1861_amd", "csrc")
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE; used
 # only while the kernel sources still hash to the recorded digest
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large-library.json")
+def traffic_file(workload: str) -> str:
+    """Counter record of a workload: profiles/traffic_<workload>-library.json."""
+    return os.path.join(ROOT, "profiles", f"traffic_{workload.replace('_', '-')}-library.json")
 STAGE_SOURCES = {
     "bucket": ["bucket.hip", "device.hpp", "internal.hpp"],
     "partition": ["partition.hip", "scan.hip", "device.hpp", "internal.hpp"],
@@ -48,7 +50,7 @@ SINGLE_KERNEL_STAGES = ("bucket", "gather", "screen", "collect", "pack")
 WORKLOAD_INFO = {
     "phased": dict(library="the large library, streamed from host memory in chunks into a resident SAC"),
     "served": dict(jobs="Poisson arrivals, mean 50/s; batched-style libraries, k in {21, 31, 55}"),
-    "batched": dict(libraries="log-uniform genomes 1e5..2e7 bp (times --batch-scale), coverage U[5, 60]"),
+    "batched": dict(libraries="log-uniform genomes 1e5..2e7 bp, coverage U[5, 60]"),
     "small": dict(genome_bp=1_000_000, coverage=10, read_len=100, sub_rate=0.01, n_rate=0.0, repeats=None),
     "large": dict(genome_bp=50_000_000, coverage=30, read_len=100, sub_rate=0.01, n_rate=0.0,
                   repeats="20% as 5 kbp copies, 2-10 per family, 2% divergence"),
@@ -191,46 +193,75 @@ def cpu_baseline(lib, target_s: float = 12.0) -> dict:
                       f"single-threaded on 1 of {os.cpu_count()} host cores ({cpu})"}
 
 
+def batched_digest_check(res_by_lib, gold, np):
+    """Per-range digests of selected batched libraries' records against the
+    oracle's (tests/golden/full_batched.json); returns (checked, mismatched)."""
+    import hashlib
+    checked, bad = 0, []
+    for js, g in gold["libraries"].items():
+        j = int(js)
+        if j not in res_by_lib:
+            continue
+        keys, counts = res_by_lib[j]
+        k, rb = g["k"], g["range_bits"]
+        top = keys[:, 0] >> np.uint64(2 * k - rb) if rb else np.zeros(keys.shape[0], np.uint64)
+        edges = np.searchsorted(top, np.arange((1 << rb) + 1, dtype=np.uint64))
+        ok = True
+        for r, want in enumerate(g["ranges"]):
+            a, b = int(edges[r]), int(edges[r + 1])
+            ok &= (b - a) == want["n_out"]
+            ok &= hashlib.sha256(np.ascontiguousarray(keys[a:b], dtype="<u8").tobytes()).hexdigest() == \
+                want["sha256_keys"]
+            ok &= hashlib.sha256(np.ascontiguousarray(counts[a:b], dtype="<u4").tobytes()).hexdigest() == \
+                want["sha256_counts"]
+        checked += 1
+        if not ok:
+            bad.append(j)
+    return checked, bad
+
+
+def gen_progress(done: int, total: int):
+    if done % 64 == 0 or done == total:
+        print(f"[bench] drawn {done}/{total} libraries", file=sys.stderr, flush=True)
+
+
 def bench_batched(args, tk, readsim, torch, np, dev) -> int:
-    """Many libraries of uneven size: one batch call per wave against one
-    single-library call per library, on the same resident data."""
+    """The batched workload: 256 libraries of uneven size counted in waves
+    (one tk_count_batch_device call per wave, every library with its own
+    buckets, filters and result) against one tk_count_device call per
+    library, on the same resident reads.  After timing, every library's
+    batch result is compared with its single call and a spread of them
+    (smallest, median and largest of every wave) with the oracle's digests."""
     t0 = time.perf_counter()
-    libs = readsim.batched_libraries(n_libs=args.batch_libs, scale=args.batch_scale)
-    sizes = np.array([l.n_bases for l in libs], np.uint64)
-    print(f"[bench] generated {len(libs)} libraries, {int(sizes.sum())} bases in {time.perf_counter() - t0:.1f} s",
-          file=sys.stderr, flush=True)
-    # waves: consecutive libraries up to wave_bases bases each
-    waves, cur, acc = [], [], 0
-    for j, l in enumerate(libs):
-        if cur and acc + l.n_bases > args.wave_bases:
-            waves.append(cur)
-            cur, acc = [], 0
-        cur.append(j)
-        acc += l.n_bases
-    if cur:
-        waves.append(cur)
-    k, c = libs[0].k, libs[0].c
+    n_libs, scale = args.batch_libs, args.batch_scale
+    bases, offsets, lib_bases, lib_reads = readsim.batched_workload(n_libs, scale, workers=args.gen_workers,
+                                                                    progress=gen_progress)
+    waves = readsim.batched_waves(n_libs, scale, wave_bases=int(args.wave_bases))
+    print(f"[bench] generated {n_libs} libraries, {bases.size} bases, {len(waves)} waves in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    k, c = 31, 2
     opts = tk.tk_default_options()
     opts.flags = tk.TK_FLAG_TIMING
+    db_all = torch.from_numpy(bases).to(dev)
     wave_data = []
     for w in waves:
-        bases = np.concatenate([libs[j].bases for j in w])
-        lb, lr, offs = [0], [0], [np.zeros(1, np.uint64)]
-        for j in w:
-            offs.append(libs[j].offsets[1:] + np.uint64(lb[-1]))
-            lb.append(lb[-1] + libs[j].n_bases)
-            lr.append(lr[-1] + libs[j].n_reads)
-        offsets = np.concatenate(offs)
-        db = torch.from_numpy(bases).to(dev)
-        do = torch.from_numpy(offsets.view(np.int64)).to(dev)
-        # each library on its own (for the single-library calls): views of the
-        # same bases and offsets re-based to the library's first base
+        b0, b1 = int(lib_bases[w[0]]), int(lib_bases[w[-1] + 1])
+        r0, r1 = int(lib_reads[w[0]]), int(lib_reads[w[-1] + 1])
+        lb = [int(lib_bases[j]) - b0 for j in w] + [b1 - b0]
+        lr = [int(lib_reads[j]) - r0 for j in w] + [r1 - r0]
+        do = torch.from_numpy((offsets[r0:r1 + 1] - np.uint64(b0)).view(np.int64)).to(dev)
+        db = db_all[b0:b1]
         single = [(db[lb[q]:lb[q + 1]], do[lr[q]:lr[q + 1] + 1] - lb[q]) for q in range(len(w))]
         wave_data.append(dict(db=db, do=do, lb=lb, lr=lr, libs=w, single=single))
+    del bases, offsets
     ws_bytes = max(tk.tk_batch_workspace_size(wd["lb"], wd["lr"], k, c, opts) for wd in wave_data)
-    ws_bytes = max(ws_bytes, max(tk.tk_workspace_size(l.n_bases, l.n_reads, k, c, opts) for l in libs))
+    ws_bytes = max(ws_bytes, max(tk.tk_workspace_size(int(lib_bases[j + 1] - lib_bases[j]),
+                                                      int(lib_reads[j + 1] - lib_reads[j]), k, c, opts)
+                                 for j in range(n_libs)))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+    print(f"[bench] resident: {db_all.numel() / 1e9:.1f} GB of reads, workspace {ws_bytes / 1e9:.1f} GB",
+          file=sys.stderr, flush=True)
 
     def batched():
         n_win = n_out = 0
@@ -263,52 +294,88 @@ def bench_batched(args, tk, readsim, torch, np, dev) -> int:
         print(f"[bench] {name}: {1e3 * results[name][0]:.2f} ms per pass", file=sys.stderr, flush=True)
     tb, n_win, n_out = results["batched"]
     ts = results["sequential"][0]
-    assert results["sequential"][1:] == (n_win, n_out)
+    # parity: every library's batch result against its single call, and the
+    # digested spread against the oracle
+    gold_path = os.path.join(ROOT, "tests", "golden", "full_batched.json")
+    gold = None
+    if scale == 1.0 and n_libs == 256 and os.path.exists(gold_path):
+        with open(gold_path) as f:
+            gold = json.load(f)
+    want = set(int(j) for j in gold["libraries"]) if gold else set()
+    same, got = 0, {}
+    for wd in wave_data:
+        res = tk.tk_count_batch_device(wd["db"], wd["do"], wd["lb"], wd["lr"], k, c, opts, workspace=ws,
+                                       stream=stream)
+        kept = [(r.keys.clone(), r.counts.clone(), r) for r in res]
+        for j, (b, o), (kk, cc, r) in zip(wd["libs"], wd["single"], kept):
+            s1 = tk.tk_count_device(b, o, k, c, opts, workspace=ws, stream=stream)
+            same += int(torch.equal(kk, s1.keys) and torch.equal(cc, s1.counts) and
+                        (r.n_windows, r.n_collected, r.n_distinct, r.n_singletons) ==
+                        (s1.n_windows, s1.n_collected, s1.n_distinct, s1.n_singletons))
+            if j in want:
+                got[j] = (kk.cpu().numpy().view(np.uint64), cc.cpu().numpy().view(np.uint32))
+        del kept
+    checked, bad = batched_digest_check(got, gold, np) if gold else (0, [])
+    plain = getattr(args, "plain_windows_per_s", None)
     out = {
         "metric": METRIC, "value": n_win / tb, "unit": "k-mer windows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * tb, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": f"batched-{len(libs)}-libraries-scale-{args.batch_scale:g}",
-                   "genome_bp": "log-uniform 1e5..2e7 times scale", "coverage": "U[5, 60]", "read_len": 100,
-                   "sub_rate": 0.01, "k": k, "c": c, "n_bases": int(sizes.sum()), "waves": len(waves)},
-        "result": {"n_windows": n_win, "n_frequent": n_out},
-        "sequential": {"ms_per_step": 1e3 * ts, "value": n_win / ts, "calls": len(libs)},
+        "config": {"workload": f"batched-{n_libs}-libraries" + ("" if scale == 1.0 else f"-scale-{scale:g}"),
+                   "genome_bp": "log-uniform 1e5..2e7" + ("" if scale == 1.0 else f" times {scale:g}"),
+                   "coverage": "U[5, 60]", "read_len": 100, "sub_rate": 0.01, "k": k, "c": c,
+                   "n_bases": int(lib_bases[-1]), "waves": len(waves), "wave_bases": int(args.wave_bases)},
+        "result": {"n_windows": n_win, "n_frequent": n_out,
+                   "libraries_equal_to_single_call": f"{same}/{n_libs}",
+                   "libraries_equal_to_oracle_digests": f"{checked - len(bad)}/{checked}" if gold else None,
+                   "digest_mismatches": bad},
+        "frequent_kmers_per_s": n_out / tb,
+        "sequential": {"ms_per_step": 1e3 * ts, "value": n_win / ts, "calls": n_libs},
         "speedup_vs_sequential": ts / tb,
         "host": platform.node(),
     }
     print(json.dumps(out), flush=True)
-    return 0
+    return 0 if same == n_libs and not bad else 1
 
 
 def bench_served(args, tk, readsim, torch, np, dev) -> int:
-    """Jobs arriving as a Poisson process, served by continuous batching;
-    latency per job from arrival to result on the host."""
+    """Jobs arriving as a Poisson process (mean args.rate per second), each a
+    library drawn as in the batched workload (job j: seed 5000000 + j mod
+    the pool) with k drawn from {21, 31, 55}, served by continuous batching
+    with admission by HBM footprint; latency per job from arrival to result
+    on the host, throughput against the plain path on the same device."""
     from paper_1305_1861_amd.serve import Job, Server
-    pool_n = args.pool
+    pool_n = min(args.pool, args.jobs)
     t0 = time.perf_counter()
-    pool = readsim.batched_libraries(n_libs=pool_n, scale=args.batch_scale, base_seed=5_000_000)
-    print(f"[bench] generated a pool of {pool_n} libraries in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
-          flush=True)
+    bases, offsets, lib_bases, lib_reads = readsim.batched_workload(pool_n, args.batch_scale, base_seed=5_000_000,
+                                                                    workers=args.gen_workers, progress=gen_progress)
+    pool = []
+    for q in range(pool_n):
+        b0, b1, r0, r1 = int(lib_bases[q]), int(lib_bases[q + 1]), int(lib_reads[q]), int(lib_reads[q + 1])
+        pool.append((bases[b0:b1], offsets[r0:r1 + 1] - np.uint64(b0)))
+    print(f"[bench] generated {pool_n} job libraries ({bases.size} bases) in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
     rng = np.random.Generator(np.random.PCG64(5))
     gaps = rng.exponential(1.0 / args.rate, args.jobs)
     ks = rng.choice([21, 31, 55], args.jobs)
     arrivals = np.cumsum(gaps)
-    biggest = max(l.n_bases for l in pool)
-    budget = max(1 << 28, 1 << (biggest - 1).bit_length())
-    srv = Server(max_batch_bases=budget, max_batch_reads=budget // 64, max_batch_libs=64, workers=2,
-                 device="cuda:0")
+    free, _ = torch.cuda.mem_get_info(dev)
+    hbm = int(args.serve_hbm_frac * free)
+    srv = Server(hbm_bytes=hbm, max_batch_libs=64, workers=2, device="cuda:0")
     try:
         # warm-up: one job of each k
         for k in (21, 31, 55):
-            srv.submit(Job(pool[0].bases, pool[0].offsets, int(k), 2)).result()
+            srv.submit(Job(pool[0][0], pool[0][1], int(k), 2)).result()
         futs = []
         start = time.perf_counter()
         for j in range(args.jobs):
             wait = start + arrivals[j] - time.perf_counter()
             if wait > 0:
                 time.sleep(wait)
-            lib = pool[j % pool_n]
-            futs.append(srv.submit(Job(lib.bases, lib.offsets, int(ks[j]), 2, t_submit=time.perf_counter())))
+            b, o = pool[j % pool_n]
+            futs.append(srv.submit(Job(b, o, int(ks[j]), 2, t_submit=time.perf_counter())))
+            if (j + 1) % 200 == 0:
+                print(f"[bench] {j + 1} jobs submitted", file=sys.stderr, flush=True)
         res = [f.result() for f in futs]
         end = max(r.t_done for r in res)
     finally:
@@ -317,17 +384,35 @@ def bench_served(args, tk, readsim, torch, np, dev) -> int:
     n_win = sum(r.n_windows for r in res)
     span = end - start
     batches = len({(r.t_start, r.t_done) for r in res})
+    # the plain path on the same device: the largest pool library alone
+    q = int(np.argmax(lib_bases[1:] - lib_bases[:-1]))
+    b, o = pool[q]
+    db = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+    do = torch.from_numpy(o.view(np.int64)).to(dev)
+    ws = torch.empty(tk.tk_workspace_size(int(b.size), int(o.size - 1), 31, 2), dtype=torch.uint8, device=dev)
+    tk.tk_count_device(db, do, 31, 2, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        r = tk.tk_count_device(db, do, 31, 2, workspace=ws)
+    torch.cuda.synchronize()
+    plain = r.n_windows / ((time.perf_counter() - t) / 3)
+    distinct = "" if pool_n >= args.jobs else f"-pool-{pool_n}"
     out = {
         "metric": METRIC, "value": n_win / span, "unit": "k-mer windows/s", "n_gpus": 1, "steps": args.jobs,
         "warmup": 3, "ms_per_step": 1e3 * span / args.jobs, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64/u128", "data": "synthetic",
-        "config": {"workload": f"served-{args.jobs}-jobs-{args.rate:g}-per-s-scale-{args.batch_scale:g}",
+        "config": {"workload": f"served-{args.jobs}-jobs-{args.rate:g}-per-s{distinct}"
+                               + ("" if args.batch_scale == 1.0 else f"-scale-{args.batch_scale:g}"),
                    "jobs": args.jobs, "rate_per_s": args.rate, "k": "U{21, 31, 55}", "c": 2,
-                   "library_pool": pool_n, "workers": 2, "batch_budget_bases": budget},
+                   "distinct_libraries": pool_n, "job_library": "batched recipe, seed 5000000 + (j mod pool)",
+                   "workers": 2, "hbm_bytes": hbm, "admission": "HBM footprint per batch"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
         "result": {"n_windows": n_win, "n_frequent": sum(int(r.counts.size) for r in res), "batches": batches,
+                   "mean_jobs_per_batch": args.jobs / batches,
                    "offered_windows_per_s": n_win / arrivals[-1]},
+        "plain_path_windows_per_s": plain,
         "host": platform.node(),
     }
     print(json.dumps(out), flush=True)
@@ -491,16 +576,21 @@ def main() -> int:
                     help="one Bloom filter in HBM for the whole library (device-scope atomics)")
     ap.add_argument("--part-bits", type=int, default=-1,
                     help="bucket bits D of the per-bucket plan (-1: the library's size rule)")
-    ap.add_argument("--traffic", default=TRAFFIC_FILE,
+    ap.add_argument("--traffic", default=None,
                     help="JSON record of measured HBM bytes per launch of the dominant kernel")
     ap.add_argument("--batch-libs", type=int, default=256, help="batched workload: number of libraries")
-    ap.add_argument("--batch-scale", type=float, default=1.0 / 16,
-                    help="batched workload: factor on every library's genome size")
-    ap.add_argument("--wave-bases", type=float, default=3.0e9,
+    ap.add_argument("--batch-scale", type=float, default=1.0,
+                    help="batched workload: factor on every library's genome size (1: the stated config)")
+    ap.add_argument("--wave-bases", type=float, default=2.0e9,
                     help="batched workload: bases per batch call (waves sized to HBM)")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="batched workload: processes drawing the libraries")
     ap.add_argument("--jobs", type=int, default=1000, help="served workload: number of jobs")
     ap.add_argument("--rate", type=float, default=50.0, help="served workload: mean arrivals per second")
-    ap.add_argument("--pool", type=int, default=48, help="served workload: distinct libraries the jobs cycle over")
+    ap.add_argument("--pool", type=int, default=1000,
+                    help="served workload: distinct job libraries (jobs cycle over them when fewer than --jobs)")
+    ap.add_argument("--serve-hbm-frac", type=float, default=0.6,
+                    help="served workload: fraction of free device memory the server holds")
     ap.add_argument("--chunk-bases", type=float, default=1.0e8, help="phased workload: bases per chunk")
     ap.add_argument("--sac-capacity", type=float, default=6.0e7,
                     help="phased workload: records of the resident sorted-and-compacted array")
@@ -521,10 +611,12 @@ def main() -> int:
                     help="after the run, copy a buffer of this many MiB three times with a plain "
                          "device copy kernel (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.traffic is None:
+        args.traffic = traffic_file(args.workload)
 
     if args.record_traffic:
         rec = record_traffic(args.record_traffic[0], args.record_traffic[1], args.calibrate_copy_mib << 20,
-                             WORKLOAD_NAMES[args.workload], f"profiles/kernels_{args.workload}-library_per-bucket.md",
+                             WORKLOAD_NAMES[args.workload], f"profiles/kernels_{args.workload.replace('_', '-')}-library_per-bucket.md",
                              args.traffic)
         print(json.dumps({s: v["bytes"] for s, v in rec["stages"].items()}))
         return 0

@@ -297,3 +297,55 @@ def to_strings(bases: np.ndarray, offsets: np.ndarray) -> list[str]:
     raw = bases.tobytes()
     return [raw[int(offsets[i]):int(offsets[i + 1])].decode("latin-1")
             for i in range(offsets.size - 1)]
+
+
+_SHARED = None  # (bases map, offsets map) of the workload being drawn
+
+
+def _fill_batched(args):
+    """Draw batched library j into its slice of the shared bases and offsets."""
+    j, scale, base_seed, b0, r0, nb, nr = args
+    lib = batched_library(j, scale, base_seed)
+    bases = np.frombuffer(_SHARED[0], dtype=np.uint8, count=nb)
+    offs = np.frombuffer(_SHARED[1], dtype=np.uint64, count=nr + 1)
+    bases[b0:b0 + lib.n_bases] = lib.bases
+    offs[r0 + 1:r0 + lib.n_reads + 1] = lib.offsets[1:] + np.uint64(b0)
+    return j
+
+
+def batched_workload(n_libs: int = 256, scale: float = 1.0, base_seed: int = 4000, workers: int = 8,
+                     progress=None):
+    """All batched libraries laid end to end in one bases/offsets pair:
+    returns (bases, offsets, lib_bases, lib_reads), library j owning bases
+    [lib_bases[j], lib_bases[j+1]) and reads [lib_reads[j], lib_reads[j+1]).
+    The libraries are the ones ``batched_library`` draws (identical bytes);
+    ``workers`` forked processes draw them in parallel into shared memory;
+    ``progress(done, total)`` is called as libraries are finished."""
+    import mmap
+    import multiprocessing as mp
+    global _SHARED
+    sizes = [batched_library_size(j, scale, base_seed) for j in range(n_libs)]
+    lib_bases = np.zeros(n_libs + 1, np.uint64)
+    lib_reads = np.zeros(n_libs + 1, np.uint64)
+    lib_bases[1:] = np.cumsum([s[0] for s in sizes])
+    lib_reads[1:] = np.cumsum([s[1] for s in sizes])
+    nb, nr = int(lib_bases[-1]), int(lib_reads[-1])
+    _SHARED = (mmap.mmap(-1, max(nb, 1)), mmap.mmap(-1, 8 * (nr + 1)))
+    tasks = [(j, scale, base_seed, int(lib_bases[j]), int(lib_reads[j]), nb, nr)
+             for j in sorted(range(n_libs), key=lambda j: -sizes[j][0])]
+    try:
+        if workers > 1:
+            with mp.get_context("fork").Pool(workers) as pool:
+                for done, _ in enumerate(pool.imap_unordered(_fill_batched, tasks), 1):
+                    if progress:
+                        progress(done, n_libs)
+        else:
+            for done, t in enumerate(tasks, 1):
+                _fill_batched(t)
+                if progress:
+                    progress(done, n_libs)
+        bases = np.frombuffer(_SHARED[0], dtype=np.uint8, count=nb)
+        offsets = np.frombuffer(_SHARED[1], dtype=np.uint64, count=nr + 1)
+    finally:
+        _SHARED = None
+    return bases, offsets, lib_bases, lib_reads
