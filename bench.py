@@ -604,7 +604,8 @@ def main() -> int:
                     help="write the per-stage HBM byte record (--traffic) from two rocprofv3 --pmc counter "
                          "files of one step of --workload run with --calibrate-copy-mib, then exit")
     ap.add_argument("--autotune", action="store_true",
-                    help="time bucket bits and filter bits per window around the size rule; print the fastest")
+                    help="time bucket bits, filter bits per window, pattern bits and the bucket kernel's tile "
+                         "shape; print the fastest (stored in $TK_TUNE_CACHE when set)")
     ap.add_argument("--no-end-to-end", action="store_true",
                     help="skip the end-to-end run from host buffers (reported beside the timed value)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -653,10 +654,12 @@ def main() -> int:
         bases = torch.from_numpy(lib.bases).to(dev)
         offsets = torch.from_numpy(lib.offsets.view(np.int64)).to(dev)
         t = autotune(bases, offsets, lib.k, lib.c, repeats=max(1, args.steps))
-        print(json.dumps({"workload": lib.name, "best": {"part_bits": t.part_bits, "bloom_beta": t.bloom_beta,
-                                                          "ms": t.ms},
-                          "timings": [{"part_bits": d, "bloom_beta": be, "ms": ms, "n_fallback": nf}
-                                      for d, be, ms, nf in t.timings], "host": platform.node()}), flush=True)
+        print(json.dumps({"workload": lib.name, "cached": t.cached,
+                          "best": {"part_bits": t.part_bits, "bloom_beta": t.bloom_beta, "bloom_bits": t.bloom_bits,
+                                   "bucket_tile": t.bucket_tile, "ms": t.ms},
+                          "timings": [{"part_bits": d, "bloom_beta": be, "bloom_bits": bi, "bucket_tile": ti,
+                                       "ms": ms, "n_fallback": nf} for d, be, bi, ti, ms, nf in t.timings],
+                          "host": platform.node()}), flush=True)
         return 0
 
     t0 = time.perf_counter()

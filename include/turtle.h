@@ -144,7 +144,11 @@ typedef struct {
                                    -1 (default) = size rule                 */
     uint32_t shard_count;       /* key-range shards, 0 or 1 = none; <= 1024  */
     uint32_t shard_index;       /* the shard this call counts, < shard_count */
-    uint32_t reserved;          /* 0 */
+    uint32_t bucket_tile;       /* partitioned path: tile shape of the
+                                   bucket kernel, 0 (default: 7168 one-word
+                                   or 3584 two-word windows per group) or 1
+                                   (6144 or 3072); results never depend on
+                                   it                                      */
 } tk_options;
 
 /*

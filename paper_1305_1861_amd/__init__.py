@@ -38,7 +38,7 @@ class tk_options(ctypes.Structure):
     _fields_ = [("bloom_beta", _u32), ("bloom_table_bits", _u32), ("bloom_bits", _u32),
                 ("flags", _u32), ("bloom_blocks", _u64), ("bloom_seed", _u64),
                 ("part_bits", ctypes.c_int32), ("shard_count", _u32), ("shard_index", _u32),
-                ("reserved", _u32)]
+                ("bucket_tile", _u32)]
 
 
 class tk_result(ctypes.Structure):
@@ -387,11 +387,23 @@ def _batch_arrays(lib_bases, lib_reads, k, c):
     return n_libs, lb, lr, kk, cc
 
 
+def _batch_options(opts, lb, kk):
+    """Explicit options, else the autotuner's cached choice for the batch's
+    largest library (batch-wide options only; every library keeps the size
+    rule's D) when the cache file ``$TK_TUNE_CACHE`` is set, else None."""
+    if opts is not None or not os.environ.get("TK_TUNE_CACHE"):
+        return _opts(opts)
+    from .tune import cached_options
+    sizes = np.diff(lb.astype(np.int64))
+    j = int(np.argmax(sizes))
+    return cached_options(int(kk[j]), int(sizes[j]), with_part_bits=False)
+
+
 def tk_batch_workspace_size(lib_bases, lib_reads, k, c, opts=None) -> int:
     """Workspace bytes of tk_count_batch_device for these library boundaries
     (``k`` and ``c``: one value or one per library)."""
     n_libs, lb, lr, kk, cc = _batch_arrays(lib_bases, lib_reads, k, c)
-    o = _opts(opts)
+    o = _batch_options(opts, lb, kk)
     out = ctypes.c_size_t(0)
     _check(load_library().tk_batch_workspace_size(n_libs, lb.ctypes.data, lr.ctypes.data, kk.ctypes.data,
                                                   cc.ctypes.data, _optp(o), ctypes.byref(out)),
@@ -404,12 +416,14 @@ def tk_count_batch_device(bases, offsets, lib_bases, lib_reads, k, c, opts=None,
     """Count a batch of libraries held in device memory (one bases/offsets
     pair; library j owns reads lib_reads[j]..lib_reads[j+1] and bases
     lib_bases[j]..lib_bases[j+1]).  ``k`` and ``c``: one value or one per
-    library.  Returns one Counts per library, viewing the workspace."""
+    library.  ``opts=None``: the autotuner's cached choice when
+    ``$TK_TUNE_CACHE`` names a cache file (see ``tune``), else the defaults.
+    Returns one Counts per library, viewing the workspace."""
     torch = _torch()
     lib = load_library()
     n_libs, lb, lr, kk, cc = _batch_arrays(lib_bases, lib_reads, k, c)
     _check_device_reads(bases, offsets, int(lb[-1]), int(lr[-1]) + 1)
-    o = _opts(opts)
+    o = _batch_options(opts, lb, kk)
     need = tk_batch_workspace_size(lb, lr, kk, cc, o)
     if workspace is None:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=bases.device)

@@ -50,6 +50,7 @@ struct Opts {
     uint64_t blocks, seed;
     int part_bits;
     uint32_t shard_count, shard_index;
+    int tile;
 };
 
 tk_status resolve(const tk_options *o, Opts *r) {
@@ -62,6 +63,7 @@ tk_status resolve(const tk_options *o, Opts *r) {
     r->part_bits = -1;
     r->shard_count = 1;
     r->shard_index = 0;
+    r->tile = 0;
     if (o) {
         if (o->bloom_beta)
             r->beta = o->bloom_beta;
@@ -75,6 +77,9 @@ tk_status resolve(const tk_options *o, Opts *r) {
         r->part_bits = o->part_bits;
         r->shard_count = o->shard_count ? o->shard_count : 1;
         r->shard_index = o->shard_index;
+        if (o->bucket_tile > 1)
+            return fail(TK_EINVAL, "bucket_tile %u out of range [0, 1]", o->bucket_tile);
+        r->tile = (int)o->bucket_tile;
     }
     const bool global = r->flags & (TK_FLAG_GLOBAL_FILTER | TK_FLAG_CTURTLE | TK_FLAG_SINGLE_PASS);
     if ((r->flags & TK_FLAG_CTURTLE) && (r->flags & (TK_FLAG_SINGLE_PASS | TK_FLAG_GLOBAL_FILTER)))
@@ -305,7 +310,7 @@ tk_status make_plan(const LibSpec *ls, uint64_t n_libs, uint64_t n_bases, uint64
         p->part.cap = p->cap;
         p->part.shard_count = p->opts.shard_count;
         p->part.shard_index = p->opts.shard_index;
-        p->fb_cap = p->cap / ((uint64_t)bucket_capacity(p->key_words) + 1) + 1;
+        p->fb_cap = p->cap / ((uint64_t)bucket_capacity(p->key_words, p->opts.tile) + 1) + 1;
         p->fb_nb_max = p->screen ? ceil_div((uint64_t)p->opts.beta * std::max<uint64_t>(p->cap, 1), 256) + p->fb_cap : 0;
         p->part_words = partition_scratch_words(p->part, p->key_words);
         p->part.n_buckets = (uint32_t)n_bk;
@@ -834,6 +839,7 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
     ba.grp_last = reinterpret_cast<uint32_t *>(ws + p.off_grp_last);
     ba.grp_count = reinterpret_cast<uint32_t *>(ws + p.off_grp_count);
     ba.chunk_next = &misc->chunk_next;
+    ba.tile = p.opts.tile;
     TK_HIP(launch_bucket(ba, kw, grid, s));
     if ((st = tm.end(TK_STAGE_BUCKET, s)) != TK_OK)
         return st;

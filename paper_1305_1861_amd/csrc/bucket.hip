@@ -37,15 +37,18 @@ constexpr int BK_BINS = 1 << BK_SORT_BITS;  // == BK_THREADS: one bin per thread
 constexpr int BK_TABLE_BITS = 10;         // log2 of the largest pattern table (the default)
 constexpr int BK_TABLE = 1 << BK_TABLE_BITS;  // pattern table entries held in LDS (max)
 
-template <typename K>
+// Keys per thread of a group (tile shape; options.bucket_tile picks one):
+// tile 0 holds 7168 one-word or 3584 two-word windows per group in
+// registers, tile 1 holds 6144 or 3072 (fewer registers, smaller groups).
+template <typename K, int TILE>
 struct BkItems;
-template <>
-struct BkItems<uint64_t> {
-    static constexpr int value = 14;  // 7168 windows per group in registers
+template <int TILE>
+struct BkItems<uint64_t, TILE> {
+    static constexpr int value = TILE ? 12 : 14;
 };
-template <>
-struct BkItems<Key2> {
-    static constexpr int value = 7;  // 3584 windows per group in registers
+template <int TILE>
+struct BkItems<Key2, TILE> {
+    static constexpr int value = TILE ? 6 : 7;
 };
 constexpr int BK_RMAX = 1024;  // buckets per group
 constexpr int BK_MSD_BITS = 12;  // first (MSD) sort pass: 4096 bins, 16-bit counters in the LSD counter array
@@ -148,11 +151,11 @@ __device__ __forceinline__ uint32_t wave_count(uint64_t ball) { return (uint32_t
 // TBITS: log2 of the pattern table entries when fixed at compile time (the
 // default table: the pattern fields of the hash become constant shifts), or
 // 0 to take it from the arguments.
-template <typename K, int TBITS>
+template <typename K, int TBITS, int TILE>
 // Two workgroups per CU (LDS < 80 KB each) hide more latency than the
 // registers saved by running one.
 __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void bucket_kernel(BucketArgs a) {
-    constexpr int ITEMS = BkItems<K>::value;
+    constexpr int ITEMS = BkItems<K, TILE>::value;
     constexpr int CAP = BK_THREADS * ITEMS;
     // filter blocks that fit in the exchange buffer
     constexpr uint32_t FMAX = (uint32_t)((CAP + 2) * sizeof(K) / 64);
@@ -1058,9 +1061,9 @@ __global__ __launch_bounds__(256) void lib_stats_kernel(const LibDesc *__restric
 // (FMAX blocks) and its bucket ids span at most BK_RMAX.  A bucket too large
 // on its own goes to the fallback list instead (its records are filed under
 // it by the fallback kernels).  Groups never cross a chunk boundary.
-template <typename K>
+template <typename K, int TILE>
 __global__ __launch_bounds__(256) void plan_groups(BucketArgs a) {
-    constexpr uint32_t CAP = BK_THREADS * BkItems<K>::value;
+    constexpr uint32_t CAP = BK_THREADS * BkItems<K, TILE>::value;
     constexpr uint32_t FMAX = (uint32_t)((CAP + 2) * sizeof(K) / 64);
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.n_chunks)
@@ -1117,34 +1120,32 @@ __global__ __launch_bounds__(256) void plan_groups(BucketArgs a) {
 
 int bucket_grid() { return device_cu_count() * 2; }
 
-int bucket_capacity(int key_words) {
-    return BK_THREADS * (key_words == 2 ? BkItems<Key2>::value : BkItems<uint64_t>::value);
+int bucket_capacity(int key_words, int tile) {
+    if (key_words == 2)
+        return BK_THREADS * (tile ? BkItems<Key2, 1>::value : BkItems<Key2, 0>::value);
+    return BK_THREADS * (tile ? BkItems<uint64_t, 1>::value : BkItems<uint64_t, 0>::value);
 }
 
-hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream) {
+template <typename K, int TILE>
+hipError_t launch_bucket_tile(const BucketArgs &a, int grid, hipStream_t stream) {
     // the groups of every chunk (grp_* and *a.chunk_next, zero on entry,
     // belong to the caller's workspace)
     const unsigned cg = (unsigned)((a.n_chunks + 255) / 256);
-    if (key_words == 2)
-        plan_groups<Key2><<<dim3(cg), dim3(256), 0, stream>>>(a);
-    else
-        plan_groups<uint64_t><<<dim3(cg), dim3(256), 0, stream>>>(a);
+    plan_groups<K, TILE><<<dim3(cg), dim3(256), 0, stream>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    const bool fixed = a.table_bits == BK_TABLE_BITS;
-    if (key_words == 2) {
-        if (fixed)
-            bucket_kernel<Key2, BK_TABLE_BITS><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
-        else
-            bucket_kernel<Key2, 0><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
-    } else {
-        if (fixed)
-            bucket_kernel<uint64_t, BK_TABLE_BITS><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
-        else
-            bucket_kernel<uint64_t, 0><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
-    }
+    if (a.table_bits == BK_TABLE_BITS)
+        bucket_kernel<K, BK_TABLE_BITS, TILE><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
+    else
+        bucket_kernel<K, 0, TILE><<<dim3(grid), dim3(BK_THREADS), 0, stream>>>(a);
     return hipGetLastError();
+}
+
+hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream) {
+    if (key_words == 2)
+        return a.tile ? launch_bucket_tile<Key2, 1>(a, grid, stream) : launch_bucket_tile<Key2, 0>(a, grid, stream);
+    return a.tile ? launch_bucket_tile<uint64_t, 1>(a, grid, stream) : launch_bucket_tile<uint64_t, 0>(a, grid, stream);
 }
 
 hipError_t launch_fb_screen(const void *keys, const FbEntry *ent, uint32_t n_ent, uint64_t n, int key_words,

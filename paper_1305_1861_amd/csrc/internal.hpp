@@ -127,10 +127,11 @@ struct BucketArgs {
     uint32_t n_chunks, chunk_buckets;
     uint32_t *grp_first, *grp_last, *grp_count;
     uint32_t *chunk_next;           // chunk counter, zero before the launch
+    int tile;                       // tile shape (keys per thread), 0 or 1
 };
 int bucket_grid();
 constexpr uint32_t BK_CHUNK_MAX = 32;  // bucket ids per chunk of the bucket kernel's schedule
-int bucket_capacity(int key_words);
+int bucket_capacity(int key_words, int tile);
 hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream);
 // Oversized buckets (more keys than a workgroup holds) of one library, in
 // key order.

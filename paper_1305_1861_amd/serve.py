@@ -22,8 +22,11 @@ slice, then one transfer per batch, offsets rebased on the host), and
 results come back through pinned buffers into ordinary host arrays: copies
 from pageable memory ran at about 4 GB/s.
 
-Results are host arrays, identical to what a single ``tk_count_device`` call
-on the job alone returns.
+Options: the ``opts`` given to the server, else, per batch, the
+autotuner's cached choice for the batch's largest job when ``$TK_TUNE_CACHE``
+names a cache file (``tune.py``), else the defaults.  Results are host
+arrays, identical to what a single ``tk_count_device`` call on the job alone
+(with the same options) returns.
 """
 from __future__ import annotations
 
@@ -35,7 +38,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import _torch, load_library, tk_batch_workspace_size, tk_count_batch_device, tk_default_options
+from . import _torch, load_library, tk_batch_workspace_size, tk_count_batch_device
 
 _ALIGN = 256
 
@@ -94,7 +97,9 @@ class Server:
         if self.share < (1 << 20):
             raise ValueError("the server needs at least 1 MiB of device memory per worker")
         self.max_libs = int(max_batch_libs)
-        self.opts = opts if opts is not None else tk_default_options()
+        # None: per batch, the autotuner's cached choice ($TK_TUNE_CACHE)
+        # for its largest job, else the defaults (tk_count_batch_device)
+        self.opts = opts
         self.linger_s = linger_s
         self._pending: list[tuple[Job, Future, int]] = []  # job, future, its own footprint
         self._cv = threading.Condition()
