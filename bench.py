@@ -39,7 +39,7 @@ STAGE_SOURCES = {
 # records; the shared scan kernels are left out)
 STAGE_KERNELS = {
     "pack": ["mark_read_starts", "pack_kernel"],
-    "partition": ["pt_hist", "pt_scatter", "pt_segments", "pt_bucket_starts"],
+    "partition": ["pt_hist", "pt_scatter", "pt_segments", "pt_bucket_starts", "pt_tiles", "pt_transpose"],
     "bucket": ["plan_groups", "bucket_kernel"],
     "gather": ["gather_kernel"],
 }
@@ -71,7 +71,9 @@ def algorithmic_bytes(n_bases: int, n_windows: int, n_collected: int, n_out: int
     Partitioned path (filters, sort and compaction of a bucket live in LDS):
       pack      : as above
       partition : 0.375 B/base read + key bytes per window written, plus one
-                  read and one write of every key for the second pass (D > 10)
+                  read and one write of every key for the second pass (D > 10;
+                  its prefix tables, 2 B per digit and tile of 16384 keys,
+                  are left out)
       bucket    : key bytes per window read + (key bytes + 4) per record written
       gather    : (key bytes + 4) per record read and written
     """

@@ -182,7 +182,8 @@ struct Plan {
     size_t off_ctr, off_table, off_packed, off_valid, off_starts, off_filter;
     size_t off_keys_a, off_keys_b, off_counts, off_sort, off_compact;
     size_t off_gapc, off_f, off_part, off_rec_start, off_rec_nout, off_rec_off, off_rec_scan;
-    size_t off_fb_list, off_fb_ent, off_fbc, off_misc, off_bstart, off_grp_first, off_grp_last, off_grp_count, total;
+    size_t off_fb_list, off_fb_ent, off_fbc, off_misc, off_bstart, off_grp_first, off_grp_last, off_grp_count;
+    size_t off_grp_piece, total;
     size_t off_libs, off_lib_keys, off_lib_stats, off_lib_ctr, off_lib_first;
     size_t sort_bytes, compact_bytes;
 };
@@ -312,8 +313,8 @@ tk_status make_plan(const LibSpec *ls, uint64_t n_libs, uint64_t n_bases, uint64
         p->part.shard_index = p->opts.shard_index;
         p->fb_cap = p->cap / ((uint64_t)bucket_capacity(p->key_words, p->opts.tile) + 1) + 1;
         p->fb_nb_max = p->screen ? ceil_div((uint64_t)p->opts.beta * std::max<uint64_t>(p->cap, 1), 256) + p->fb_cap : 0;
-        p->part_words = partition_scratch_words(p->part, p->key_words);
         p->part.n_buckets = (uint32_t)n_bk;
+        p->part_words = partition_scratch_words(p->part, p->key_words);
     }
     p->sort_bytes = radix_scratch_bytes(p->cap, p->key_words);
     p->compact_bytes = compact_scratch_bytes(p->cap);
@@ -355,6 +356,7 @@ tk_status make_plan(const LibSpec *ls, uint64_t n_libs, uint64_t n_bases, uint64
         p->off_grp_first = take((p->n_buckets + BK_CHUNK_MAX) * sizeof(uint32_t));
         p->off_grp_last = take((p->n_buckets + BK_CHUNK_MAX) * sizeof(uint32_t));
         p->off_grp_count = take((p->n_buckets + 1) * sizeof(uint32_t));
+        p->off_grp_piece = take((p->n_buckets + BK_CHUNK_MAX) * sizeof(uint4));
         p->off_libs = take(n_libs * sizeof(LibDesc));
         p->off_lib_keys = take((n_libs + 1) * sizeof(uint32_t));
         p->off_lib_stats = take(n_libs * 4 * sizeof(unsigned long long));
@@ -806,7 +808,8 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
     pp.valid = valid;
     pp.libs = d_libs;
     uint32_t *bstart = reinterpret_cast<uint32_t *>(ws + p.off_bstart);
-    TK_HIP(partition_keys(pp, kw, keys_b, keys_a, part, p.part_words, lib_keys, bstart, s));
+    KeyLayout lay{};
+    TK_HIP(partition_keys(pp, kw, keys_b, keys_a, part, p.part_words, lib_keys, bstart, &lay, s));
     uint64_t *sorted = keys_a, *other = keys_b;
     if ((st = tm.end(TK_STAGE_PARTITION, s)) != TK_OK || (st = tm.mark(TK_STAGE_BUCKET, s)) != TK_OK)
         return st;
@@ -840,6 +843,8 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
     ba.grp_count = reinterpret_cast<uint32_t *>(ws + p.off_grp_count);
     ba.chunk_next = &misc->chunk_next;
     ba.tile = p.opts.tile;
+    ba.layout = lay;
+    ba.grp_piece = reinterpret_cast<uint4 *>(ws + p.off_grp_piece);
     TK_HIP(launch_bucket(ba, kw, grid, s));
     if ((st = tm.end(TK_STAGE_BUCKET, s)) != TK_OK)
         return st;
@@ -914,14 +919,19 @@ tk_status run_partitioned(const uint8_t *d_bases, const uint64_t *d_offsets, con
         TK_HIP(zero_bytes(lib_ctr, (size_t)L * sizeof(DevCounters), s));  // per-library fallback counters
         if (p.screen)
             TK_HIP(zero_bytes(filter, n_blk * 64, s));
-        // screen and collect every library's oversized buckets (they are read
-        // from `sorted`, which becomes free afterwards)
+        // every oversized bucket's keys to its own index range of `other`
+        // (free there: the bucket kernel files records only in the ranges of
+        // its groups), where they are screened and collected; `sorted`
+        // becomes free
+        for (const Group &gr : groups)
+            TK_HIP(launch_fb_gather(sorted, other, d_ent + gr.e0, gr.ne, kw, lay, p.libs[gr.lib].seg0,
+                                    p.libs[gr.lib].D2, s));
         for (const Group &gr : groups) {
             const bool screen = p.libs[gr.lib].c >= 2;
             if (screen)
-                TK_HIP(launch_fb_screen(sorted, d_ent + gr.e0, gr.ne, gr.n_win, kw, table, p.opts.table_bits, filter,
+                TK_HIP(launch_fb_screen(other, d_ent + gr.e0, gr.ne, gr.n_win, kw, table, p.opts.table_bits, filter,
                                         s));
-            TK_HIP(launch_fb_collect(sorted, d_ent + gr.e0, gr.ne, gr.n_win, kw, table, p.opts.table_bits, filter,
+            TK_HIP(launch_fb_collect(other, d_ent + gr.e0, gr.ne, gr.n_win, kw, table, p.opts.table_bits, filter,
                                      screen, fbuf + gr.w0 * kw, &lib_ctr[gr.lib].n_collected, s));
         }
         std::vector<DevCounters> fc(L);

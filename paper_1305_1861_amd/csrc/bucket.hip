@@ -1,6 +1,8 @@
 // Per-bucket screen, sort and compaction in LDS.
 //
-// The keys arrive ordered by bucket (top D bits).  Every bucket owns a
+// The keys arrive partitioned by bucket (top D bits): a bucket is one range,
+// or, after a second partition pass, one piece per tile of its segment (the
+// kernel reads the tiles' prefix tables to find them).  Every bucket owns a
 // pattern-blocked Bloom filter sized from its own number of windows, so the
 // filter of one bucket fits in LDS and is touched by one workgroup only -- the
 // GPU counterpart of the paper's per-consumer filters (§2.1, parallelization:
@@ -179,6 +181,17 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     // sum is below the number of windows, hence below 2^32
     __shared__ uint32_t s_acc[BK_WAVES][3];
     __shared__ uint32_t s_tot[1];
+    // pieces of the next group of a tiled library (one per tile of its
+    // segment): s_pc[p] the group index of piece p's first key, s_dl[p] the
+    // key position of group index e in piece p minus e and the segment's
+    // start.  Row r (group indices 64 r .. 64 r + 63, one wave's load):
+    // s_row0[r] = piece of index 64 r | (pieces starting inside the row << 8),
+    // s_row1[r] = for one such piece, its number | (its first lane << 8).
+    constexpr int ROWS = (CAP + WAVE - 1) / WAVE;
+    __shared__ uint16_t s_pc[BK_TILES_MAX + 1];
+    __shared__ uint32_t s_dl[BK_TILES_MAX];
+    __shared__ uint32_t s_row0[ROWS], s_row1[ROWS];
+    static_assert(BK_TILES_MAX <= 4 * WAVE, "piece numbers fit a byte, four pieces per lane of wave 0");
 
     K *const s_ex = s_exs + 1;
     uint64_t *s_filter = reinterpret_cast<uint64_t *>(s_exs);
@@ -230,6 +243,83 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                 key[i] = keys[p + e];
         }
     };
+    // A group of a tiled library is one piece per tile of its segment
+    // (descriptor gp: first tile, tiles, segment start, digits): (1) thread
+    // t < tiles reads tile t's prefix entries of the group's first digit and
+    // of the digit after its last, (2) writes the piece's size and offset,
+    // (3) after a barrier wave 0 turns the sizes into the group indices of
+    // the pieces and marks, for every row of 64 indices, the piece of its
+    // first index and the pieces starting inside it, (4) after another
+    // barrier every thread loads its keys: one piece or two per row, else a
+    // walk from the row's first piece.
+    const uint32_t tile_keys = a.layout.tile_keys, pw = a.layout.pw;
+    auto piece_read = [&](const uint4 &gp, int t, uint32_t &lo, uint32_t &hi) {
+        lo = hi = 0;
+        if ((uint32_t)t < gp.y) {
+            const uint16_t *col = a.layout.px + (uint64_t)gp.x * pw + (uint32_t)t;
+            lo = col[(gp.w & 0xFFFFu) * gp.y];
+            hi = col[((gp.w >> 16) + 1) * gp.y];
+        }
+    };
+    auto piece_write = [&](const uint4 &gp, int t, uint32_t lo, uint32_t hi) {
+        if ((uint32_t)t < gp.y)
+            s_dl[t] = (hi - lo) | (lo << 16);  // size, offset in the tile (both < 2^16)
+    };
+    auto piece_index = [&](const uint4 &gp, uint32_t ln) {  // wave 0
+        const uint32_t np = gp.y;  // <= BK_TILES_MAX = 4 * WAVE
+        uint32_t v[4], o[4], sum = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t p = 4 * ln + (uint32_t)q;
+            const uint32_t w = p < np ? s_dl[p] : 0u;
+            v[q] = w & 0xFFFFu;
+            o[q] = w >> 16;
+            sum += v[q];
+        }
+        uint32_t run = wave_inclusive_sum(sum) - sum;
+        for (uint32_t r = ln; r < (uint32_t)ROWS; r += WAVE)
+            s_row0[r] = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t p = 4 * ln + (uint32_t)q;
+            if (p < np) {
+                s_pc[p] = (uint16_t)run;
+                s_dl[p] = p * tile_keys + o[q] - run;
+                if (v[q]) {
+                    // a piece starting inside a row is counted there; the
+                    // rows whose first index it holds name it
+                    if (run & (WAVE - 1)) {
+                        atomicAdd(&s_row0[run / WAVE], 1u << 8);
+                        s_row1[run / WAVE] = p | ((run & (WAVE - 1)) << 8);
+                    }
+                    for (uint32_t r = (run + WAVE - 1) / WAVE; r * WAVE < run + v[q]; r++)
+                        atomicOr(&s_row0[r], p);
+                }
+            }
+            run += v[q];
+        }
+    };
+    auto piece_load = [&](const uint4 &gp, uint32_t n, int t) {
+        const uint32_t np = gp.y, ln = (uint32_t)t % WAVE;
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint32_t e = (uint32_t)i * BK_THREADS + t;
+            key[i] = sentinel<K>();
+            if (e < n) {
+                const uint32_t r0 = s_row0[e / WAVE];
+                uint32_t p = r0 & 0xFFu;
+                if ((r0 >> 8) == 1) {
+                    const uint32_t r1 = s_row1[e / WAVE];
+                    if (ln >= (r1 >> 8))
+                        p = r1 & 0xFFu;
+                } else if (r0 >> 8) {
+                    while (p + 1 < np && (uint32_t)s_pc[p + 1] <= e)
+                        p++;
+                }
+                key[i] = keys[(uint32_t)(gp.z + s_dl[p] + e)];
+            }
+        }
+    };
     for (;;) {
     if (tid0 == 0)
         s_chunk = atomicAdd(a.chunk_next, 1u);
@@ -251,7 +341,19 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         // compiler does not hoist per-item addresses out of the chunk loop)
         int tidc = tid0;
         asm volatile("" : "+v"(tidc));
-        load_group(pos, n_sb, tidc);
+        const uint4 gp = a.grp_piece[gbase];
+        if (gp.y) {
+            uint32_t lo, hi;
+            piece_read(gp, tidc, lo, hi);
+            piece_write(gp, tidc, lo, hi);
+            __syncthreads();
+            if (tidc < WAVE)
+                piece_index(gp, (uint32_t)tidc);
+            __syncthreads();
+            piece_load(gp, n_sb, tidc);
+        } else {
+            load_group(pos, n_sb, tidc);
+        }
     }
 
     for (uint32_t g = 0; g < n_grp; g++) {
@@ -263,6 +365,14 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
         const uint32_t lane = (uint32_t)tid % WAVE;
         const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+        // the chunk's next group: buckets, and its pieces for a tiled library
+        uint32_t nb0 = 0, nb1 = 0;
+        uint4 ngp = make_uint4(0, 0, 0, 0);
+        if (g + 1 < n_grp) {
+            nb0 = a.grp_first[gbase + g + 1];
+            nb1 = a.grp_last[gbase + g + 1];
+            ngp = a.grp_piece[gbase + g + 1];
+        }
 
         // ---- the group's library ----
         {
@@ -449,6 +559,12 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             }
         }
         __syncthreads();
+        // the keys are in s_ex: the next group's prefix entries are requested
+        // now, written to LDS after the mixed-bin detection, indexed by wave 0
+        // after the mixed-bin count, its keys loaded after the ordering
+        uint32_t plo = 0, phi = 0;
+        if (ngp.y)
+            piece_read(ngp, tid, plo, phi);
         // mixed bins: a key differing from its left neighbour in the same bin
         const int n_ch = (int)((n_surv + BK_THREADS - 1) / BK_THREADS);
 #pragma unroll
@@ -464,6 +580,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             }
         }
         __syncthreads();
+        if (ngp.y)
+            piece_write(ngp, tid, plo, phi);
         // mixed bins of this thread (bins 8t .. 8t+7): number, keys, oversized
         // ones, packed into one sum (each field stays below 2^13, 2^13, 2^6)
         const uint32_t mixw = (s_mix[tid >> 2] >> ((tid & 3u) * 8u)) & 0xFFu;
@@ -478,6 +596,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         }
         uint32_t mix_tot;
         const uint32_t mix_ex = block_exclusive_sum<BK_THREADS>(mine, &mix_tot);
+        if (ngp.y && wave == 0)
+            piece_index(ngp, lane);  // read by piece_load after a barrier
         uint32_t n_sort = mix_tot & 0x1FFFu;
         const uint32_t n_mb = (mix_tot >> 13) & 0x1FFFu, n_big = mix_tot >> 26;
         if (n_sort > 0 && n_big == 0 && n_mb <= BK_LIST_MAX) {
@@ -742,15 +862,18 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         // the next group's keys are requested now (the sorted keys are in
         // s_ex), so that their latency overlaps the run-length pass, the
         // record writes and the bookkeeping below
-        uint32_t nb0 = 0, nb1 = 0, n_next = 0;  // the chunk's next group
+        uint32_t n_next = 0;
         uint64_t p_next = 0;
         if (g + 1 < n_grp) {
-            nb0 = a.grp_first[gbase + g + 1];
-            nb1 = a.grp_last[gbase + g + 1];
             p_next = a.bucket_starts[nb0];
             n_next = a.bucket_starts[nb1 + 1] - (uint32_t)p_next;
         }
-        load_group(p_next, n_next, tid);
+        if (ngp.y) {
+            __syncthreads();  // the piece table of the next group is complete
+            piece_load(ngp, n_next, tid);
+        } else {
+            load_group(p_next, n_next, tid);
+        }
         // ---- run-length compaction of s_ex[0, n_surv) ----
         // positions in (wave, item, lane) order with n_it items per wave.  A
         // run's count is its tail position minus its head position plus one;
@@ -879,6 +1002,32 @@ __device__ __forceinline__ uint32_t fb_entry_of(const FbEntry *__restrict__ e, u
             hi = mid;
     }
     return lo;
+}
+
+// Keys of oversized bucket ent[blockIdx.x] to dst + its first index: one
+// range, or in a tiled layout one piece per tile of its segment.
+template <typename K>
+__global__ __launch_bounds__(256) void fb_gather(const K *__restrict__ src, K *__restrict__ dst,
+                                                 const FbEntry *__restrict__ ent, KeyLayout lay, uint32_t seg0,
+                                                 int D2) {
+    const FbEntry e = ent[blockIdx.x];
+    K *const out = dst + e.start;
+    if (!lay.tiled || D2 == 0) {
+        for (uint32_t i = threadIdx.x; i < e.ns; i += 256)
+            out[i] = src[(uint64_t)e.start + i];
+        return;
+    }
+    const uint32_t sg = seg0 + (e.d >> D2), d2 = e.d & ((1u << D2) - 1u);
+    const uint32_t t0 = lay.tt[sg], nt = lay.tt[sg + 1] - t0;
+    const uint16_t *const col = lay.px + (uint64_t)t0 * lay.pw;
+    uint64_t at = lay.seg[sg];
+    uint32_t o = 0;
+    for (uint32_t i = 0; i < nt; i++, at += lay.tile_keys) {
+        const uint32_t lo = col[(uint64_t)d2 * nt + i], hi = col[(uint64_t)(d2 + 1) * nt + i];
+        for (uint32_t i = threadIdx.x; i < hi - lo; i += 256)
+            out[o + i] = src[at + lo + i];
+        o += hi - lo;
+    }
 }
 
 template <typename K>
@@ -1060,7 +1209,10 @@ __global__ __launch_bounds__(256) void lib_stats_kernel(const LibDesc *__restric
 // while its keys fit the registers (CAP), its filters the exchange buffer
 // (FMAX blocks) and its bucket ids span at most BK_RMAX.  A bucket too large
 // on its own goes to the fallback list instead (its records are filed under
-// it by the fallback kernels).  Groups never cross a chunk boundary.
+// it by the fallback kernels).  Groups never cross a chunk boundary.  In a
+// tiled layout, a group of a library with a second pass stays in one
+// segment and records where its pieces are (grp_piece); the buckets of a
+// segment with more than BK_TILES_MAX tiles all go to the fallback list.
 template <typename K, int TILE>
 __global__ __launch_bounds__(256) void plan_groups(BucketArgs a) {
     constexpr uint32_t CAP = BK_THREADS * BkItems<K, TILE>::value;
@@ -1076,15 +1228,26 @@ __global__ __launch_bounds__(256) void plan_groups(BucketArgs a) {
     for (uint32_t b = b_lo; b < b_hi;) {
         while (j + 1 < a.n_libs && a.libs[j + 1].bucket0 <= b)
             j++;
+        const LibDesc &L = a.libs[j];
         const uint32_t lib_end = j + 1 < a.n_libs ? a.libs[j + 1].bucket0 : a.n_buckets;
-        const bool screen = a.libs[j].c >= 2;
+        const bool screen = L.c >= 2;
         const uint32_t s0 = bs[b], ns = bs[b + 1] - s0;
         if (ns == 0) {
             b++;
             continue;
         }
+        // tiled: the bucket's segment, its tiles and the segment's last bucket
+        const bool tiled = a.layout.tiled && L.D2 > 0;
+        uint32_t seg_end = lib_end, t0 = 0, nt = 0, sgs = 0;
+        if (tiled) {
+            const uint32_t sg = L.seg0 + ((b - L.bucket0) >> L.D2);
+            seg_end = L.bucket0 + ((sg - L.seg0 + 1) << L.D2);
+            t0 = a.layout.tt[sg];
+            nt = a.layout.tt[sg + 1] - t0;
+            sgs = a.layout.seg[sg];
+        }
         const uint32_t nb = screen ? max(1u, (a.beta * ns + 255) / 256) : 0u;
-        if (ns > CAP || nb > FMAX) {
+        if (ns > CAP || nb > FMAX || nt > BK_TILES_MAX) {
             const uint32_t slot = atomicAdd(a.fb_count, 1u);
             if (slot < a.fb_cap) {
                 a.fb_list[3 * slot + 0] = b;
@@ -1096,7 +1259,7 @@ __global__ __launch_bounds__(256) void plan_groups(BucketArgs a) {
             continue;
         }
         uint32_t n_keys = ns, n_blocks = nb, last = b;
-        const uint32_t e_max = min(min(b_hi, lib_end), b + (uint32_t)BK_RMAX);
+        const uint32_t e_max = min(min(min(b_hi, lib_end), seg_end), b + (uint32_t)BK_RMAX);
         for (uint32_t e = b + 1; e < e_max; e++) {
             const uint32_t ne = bs[e + 1] - bs[e];
             if (ne == 0)
@@ -1110,6 +1273,8 @@ __global__ __launch_bounds__(256) void plan_groups(BucketArgs a) {
         }
         a.grp_first[b_lo + ng] = b;
         a.grp_last[b_lo + ng] = last;
+        const uint32_t m = (1u << L.D2) - 1u;
+        a.grp_piece[b_lo + ng] = make_uint4(t0, nt, sgs, ((b - L.bucket0) & m) | (((last - L.bucket0) & m) << 16));
         ng++;
         b = last + 1;
     }
@@ -1146,6 +1311,19 @@ hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream
     if (key_words == 2)
         return a.tile ? launch_bucket_tile<Key2, 1>(a, grid, stream) : launch_bucket_tile<Key2, 0>(a, grid, stream);
     return a.tile ? launch_bucket_tile<uint64_t, 1>(a, grid, stream) : launch_bucket_tile<uint64_t, 0>(a, grid, stream);
+}
+
+hipError_t launch_fb_gather(const void *src, void *dst, const FbEntry *ent, uint32_t n_ent, int key_words,
+                            const KeyLayout &layout, uint32_t seg0, int D2, hipStream_t stream) {
+    if (!n_ent)
+        return hipSuccess;
+    if (key_words == 2)
+        fb_gather<Key2><<<n_ent, 256, 0, stream>>>(static_cast<const Key2 *>(src), static_cast<Key2 *>(dst), ent,
+                                                   layout, seg0, D2);
+    else
+        fb_gather<uint64_t><<<n_ent, 256, 0, stream>>>(static_cast<const uint64_t *>(src),
+                                                       static_cast<uint64_t *>(dst), ent, layout, seg0, D2);
+    return hipGetLastError();
 }
 
 hipError_t launch_fb_screen(const void *keys, const FbEntry *ent, uint32_t n_ent, uint64_t n, int key_words,

@@ -71,15 +71,17 @@ __device__ __forceinline__ Key2 read_lane(const Key2 &x, int src) {
     return Key2{read_lane64(x.hi, src), read_lane64(x.lo, src)};
 }
 
-// Inclusive prefix sum across the wave.
+// Inclusive prefix sum across the wave, with DPP moves only (no LDS round
+// trips): shifts by 1, 2, 4 and 8 lanes within each row of 16 lanes (lanes
+// shifted in from outside the row add 0), then lane 15 of rows 0 and 2 into
+// rows 1 and 3, then lane 31 into rows 2 and 3.
 __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
-    const uint32_t l = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, WAVE);
-        if (l >= (uint32_t)d)
-            v += t;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111 /* row_shr:1 */, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112 /* row_shr:2 */, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114 /* row_shr:4 */, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118 /* row_shr:8 */, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142 /* row_bcast:15 */, 0xA, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143 /* row_bcast:31 */, 0xC, 0xF, false);
     return v;
 }
 

@@ -71,13 +71,14 @@ hipError_t launch_pack(const uint8_t *bases, const uint64_t *offsets, uint64_t n
                        const LibDesc *libs = nullptr, uint32_t n_libs = 0);
 
 // ---- partition.hip --------------------------------------------------------
-// Keys of every valid window, ordered by (library, top D bits): every bucket
-// is one contiguous range.  Pass 1 extracts the canonical keys from the
-// packed reads and orders them by (library, top D1 bits); pass 2, run when
-// some library has D2 > 0, orders every (library, top-digit) segment by the
-// next D2 bits (D2 = 0: a copy).  The order inside a bucket is unspecified.
-// Pass-1 chunks are per library: chunk i of library j covers window
-// positions [floor32(pos0) + i * chunk, ...) inside [pos0, pos1).
+// Keys of every valid window, ordered by (library, top D bits) as far as the
+// bucket kernel needs.  Pass 1 extracts the canonical keys from the packed
+// reads and orders them by (library, top D1 bits): every "segment" is one
+// contiguous range.  Pass 2, run when some library has D2 > 0, cuts every
+// segment into tiles and orders each tile by the next D2 bits in place
+// (D2 = 0: the tile is left as it is, in some order).  Pass-1 chunks are per
+// library: chunk i of library j covers window positions
+// [floor32(pos0) + i * chunk, ...) inside [pos0, pos1).
 uint64_t partition_chunk(int key_words);  // window positions (pass 1) or keys (pass 2) per chunk
 struct PartPlan {
     const uint64_t *packed;
@@ -93,12 +94,32 @@ struct PartPlan {
     uint32_t shard_index; // the shard whose keys are kept
     uint32_t n_buckets;   // buckets of all libraries
 };
+// Where the keys of a bucket are after the partition (device pointers into
+// its scratch).  Without a second pass (tiled = 0), and for the libraries
+// with D2 = 0, bucket b is the range [bucket_starts[b], bucket_starts[b + 1])
+// of the output.  With one, a bucket of a library with D2 > 0 is digit d2
+// (its low D2 bits) of segment s = seg0 + (its top D1 bits): the segment's
+// keys [seg[s], seg[s + 1]) form its T = tt[s + 1] - tt[s] tiles of
+// tile_keys keys each (tile i of the segment starts at seg[s] + i *
+// tile_keys), and in tile i digit d occupies [px[x + d * T + i],
+// px[x + (d + 1) * T + i]) relative to the tile's start, x = tt[s] * pw.
+// bucket_starts then holds the exclusive prefix of the bucket sizes:
+// disjoint index ranges of the right sizes, in (library, bucket) order, that
+// coincide with the key positions of the contiguous buckets.
+struct KeyLayout {
+    int tiled;
+    const uint32_t *seg, *tt;
+    const uint16_t *px;
+    uint32_t pw, tile_keys;
+};
 size_t partition_scratch_words(const PartPlan &p, int key_words);
 // out receives the keys; lib_keys (device, n_libs + 1) the first key of
 // every library and the number of keys; bucket_starts (device,
-// n_buckets + 1) the first key of every bucket and the number of keys.
+// n_buckets + 1) the first index of every bucket and the number of keys;
+// *layout where the buckets are.
 hipError_t partition_keys(const PartPlan &p, int key_words, void *tmp, void *out, uint32_t *scratch,
-                          size_t scratch_words, uint32_t *lib_keys, uint32_t *bucket_starts, hipStream_t stream);
+                          size_t scratch_words, uint32_t *lib_keys, uint32_t *bucket_starts, KeyLayout *layout,
+                          hipStream_t stream);
 
 // ---- bucket.hip -----------------------------------------------------------
 struct BucketArgs {
@@ -128,9 +149,13 @@ struct BucketArgs {
     uint32_t *grp_first, *grp_last, *grp_count;
     uint32_t *chunk_next;           // chunk counter, zero before the launch
     int tile;                       // tile shape (keys per thread), 0 or 1
+    KeyLayout layout;               // where the buckets' keys are (from the partition)
+    uint4 *grp_piece;               // per group of a tiled library: first tile, tiles,
+                                    // segment start, first | (last digit << 16); others: tiles = 0
 };
 int bucket_grid();
 constexpr uint32_t BK_CHUNK_MAX = 32;  // bucket ids per chunk of the bucket kernel's schedule
+constexpr uint32_t BK_TILES_MAX = 256;  // tiles a group of a tiled library may span
 int bucket_capacity(int key_words, int tile);
 hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream);
 // Oversized buckets (more keys than a workgroup holds) of one library, in
@@ -140,6 +165,11 @@ struct FbEntry {
     uint32_t wpre, fpre;    // keys and filter blocks of the entries before
     uint32_t nb;            // filter blocks of this bucket
 };
+// Copies the keys of the listed oversized buckets of one library (first
+// segment seg0, D2 second-pass bits) to dst + each bucket's first index
+// (ent[i].start), from src laid out as `layout` describes.
+hipError_t launch_fb_gather(const void *src, void *dst, const FbEntry *ent, uint32_t n_ent, int key_words,
+                            const KeyLayout &layout, uint32_t seg0, int D2, hipStream_t stream);
 hipError_t launch_fb_screen(const void *keys, const FbEntry *ent, uint32_t n_ent, uint64_t n, int key_words,
                             const uint64_t *table, uint32_t table_bits, uint64_t *filter, hipStream_t stream);
 hipError_t launch_fb_collect(const void *keys, const FbEntry *ent, uint32_t n_ent, uint64_t n, int key_words,

@@ -1,23 +1,31 @@
 // Partitioning of the window keys by (library, top D bits), D <= 20 -- the
 // GPU counterpart of routing every k-mer to the consumer that owns its filter
-// (paper §2.1, parallelization): afterwards every bucket (keys of one library
-// sharing their top D bits) is one contiguous range, libraries follow each
-// other and buckets are in key order inside a library, so per-bucket
+// (paper §2.1, parallelization): afterwards the keys of every bucket (keys of
+// one library sharing their top D bits) can be found without a search, and
+// libraries and buckets follow each other in key order, so per-bucket
 // sort-and-compact results concatenate into each library's sorted answer.
 //
 // Pass 1 extracts the canonical keys straight from the packed reads (§2.1,
 // k-mer extraction) and orders them by (library, top D1 = min(D, 10) bits):
-// the "segments".  Pass 2 orders every segment by the next D2 = D - D1 bits
-// (a plain copy for libraries with D2 = 0).  The order of keys inside a
-// bucket is not kept -- the bucket kernel sorts each bucket -- so both passes
-// rank keys with LDS atomic counters instead of a stable ranking.
+// the "segments", each one contiguous range.  Pass 2 (run when some library
+// has D2 = D - D1 > 0) cuts every segment into tiles of PtItems * PT_THREADS
+// keys and orders each tile by the next D2 bits in place, recording for
+// every tile the first position of every digit (a prefix table of 16-bit
+// entries).  A bucket is then digit d of its segment: one piece per tile of
+// the segment, found from the prefix tables, and its size is the sum of its
+// pieces.  Ordering tiles rather than whole segments spares a histogram pass
+// over all keys and turns the second pass's writes into one sequential
+// stream.  The order of keys inside a bucket is not kept -- the bucket
+// kernel sorts each bucket -- so both passes rank keys with LDS atomic
+// counters instead of a stable ranking.
 //
-// Work unit: a chunk of up to PT_CH tiles, one workgroup each; chunks never
-// straddle a library (pass 1) or a segment (pass 2).  hist counts the chunk's
-// digits; the counts are laid out (library or segment, digit, chunk) so that
-// one exclusive scan gives every (chunk, digit) its write position.  scatter,
-// per tile: rank every key within its digit (LDS atomics), stage the tile in
-// LDS in digit order, write each digit's run contiguously at its cursor.
+// Pass-1 work unit: a chunk of up to PT_CH tiles, one workgroup each; chunks
+// never straddle a library.  hist counts the chunk's digits; the counts are
+// laid out (library, digit, chunk) so that one exclusive scan gives every
+// (chunk, digit) its write position.  scatter, per tile: rank every key
+// within its digit (LDS atomics), stage the tile in LDS in digit order, write
+// each digit's run contiguously at its cursor.  Pass 2 takes chunks of up to
+// PT_CH tiles of one segment and writes every tile back in digit order.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -53,6 +61,7 @@ constexpr uint64_t pt_chunk() {
     return pt_tile<K>() * PT_CH;
 }
 
+
 // Largest i in [0, n) with at(i) <= v, for a non-decreasing at(); 0 if none.
 template <typename F>
 __device__ __forceinline__ uint32_t last_le(uint32_t n, uint64_t v, F at) {
@@ -75,7 +84,7 @@ struct PassArgs {
     uint32_t n_libs;
     const uint32_t *seg;     // pass 2: start of every segment (nseg + 1)
     const uint32_t *cb;      // pass 2: first chunk of every segment (nseg + 1)
-    const uint32_t *eb;      // pass 2: first count entry of every segment (nseg + 1)
+    const uint32_t *tt;      // pass 2: first tile of every segment (nseg + 1)
     uint32_t nseg;
     const uint32_t *own;     // pass 1 of a key-range shard: its digits
                              // [own[0], own[1]); nullptr: every digit
@@ -89,7 +98,8 @@ struct Chunk {
     uint64_t c0, c1, lo, hidx;
     uint32_t hstride;
     int shift, bits;
-    int k;  // the library's k-mer length
+    int k;         // the library's k-mer length
+    uint32_t tile;  // pass 2: global index of the chunk's first tile
 };
 
 template <typename K, bool FROM_WIN>
@@ -109,6 +119,7 @@ __device__ __forceinline__ bool chunk_of(const PassArgs &a, Chunk &ch) {
         ch.shift = 2 * L.k - L.D1;
         ch.bits = L.D1;
         ch.k = L.k;
+        ch.tile = 0;
         return true;
     }
     if (b >= a.cb[a.nseg])
@@ -119,11 +130,12 @@ __device__ __forceinline__ bool chunk_of(const PassArgs &a, Chunk &ch) {
     ch.c0 = a.seg[s] + (uint64_t)i * pt_chunk<K>();
     ch.c1 = min(ch.c0 + pt_chunk<K>(), (uint64_t)a.seg[s + 1]);
     ch.lo = ch.c0;
-    ch.hidx = a.eb[s] + i;
-    ch.hstride = a.cb[s + 1] - a.cb[s];
+    ch.hidx = 0;
+    ch.hstride = 0;
     ch.shift = 2 * a.libs[j].k - a.libs[j].D;
     ch.bits = a.libs[j].D2;
     ch.k = a.libs[j].k;
+    ch.tile = a.tt[s] + i * PT_CH;
     return true;
 }
 
@@ -233,82 +245,73 @@ __device__ __forceinline__ uint32_t load_tile(const PassArgs &a, uint64_t t0, ui
     return vm;
 }
 
-template <typename K, bool FROM_WIN>
+// Pass 1: digit counts of every chunk.
+template <typename K>
 __global__ __launch_bounds__(PT_THREADS) void pt_hist(PassArgs a, uint32_t *__restrict__ hist) {
     constexpr int ITEMS = PtItems<K>::value;
     __shared__ uint32_t s_h[PT_MAX_BINS];
     const int tid = threadIdx.x;
     Chunk ch;
-    if (!chunk_of<K, FROM_WIN>(a, ch))
+    if (!chunk_of<K, true>(a, ch))
         return;  // uniform over the block
     const uint32_t bins = 1u << ch.bits, mask = bins - 1;
     for (int d = tid; d < PT_MAX_BINS; d += PT_THREADS)
         s_h[d] = 0;
     __syncthreads();
-    if (FROM_WIN) {
-        // the next tile's words are requested before this tile's keys are
-        // rolled out and counted
-        RawWin cur = ch.c0 < ch.c1 ? fetch_win<K>(a, ch.c0, min(ch.c0 + pt_tile<K>(), ch.c1), ch.lo)
-                                   : RawWin{0, 0, 0, 0, 0};
-        for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += pt_tile<K>()) {
-            const uint64_t tn = t0 + pt_tile<K>();
-            RawWin nxt{0, 0, 0, 0, 0};
-            if (tn < ch.c1)
-                nxt = fetch_win<K>(a, tn, min(tn + pt_tile<K>(), ch.c1), ch.lo);
-            if (cur.okmask && ch.k >= 5) {
-                // The top bits of the canonical key, the smaller of the
-                // forward code and its reverse complement, are the smaller
-                // of the two codes' top bits.  So a window's digit (at most
-                // 10 bits) needs only its first five bases, forward, and its
-                // last five, reverse-complemented: two fields of words
-                // assembled once per thread, instead of the whole key.
-                constexpr int PER_WORD = 32 / ITEMS;
-                const int first = (tid % PER_WORD) * ITEMS;
-                const uint32_t ok = (cur.vword >> first) & cur.okmask;
-                const uint64_t last5 = ~group_reverse(codes_ending_at(cur, first + ITEMS - 1));
-                const uint64_t first5 = codes_ending_at(cur, first + ITEMS + 4 - ch.k);
-                const int drop = 10 - ch.bits;
+    // the next tile's words are requested before this tile's keys are
+    // rolled out and counted
+    RawWin cur = ch.c0 < ch.c1 ? fetch_win<K>(a, ch.c0, min(ch.c0 + pt_tile<K>(), ch.c1), ch.lo)
+                               : RawWin{0, 0, 0, 0, 0};
+    for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += pt_tile<K>()) {
+        const uint64_t tn = t0 + pt_tile<K>();
+        RawWin nxt{0, 0, 0, 0, 0};
+        if (tn < ch.c1)
+            nxt = fetch_win<K>(a, tn, min(tn + pt_tile<K>(), ch.c1), ch.lo);
+        if (cur.okmask && ch.k >= 5) {
+            // The top bits of the canonical key, the smaller of the
+            // forward code and its reverse complement, are the smaller
+            // of the two codes' top bits.  So a window's digit (at most
+            // 10 bits) needs only its first five bases, forward, and its
+            // last five, reverse-complemented: two fields of words
+            // assembled once per thread, instead of the whole key.
+            constexpr int PER_WORD = 32 / ITEMS;
+            const int first = (tid % PER_WORD) * ITEMS;
+            const uint32_t ok = (cur.vword >> first) & cur.okmask;
+            const uint64_t last5 = ~group_reverse(codes_ending_at(cur, first + ITEMS - 1));
+            const uint64_t first5 = codes_ending_at(cur, first + ITEMS + 4 - ch.k);
+            const int drop = 10 - ch.bits;
 #pragma unroll
-                for (int i = 0; i < ITEMS; i++) {
-                    if ((ok >> i) & 1u) {
-                        const uint32_t f = (uint32_t)(first5 >> (2 * (ITEMS - 1 - i))) & 0x3FFu;
-                        const uint32_t r = (uint32_t)(last5 >> (56 - 2 * ITEMS + 2 * i)) & 0x3FFu;
-                        atomicAdd(&s_h[min(f, r) >> drop], 1u);
-                    }
-                }
-            } else if (cur.okmask) {
-                // k < 5: each key is counted as it is rolled out
-                constexpr int PER_WORD = 32 / ITEMS;
-                const uint32_t first = (uint32_t)(tid % PER_WORD) * ITEMS;
-                const uint32_t ok = (cur.vword >> first) & cur.okmask;
-                typename KeyOf<std::is_same<K, Key2>::value>::Roll rl;
-                rl.init(cur.w0, cur.w1, cur.w2, first, ch.k);
-#pragma unroll
-                for (int i = 0; i < ITEMS; i++) {
-                    if (i)
-                        rl.step((uint32_t)(cur.w0 >> (62 - 2 * (first + i))) & 3u);
-                    if ((ok >> i) & 1u)
-                        atomicAdd(&s_h[digit_of(rl.key(), ch.shift, mask)], 1u);
+            for (int i = 0; i < ITEMS; i++) {
+                if ((ok >> i) & 1u) {
+                    const uint32_t f = (uint32_t)(first5 >> (2 * (ITEMS - 1 - i))) & 0x3FFu;
+                    const uint32_t r = (uint32_t)(last5 >> (56 - 2 * ITEMS + 2 * i)) & 0x3FFu;
+                    atomicAdd(&s_h[min(f, r) >> drop], 1u);
                 }
             }
-            cur = nxt;
-        }
-    } else {
-        for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += pt_tile<K>()) {
-            K key[ITEMS];
-            const uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + pt_tile<K>(), ch.c1), ch.lo, ch.k, key);
+        } else if (cur.okmask) {
+            // k < 5: each key is counted as it is rolled out
+            constexpr int PER_WORD = 32 / ITEMS;
+            const uint32_t first = (uint32_t)(tid % PER_WORD) * ITEMS;
+            const uint32_t ok = (cur.vword >> first) & cur.okmask;
+            typename KeyOf<std::is_same<K, Key2>::value>::Roll rl;
+            rl.init(cur.w0, cur.w1, cur.w2, first, ch.k);
 #pragma unroll
-            for (int i = 0; i < ITEMS; i++)
-                if ((vm >> i) & 1u)
-                    atomicAdd(&s_h[digit_of(key[i], ch.shift, mask)], 1u);
+            for (int i = 0; i < ITEMS; i++) {
+                if (i)
+                    rl.step((uint32_t)(cur.w0 >> (62 - 2 * (first + i))) & 3u);
+                if ((ok >> i) & 1u)
+                    atomicAdd(&s_h[digit_of(rl.key(), ch.shift, mask)], 1u);
+            }
         }
+        cur = nxt;
     }
     __syncthreads();
     for (uint32_t d = tid; d < bins; d += PT_THREADS)
         hist[ch.hidx + (uint64_t)d * ch.hstride] = s_h[d];
 }
 
-template <typename K, bool FROM_WIN>
+// Pass 1: keys of every chunk to their (library, digit, chunk) places.
+template <typename K>
 __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint32_t *__restrict__ offs,
                                                          K *__restrict__ out) {
     constexpr int ITEMS = PtItems<K>::value;
@@ -321,12 +324,12 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint3
     const int wave = tid / WAVE;
     const uint32_t lane = lane_id();
     Chunk ch;
-    if (!chunk_of<K, FROM_WIN>(a, ch))
+    if (!chunk_of<K, true>(a, ch))
         return;  // uniform over the block
     const uint32_t bins = 1u << ch.bits, mask = bins - 1;
-    // a shard keeps the keys of its digits only (pass 1, one library)
+    // a shard keeps the keys of its digits only (one library)
     uint32_t own_lo = 0, own_hi = bins;
-    if (FROM_WIN && a.own) {
+    if (a.own) {
         own_lo = a.own[0];
         own_hi = a.own[1];
     }
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint3
     __syncthreads();
     for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += TILE) {
         K key[ITEMS];
-        uint32_t vm = load_tile<K, FROM_WIN>(a, t0, min(t0 + (uint64_t)TILE, ch.c1), ch.lo, ch.k, key);
+        uint32_t vm = load_tile<K, true>(a, t0, min(t0 + (uint64_t)TILE, ch.c1), ch.lo, ch.k, key);
         uint32_t rd[ITEMS];  // (rank << 10) | digit
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
@@ -402,6 +405,99 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint3
                 s_cur[d0 + j] += c[j];
             s_cnt[d0 + j] = 0;
         }
+        __syncthreads();
+    }
+}
+
+// Pass 2: every tile of a segment (up to PT_CH per workgroup) ordered by its
+// library's next D2 bits in place; pt[t * pw + d] receives the first
+// position of digit d in tile t, entries past the last digit the tile's
+// size.  A tile holds at most 2^14 keys, so the entries fit 16 bits.
+template <typename K>
+__global__ __launch_bounds__(PT_THREADS) void pt_tiles(PassArgs a, uint16_t *__restrict__ pt, uint32_t pw,
+                                                       K *__restrict__ out) {
+    constexpr int ITEMS = PtItems<K>::value;
+    constexpr int TILE = PT_THREADS * ITEMS;
+    static_assert(TILE <= 65535, "prefix entries are 16 bits");
+    static_assert(TILE < (1 << (32 - PT_MAX_BITS)), "(rank, digit) fits a word");
+    __shared__ uint32_t s_cnt[PT_MAX_BINS];  // digit counts of the tile, then their starts
+    __shared__ uint32_t s_wt[PT_WAVES];
+    __shared__ K s_stage[TILE];
+    const int tid = threadIdx.x;
+    const int wave = tid / WAVE;
+    const uint32_t lane = lane_id();
+    Chunk ch;
+    if (!chunk_of<K, false>(a, ch))
+        return;  // uniform over the block
+    const uint32_t bins = 1u << ch.bits, mask = bins - 1;
+    const uint32_t d0 = (uint32_t)tid * PT_BPT;
+    const K *__restrict__ in = static_cast<const K *>(a.keys_in);
+#pragma unroll
+    for (int j = 0; j < PT_BPT; j++)
+        s_cnt[d0 + j] = 0;
+    __syncthreads();
+    uint32_t tile = ch.tile;
+    for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += TILE, tile++) {
+        const uint32_t n_tile = (uint32_t)min((uint64_t)TILE, ch.c1 - t0);
+        // all of the tile's loads first, then the ranking (the LDS atomics
+        // would otherwise hold each load back)
+        K key[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint32_t e = (uint32_t)i * PT_THREADS + tid;
+            key[i] = K{};
+            if (e < n_tile)
+                key[i] = in[t0 + e];
+        }
+        uint32_t rd[ITEMS];  // (rank << 10) | digit; ~0 for no key
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            rd[i] = ~0u;
+            if ((uint32_t)i * PT_THREADS + tid < n_tile) {
+                const uint32_t d = digit_of(key[i], ch.shift, mask);
+                rd[i] = (atomicAdd(&s_cnt[d], 1u) << PT_MAX_BITS) | d;
+            }
+        }
+        __syncthreads();
+        // starts of the digits in the tile, also its prefix table
+        uint32_t c[PT_BPT];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < PT_BPT; j++) {
+            c[j] = s_cnt[d0 + j];
+            sum += c[j];
+        }
+        const uint32_t inc = wave_inclusive_sum(sum);
+        if (lane == WAVE - 1)
+            s_wt[wave] = inc;
+        __syncthreads();
+        uint32_t before = 0;
+#pragma unroll
+        for (int w = 0; w < PT_WAVES; w++)
+            before += w < wave ? s_wt[w] : 0u;
+        uint32_t run = before + inc - sum;
+        uint16_t *const row = pt + (uint64_t)tile * pw;
+#pragma unroll
+        for (int j = 0; j < PT_BPT; j++) {
+            s_cnt[d0 + j] = run;
+            if (d0 + j < pw)
+                row[d0 + j] = (uint16_t)(d0 + j < bins ? run : n_tile);
+            run += c[j];
+        }
+        for (uint32_t d = PT_MAX_BINS + tid; d < pw; d += PT_THREADS)
+            row[d] = (uint16_t)n_tile;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++)
+            if (rd[i] != ~0u)
+                s_stage[s_cnt[rd[i] & (PT_MAX_BINS - 1)] + (rd[i] >> PT_MAX_BITS)] = key[i];
+        __syncthreads();
+        // the tile back to its own positions, now in digit order
+        for (uint32_t j = tid; j < n_tile; j += PT_THREADS)
+            out[t0 + j] = s_stage[j];
+#pragma unroll
+        for (int j = 0; j < PT_BPT; j++)
+            s_cnt[d0 + j] = 0;
         __syncthreads();
     }
 }
@@ -481,13 +577,13 @@ __device__ __forceinline__ uint32_t segment_start(const PassArgs &a, const uint3
     return e < n_hist1 ? scan1[e] : total1;
 }
 
-// Per segment: its start, its number of pass-2 chunks and of pass-2 count
-// entries; the first key of every library.
+// Per segment: its start, its number of pass-2 chunks and of pass-2 tiles;
+// the first key of every library.
 template <typename K>
 __global__ __launch_bounds__(SEG_THREADS) void pt_segments(PassArgs a, const uint32_t *__restrict__ scan1,
                                                            uint64_t n_hist1, const uint32_t *__restrict__ total1p,
                                                            uint32_t *__restrict__ seg, uint32_t *__restrict__ chs,
-                                                           uint32_t *__restrict__ ent, uint32_t *__restrict__ lib_keys) {
+                                                           uint32_t *__restrict__ tiles, uint32_t *__restrict__ lib_keys) {
     const uint32_t total1 = *total1p;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= a.nseg; t += stride) {
@@ -496,10 +592,8 @@ __global__ __launch_bounds__(SEG_THREADS) void pt_segments(PassArgs a, const uin
         seg[s] = start;
         if (s < a.nseg) {
             const uint32_t end = segment_start(a, scan1, n_hist1, total1, s + 1);
-            const uint32_t j = last_le(a.n_libs, s, [&](uint32_t i) { return (uint64_t)a.libs[i].seg0; });
-            const uint32_t n_ch = (uint32_t)(((uint64_t)(end - start) + pt_chunk<K>() - 1) / pt_chunk<K>());
-            chs[s] = n_ch;
-            ent[s] = n_ch << a.libs[j].D2;
+            chs[s] = (uint32_t)(((uint64_t)(end - start) + pt_chunk<K>() - 1) / pt_chunk<K>());
+            tiles[s] = (uint32_t)(((uint64_t)(end - start) + pt_tile<K>() - 1) / pt_tile<K>());
         }
     }
     // first key of every library: the start of its first segment
@@ -510,13 +604,10 @@ __global__ __launch_bounds__(SEG_THREADS) void pt_segments(PassArgs a, const uin
 }
 
 // First key of every bucket (global id b = bucket0 of its library + its top
-// D bits; entry n_buckets: the number of keys).  A bucket is digit d2 of
-// its library's segment s: after the second pass it starts where the scan
-// placed digit d2 of the segment's first chunk; a segment without keys, and
-// every segment of a library without a second digit, gives its own start.
-__global__ __launch_bounds__(256) void pt_bucket_starts(PassArgs a, const uint32_t *__restrict__ scan2, bool pass2,
-                                                        const uint32_t *__restrict__ total1p, uint32_t n_buckets,
-                                                        uint32_t *__restrict__ starts) {
+// D bits; entry n_buckets: the number of keys) when there is no second pass:
+// every bucket is a segment.
+__global__ __launch_bounds__(256) void pt_bucket_starts(PassArgs a, const uint32_t *__restrict__ total1p,
+                                                        uint32_t n_buckets, uint32_t *__restrict__ starts) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= n_buckets; t += stride) {
         const uint32_t b = (uint32_t)t;
@@ -526,39 +617,112 @@ __global__ __launch_bounds__(256) void pt_bucket_starts(PassArgs a, const uint32
         }
         const uint32_t j = last_le(a.n_libs, b, [&](uint32_t i) { return (uint64_t)a.libs[i].bucket0; });
         const LibDesc &L = a.libs[j];
-        const uint32_t d = b - L.bucket0;
-        const uint32_t sg = L.seg0 + (d >> L.D2);
-        const uint32_t d2 = d & ((1u << L.D2) - 1u);
-        uint32_t st = a.seg[sg];
-        if (pass2) {
-            const uint32_t nch = a.cb[sg + 1] - a.cb[sg];
-            if (nch)
-                st = scan2[a.eb[sg] + (uint64_t)d2 * nch];
-        }
-        starts[b] = st;
+        starts[b] = a.seg[L.seg0 + (b - L.bucket0)];
     }
+}
+
+// The prefix tables of every segment transposed (px: the segment's tiles
+// side by side per digit, digit d of tile tt[s] + i at tt[s] * pw + d * T + i
+// for the segment's T tiles, so that one digit's entries over all tiles are
+// contiguous), and the size of every bucket (into sizes[b], b = bucket0 of
+// its library + its top D bits): digit d2 of its segment summed over the
+// segment's tiles, the difference of two row sums.  One workgroup per
+// segment, blocks of 64 tiles x 64 digits through LDS.
+constexpr int TR_THREADS = 256;
+constexpr int TR_B = 64;
+__global__ __launch_bounds__(TR_THREADS) void pt_transpose(PassArgs a, const uint16_t *__restrict__ pt, uint32_t pw,
+                                                           uint16_t *__restrict__ px, uint32_t *__restrict__ sizes) {
+    __shared__ uint16_t s_b[TR_B][TR_B + 2];
+    __shared__ uint32_t s_rs[PT_MAX_BINS + 1];
+    const uint32_t s = blockIdx.x;
+    if (s >= a.nseg)
+        return;
+    const int tid = threadIdx.x;
+    const uint32_t j = last_le(a.n_libs, s, [&](uint32_t i) { return (uint64_t)a.libs[i].seg0; });
+    const LibDesc &L = a.libs[j];
+    const uint32_t bins = 1u << L.D2, nd = bins + 1;
+    const uint32_t t0 = a.tt[s], T = a.tt[s + 1] - t0;
+    uint16_t *const out = px + (uint64_t)t0 * pw;
+    for (uint32_t dd = 0; dd < nd; dd += TR_B) {
+        uint32_t acc = 0;  // row sum of digit dd + tid (tid < TR_B)
+        for (uint32_t tb = 0; tb < T; tb += TR_B) {
+            for (int x = tid; x < TR_B * TR_B; x += TR_THREADS) {
+                const uint32_t ti = (uint32_t)x / TR_B, di = (uint32_t)x % TR_B;
+                s_b[ti][di] = (tb + ti < T && dd + di < nd) ? pt[(uint64_t)(t0 + tb + ti) * pw + dd + di] : 0;
+            }
+            __syncthreads();
+            for (int x = tid; x < TR_B * TR_B; x += TR_THREADS) {
+                const uint32_t di = (uint32_t)x / TR_B, ti = (uint32_t)x % TR_B;
+                if (tb + ti < T && dd + di < nd)
+                    out[(uint64_t)(dd + di) * T + tb + ti] = s_b[ti][di];
+            }
+            if (tid < TR_B)
+                for (int ti = 0; ti < TR_B; ti++)
+                    acc += s_b[ti][tid];
+            __syncthreads();
+        }
+        if (tid < TR_B && dd + tid < nd)
+            s_rs[dd + tid] = acc;
+    }
+    __syncthreads();
+    const uint32_t b0 = L.bucket0 + ((s - L.seg0) << L.D2);
+    for (uint32_t d = tid; d < bins; d += TR_THREADS)
+        sizes[b0 + d] = s_rs[d + 1] - s_rs[d];
+}
+
+// Scratch words of the partition, in order: pass-1 counts and their scan
+// scratch, segment starts, pass-2 chunks and tiles per segment, their scan
+// scratch, totals, shard digits; with a second pass also the bucket-size
+// scan scratch and the tiles' prefix tables, as written and transposed.
+struct ScratchMap {
+    uint64_t hist, seg, cb, tt, sscan, total1, own, bscan, pt, px, words;
+    uint64_t n_tiles;  // bound on pass-2 tiles
+    uint32_t pw;       // prefix entries per tile
+};
+
+ScratchMap scratch_map(const PartPlan &p, uint64_t tile) {
+    ScratchMap m{};
+    const uint64_t n1 = p.n_hist1;
+    const uint64_t ns = (uint64_t)p.nseg + 1;
+    m.hist = 0;
+    m.seg = n1 + scan_scratch_words(n1);
+    m.cb = m.seg + ns;
+    m.tt = m.cb + ns;
+    m.sscan = m.tt + ns;
+    m.total1 = m.sscan + scan_scratch_words(p.nseg);
+    m.own = m.total1 + 4;
+    uint64_t w = m.own + (p.shard_count > 1 ? p.nseg + 2 : 0);
+    if (p.D2max) {
+        m.bscan = w;
+        w += scan_scratch_words(p.n_buckets);
+        m.pw = (1u << p.D2max) + 1;
+        m.n_tiles = ceil_div(p.cap, tile) + p.nseg;  // pass-2 tiles
+        m.pt = align_up(w, 4);
+        w = m.pt + ceil_div(m.n_tiles * m.pw, 2);
+        m.px = align_up(w, 4);
+        w = m.px + ceil_div(m.n_tiles * m.pw, 2);
+    }
+    m.words = w;
+    return m;
 }
 
 template <typename K>
 hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scratch, size_t scratch_words,
-                         uint32_t *lib_keys, uint32_t *bucket_starts, hipStream_t stream) {
+                         uint32_t *lib_keys, uint32_t *bucket_starts, KeyLayout *layout, hipStream_t stream) {
     if (p.D2max < 0 || p.D2max > PT_MAX_BITS)
         return hipErrorInvalidValue;
-    const uint64_t n1 = p.n_hist1;
-    const uint64_t grid2 = ceil_div(p.cap, pt_chunk<K>()) + p.nseg;  // bound on pass-2 chunks
-    const uint64_t n2 = grid2 << p.D2max;
-    const uint64_t H = std::max(n1 + scan_scratch_words(n1), n2 + scan_scratch_words(n2));
+    const ScratchMap m = scratch_map(p, pt_tile<K>());
     const bool shard = p.shard_count > 1;
-    const uint64_t need = H + 3 * ((uint64_t)p.nseg + 1) + scan_scratch_words(p.nseg) + 4 + (shard ? p.nseg + 2 : 0);
-    if (need > scratch_words || (shard && (p.n_libs != 1 || p.nseg > SH_THREADS)))
+    if (m.words > scratch_words || (shard && (p.n_libs != 1 || p.nseg > SH_THREADS)))
         return hipErrorInvalidValue;
-    uint32_t *hist = scratch;
-    uint32_t *seg = scratch + H;
-    uint32_t *cb = seg + (p.nseg + 1);
-    uint32_t *eb = cb + (p.nseg + 1);
-    uint32_t *sscan = eb + (p.nseg + 1);
-    uint32_t *total1 = sscan + scan_scratch_words(p.nseg);
-    uint32_t *own = total1 + 4;    // shards: owned digits, then the digit totals
+    const uint64_t n1 = p.n_hist1;
+    uint32_t *hist = scratch + m.hist;
+    uint32_t *seg = scratch + m.seg;
+    uint32_t *cb = scratch + m.cb;
+    uint32_t *tt = scratch + m.tt;
+    uint32_t *sscan = scratch + m.sscan;
+    uint32_t *total1 = scratch + m.total1;
+    uint32_t *own = scratch + m.own;  // shards: owned digits, then the digit totals
     uint32_t *dig_tot = own + 2;
     const dim3 block(PT_THREADS);
 
@@ -569,15 +733,16 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
     a.n_libs = p.n_libs;
     a.seg = seg;
     a.cb = cb;
-    a.eb = eb;
+    a.tt = tt;
     a.nseg = p.nseg;
     a.cap = p.cap;
+    *layout = KeyLayout{};
 
     // pass 1: windows -> (second pass ? tmp : out), by (library, top D1 bits)
     void *out1 = p.D2max ? tmp : out;
     hipError_t e;
     if (p.nch1) {
-        pt_hist<K, true><<<dim3(p.nch1), block, 0, stream>>>(a, hist);
+        pt_hist<K><<<dim3(p.nch1), block, 0, stream>>>(a, hist);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (shard) {  // one library: nseg digits of nch1 counts each
@@ -593,37 +758,50 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
     if ((e = launch_exclusive_scan(hist, hist, n1, hist + n1, total1, stream)) != hipSuccess)
         return e;
     if (p.nch1) {
-        pt_scatter<K, true><<<dim3(p.nch1), block, 0, stream>>>(a, hist, static_cast<K *>(out1));
+        pt_scatter<K><<<dim3(p.nch1), block, 0, stream>>>(a, hist, static_cast<K *>(out1));
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
     const unsigned sgrid = (unsigned)std::min<uint64_t>(ceil_div((uint64_t)p.nseg + 1, SEG_THREADS), 4096);
-    pt_segments<K><<<dim3(sgrid), dim3(SEG_THREADS), 0, stream>>>(a, hist, n1, total1, seg, cb, eb, lib_keys);
+    pt_segments<K><<<dim3(sgrid), dim3(SEG_THREADS), 0, stream>>>(a, hist, n1, total1, seg, cb, tt, lib_keys);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    const unsigned bgrid = (unsigned)std::min<uint64_t>(ceil_div((uint64_t)p.n_buckets + 1, 256), 8192);
     if (!p.D2max) {
-        pt_bucket_starts<<<dim3(bgrid), dim3(256), 0, stream>>>(a, nullptr, false, total1, p.n_buckets, bucket_starts);
+        const unsigned bgrid = (unsigned)std::min<uint64_t>(ceil_div((uint64_t)p.n_buckets + 1, 256), 8192);
+        pt_bucket_starts<<<dim3(bgrid), dim3(256), 0, stream>>>(a, total1, p.n_buckets, bucket_starts);
         return hipGetLastError();
     }
 
-    // pass 2: tmp -> out, every segment by its library's next D2 bits
+    // pass 2: tmp -> out, every tile of every segment by its library's next
+    // D2 bits, in place
     if ((e = launch_exclusive_scan(cb, cb, p.nseg, sscan, cb + p.nseg, stream)) != hipSuccess ||
-        (e = launch_exclusive_scan(eb, eb, p.nseg, sscan, eb + p.nseg, stream)) != hipSuccess)
+        (e = launch_exclusive_scan(tt, tt, p.nseg, sscan, tt + p.nseg, stream)) != hipSuccess)
         return e;
     a.keys_in = tmp;
-    if ((e = zero_bytes(hist, n2 * sizeof(uint32_t), stream)) != hipSuccess)
-        return e;
-    pt_hist<K, false><<<dim3((unsigned)grid2), block, 0, stream>>>(a, hist);
+    uint16_t *pt = reinterpret_cast<uint16_t *>(scratch + m.pt);
+    const uint64_t grid2 = ceil_div(p.cap, pt_chunk<K>()) + p.nseg;  // bound on pass-2 chunks
+    pt_tiles<K><<<dim3((unsigned)grid2), block, 0, stream>>>(a, pt, m.pw, static_cast<K *>(out));
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    if ((e = launch_exclusive_scan(hist, hist, n2, hist + n2, total1 + 1, stream)) != hipSuccess)
+    // transposed prefix tables and bucket sizes, then the sizes' exclusive
+    // scan: the first index of every bucket in (library, bucket) order and,
+    // in entry n_buckets, the number of keys
+    uint16_t *px = reinterpret_cast<uint16_t *>(scratch + m.px);
+    if (p.nseg) {
+        pt_transpose<<<dim3(p.nseg), dim3(TR_THREADS), 0, stream>>>(a, pt, m.pw, px, bucket_starts);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    if ((e = launch_exclusive_scan(bucket_starts, bucket_starts, p.n_buckets, scratch + m.bscan,
+                                   bucket_starts + p.n_buckets, stream)) != hipSuccess)
         return e;
-    pt_scatter<K, false><<<dim3((unsigned)grid2), block, 0, stream>>>(a, hist, static_cast<K *>(out));
-    if ((e = hipGetLastError()) != hipSuccess)
-        return e;
-    pt_bucket_starts<<<dim3(bgrid), dim3(256), 0, stream>>>(a, hist, true, total1, p.n_buckets, bucket_starts);
-    return hipGetLastError();
+    layout->tiled = 1;
+    layout->seg = seg;
+    layout->tt = tt;
+    layout->px = px;
+    layout->pw = m.pw;
+    layout->tile_keys = (uint32_t)pt_tile<K>();
+    return hipSuccess;
 }
 
 }  // namespace
@@ -631,18 +809,16 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
 uint64_t partition_chunk(int key_words) { return key_words == 2 ? pt_chunk<Key2>() : pt_chunk<uint64_t>(); }
 
 size_t partition_scratch_words(const PartPlan &p, int key_words) {
-    const uint64_t n1 = p.n_hist1;
-    const uint64_t grid2 = ceil_div(p.cap, partition_chunk(key_words)) + p.nseg;
-    const uint64_t n2 = grid2 << p.D2max;
-    const uint64_t H = std::max(n1 + scan_scratch_words(n1), n2 + scan_scratch_words(n2));
-    return H + 3 * ((uint64_t)p.nseg + 1) + scan_scratch_words(p.nseg) + 4 + (p.shard_count > 1 ? p.nseg + 2 : 0);
+    return key_words == 2 ? scratch_map(p, pt_tile<Key2>()).words : scratch_map(p, pt_tile<uint64_t>()).words;
 }
 
 hipError_t partition_keys(const PartPlan &p, int key_words, void *tmp, void *out, uint32_t *scratch,
-                          size_t scratch_words, uint32_t *lib_keys, uint32_t *bucket_starts, hipStream_t stream) {
+                          size_t scratch_words, uint32_t *lib_keys, uint32_t *bucket_starts, KeyLayout *layout,
+                          hipStream_t stream) {
     return key_words == 2
-               ? run_partition<Key2>(p, tmp, out, scratch, scratch_words, lib_keys, bucket_starts, stream)
-               : run_partition<uint64_t>(p, tmp, out, scratch, scratch_words, lib_keys, bucket_starts, stream);
+               ? run_partition<Key2>(p, tmp, out, scratch, scratch_words, lib_keys, bucket_starts, layout, stream)
+               : run_partition<uint64_t>(p, tmp, out, scratch, scratch_words, lib_keys, bucket_starts, layout,
+                                         stream);
 }
 
 }  // namespace tk

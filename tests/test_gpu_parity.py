@@ -388,6 +388,36 @@ def test_many_oversized_buckets(tk, oracle_lib, which, part_bits):
     assert r.n_fallback >= 8
 
 
+@pytest.mark.parametrize("which,scale,part_bits", [("large", 0.03, 11), ("long_k", 0.05, 12)])
+def test_oversized_buckets_in_tiles(tk, oracle_lib, which, scale, part_bits):
+    """With a second pass, a bucket is one piece per tile of its segment:
+    buckets too large for a workgroup are gathered piece by piece for the
+    fallback kernels, the others are loaded piece by piece by the bucket
+    kernel."""
+    lib = readsim.large_library(scale=scale) if which == "large" else readsim.long_k_library(scale=scale)
+    case(f"oversized buckets in tiles {lib.name} part_bits={part_bits} n_bases={lib.n_bases}")
+    r = check_against_oracle(tk, oracle_lib, lib.bases, lib.offsets, lib.k, lib.c, opts=dict(part_bits=part_bits))
+    assert r.part_bits > 10 and r.n_fallback >= 8
+
+
+@pytest.mark.parametrize("k", [31, 63])
+def test_segment_with_more_tiles_than_a_group_spans(tk, oracle_lib, k):
+    """One k-mer repeated millions of times fills one segment with more
+    second-pass tiles than a group may span: the small buckets of that
+    segment go through the fallback as well (gathered from the tiles), the
+    giant one too, and every count stays exact."""
+    rng = np.random.default_rng(404 + k)
+    n_same = 50_000 if k <= 31 else 40_000  # > 256 tiles of 16384 (8192) keys
+    reads = ["A" * 120] * n_same
+    # random reads: k-mers in the same segment (a leading run of A) and elsewhere
+    reads += ["A" * 6 + "".join("ACGT"[x] for x in rng.integers(0, 4, 114)) for _ in range(4000)]
+    reads += ["".join("ACGT"[x] for x in rng.integers(0, 4, 120)) for _ in range(4000)]
+    bases, offsets = readsim.from_strings(reads)
+    case(f"hot segment k={k} n_bases={bases.size}")
+    r = check_against_oracle(tk, oracle_lib, bases, offsets, k, 2, opts=dict(part_bits=13))
+    assert r.part_bits == 13 and r.n_fallback >= 2
+
+
 def test_bucket_capacity_edges(tk, oracle_lib):
     """One bucket (part_bits 0) of exactly the register capacity, one less
     and one more: 512 threads x 14 one-word keys = 7168, x 7 two-word keys =
