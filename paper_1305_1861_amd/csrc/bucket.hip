@@ -182,16 +182,18 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     __shared__ uint32_t s_acc[BK_WAVES][3];
     __shared__ uint32_t s_tot[1];
     // pieces of the next group of a tiled library (one per tile of its
-    // segment): s_pc[p] the group index of piece p's first key, s_dl[p] the
-    // key position of group index e in piece p minus e and the segment's
-    // start.  Row r (group indices 64 r .. 64 r + 63, one wave's load):
-    // s_row0[r] = piece of index 64 r | (pieces starting inside the row << 8),
-    // s_row1[r] = for one such piece, its number | (its first lane << 8).
+    // segment): s_pc[p] piece p's size, then the group index of its first
+    // key; s_lo[p] its first key's offset in its tile.  Row r (group indices
+    // 64 r .. 64 r + 63, one wave's load): s_rc[r] = pieces starting inside
+    // the row | (piece of index 64 r << 16); s_rd0[r] = that piece's key
+    // offset (key position of group index e: segment start + offset + e);
+    // s_rd1[r] = for a piece starting inside the row, its offset + PBIAS
+    // (24 bits) | (its first lane << 24).
     constexpr int ROWS = (CAP + WAVE - 1) / WAVE;
-    __shared__ uint16_t s_pc[BK_TILES_MAX + 1];
-    __shared__ uint32_t s_dl[BK_TILES_MAX];
-    __shared__ uint32_t s_row0[ROWS], s_row1[ROWS];
-    static_assert(BK_TILES_MAX <= 4 * WAVE, "piece numbers fit a byte, four pieces per lane of wave 0");
+    constexpr uint32_t PBIAS = 1u << 14;  // > any group index: biased offsets are positive
+    __shared__ uint16_t s_pc[BK_TILES_MAX], s_lo[BK_TILES_MAX];
+    __shared__ uint32_t s_rc[ROWS], s_rd0[ROWS], s_rd1[ROWS];
+    static_assert(BK_TILES_MAX <= 2 * WAVE, "two pieces per lane of wave 0");
 
     K *const s_ex = s_exs + 1;
     uint64_t *s_filter = reinterpret_cast<uint64_t *>(s_exs);
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     // element is assigned so that no value is carried from one group to the
     // next
     K key[ITEMS];
-    auto load_group = [&](uint64_t p, uint32_t n, int t) {
+    auto load_group = [&](uint64_t p, uint32_t n, int t) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             const uint32_t e = (uint32_t)i * BK_THREADS + t;
@@ -248,12 +250,11 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     // t < tiles reads tile t's prefix entries of the group's first digit and
     // of the digit after its last, (2) writes the piece's size and offset,
     // (3) after a barrier wave 0 turns the sizes into the group indices of
-    // the pieces and marks, for every row of 64 indices, the piece of its
-    // first index and the pieces starting inside it, (4) after another
-    // barrier every thread loads its keys: one piece or two per row, else a
-    // walk from the row's first piece.
+    // the pieces and fills the row records, (4) after another barrier every
+    // thread loads its keys: one LDS round trip for the rows of all its
+    // items, the rare rows with two or more piece starts walked afterwards.
     const uint32_t tile_keys = a.layout.tile_keys, pw = a.layout.pw;
-    auto piece_read = [&](const uint4 &gp, int t, uint32_t &lo, uint32_t &hi) {
+    auto piece_read = [&](const uint4 &gp, int t, uint32_t &lo, uint32_t &hi) __attribute__((always_inline)) {
         lo = hi = 0;
         if ((uint32_t)t < gp.y) {
             const uint16_t *col = a.layout.px + (uint64_t)gp.x * pw + (uint32_t)t;
@@ -261,63 +262,75 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             hi = col[((gp.w >> 16) + 1) * gp.y];
         }
     };
-    auto piece_write = [&](const uint4 &gp, int t, uint32_t lo, uint32_t hi) {
-        if ((uint32_t)t < gp.y)
-            s_dl[t] = (hi - lo) | (lo << 16);  // size, offset in the tile (both < 2^16)
-    };
-    auto piece_index = [&](const uint4 &gp, uint32_t ln) {  // wave 0
-        const uint32_t np = gp.y;  // <= BK_TILES_MAX = 4 * WAVE
-        uint32_t v[4], o[4], sum = 0;
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const uint32_t p = 4 * ln + (uint32_t)q;
-            const uint32_t w = p < np ? s_dl[p] : 0u;
-            v[q] = w & 0xFFFFu;
-            o[q] = w >> 16;
-            sum += v[q];
+    auto piece_write = [&](const uint4 &gp, int t, uint32_t lo, uint32_t hi) __attribute__((always_inline)) {
+        if ((uint32_t)t < gp.y) {
+            s_pc[t] = (uint16_t)(hi - lo);
+            s_lo[t] = (uint16_t)lo;
         }
-        uint32_t run = wave_inclusive_sum(sum) - sum;
-        for (uint32_t r = ln; r < (uint32_t)ROWS; r += WAVE)
-            s_row0[r] = 0;
+    };
+    auto piece_index = [&](const uint4 &gp, uint32_t ln) __attribute__((always_inline)) {  // wave 0
+        const uint32_t np = gp.y;  // <= BK_TILES_MAX = 2 * WAVE
+        uint32_t v[2], o[2];
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const uint32_t p = 4 * ln + (uint32_t)q;
+        for (int q = 0; q < 2; q++) {
+            const uint32_t p = 2 * ln + (uint32_t)q;
+            v[q] = p < np ? (uint32_t)s_pc[p] : 0u;
+            o[q] = p < np ? (uint32_t)s_lo[p] : 0u;
+        }
+        uint32_t run = wave_inclusive_sum(v[0] + v[1]) - v[0] - v[1];
+        for (uint32_t r = ln; r < (uint32_t)ROWS; r += WAVE)
+            s_rc[r] = 0;
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            const uint32_t p = 2 * ln + (uint32_t)q;
             if (p < np) {
                 s_pc[p] = (uint16_t)run;
-                s_dl[p] = p * tile_keys + o[q] - run;
                 if (v[q]) {
-                    // a piece starting inside a row is counted there; the
-                    // rows whose first index it holds name it
+                    const uint32_t dl = p * tile_keys + o[q] - run;
                     if (run & (WAVE - 1)) {
-                        atomicAdd(&s_row0[run / WAVE], 1u << 8);
-                        s_row1[run / WAVE] = p | ((run & (WAVE - 1)) << 8);
+                        atomicAdd(&s_rc[run / WAVE], 1u);
+                        s_rd1[run / WAVE] = ((dl + PBIAS) & 0xFFFFFFu) | ((run & (WAVE - 1)) << 24);
                     }
-                    for (uint32_t r = (run + WAVE - 1) / WAVE; r * WAVE < run + v[q]; r++)
-                        atomicOr(&s_row0[r], p);
+                    for (uint32_t r = (run + WAVE - 1) / WAVE; r * WAVE < run + v[q]; r++) {
+                        s_rd0[r] = dl;
+                        atomicOr(&s_rc[r], p << 16);
+                    }
                 }
             }
             run += v[q];
         }
     };
-    auto piece_load = [&](const uint4 &gp, uint32_t n, int t) {
+    auto piece_load = [&](const uint4 &gp, uint32_t n, int t) __attribute__((always_inline)) {
         const uint32_t np = gp.y, ln = (uint32_t)t % WAVE;
+        uint32_t dl[ITEMS];
+        uint32_t many = 0;  // bit i: two or more pieces start inside item i's row
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
-            const uint32_t e = (uint32_t)i * BK_THREADS + t;
-            key[i] = sentinel<K>();
-            if (e < n) {
-                const uint32_t r0 = s_row0[e / WAVE];
-                uint32_t p = r0 & 0xFFu;
-                if ((r0 >> 8) == 1) {
-                    const uint32_t r1 = s_row1[e / WAVE];
-                    if (ln >= (r1 >> 8))
-                        p = r1 & 0xFFu;
-                } else if (r0 >> 8) {
+            const uint32_t e = (uint32_t)i * BK_THREADS + (uint32_t)t;
+            const uint32_t r = min(e, n - 1) / WAVE;
+            const uint32_t rc = s_rc[r], d0 = s_rd0[r], d1 = s_rd1[r];
+            const uint32_t cnt = rc & 0xFFFFu;
+            dl[i] = (cnt == 1 && ln >= (d1 >> 24)) ? (d1 & 0xFFFFFFu) - PBIAS : d0;
+            many |= (uint32_t)(e < n && cnt > 1) << i;
+        }
+        if (many) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                if ((many >> i) & 1u) {
+                    const uint32_t e = (uint32_t)i * BK_THREADS + (uint32_t)t;
+                    uint32_t p = s_rc[e / WAVE] >> 16;
                     while (p + 1 < np && (uint32_t)s_pc[p + 1] <= e)
                         p++;
+                    dl[i] = p * tile_keys + s_lo[p] - s_pc[p];
                 }
-                key[i] = keys[(uint32_t)(gp.z + s_dl[p] + e)];
             }
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint32_t e = (uint32_t)i * BK_THREADS + (uint32_t)t;
+            key[i] = sentinel<K>();
+            if (e < n)
+                key[i] = keys[(uint32_t)(gp.z + dl[i] + e)];
         }
     };
     for (;;) {

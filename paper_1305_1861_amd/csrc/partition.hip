@@ -60,6 +60,14 @@ template <typename K>
 constexpr uint64_t pt_chunk() {
     return pt_tile<K>() * PT_CH;
 }
+// Pass-2 tiles hold PT2_ROUNDS pass-1 tiles' worth of keys, staged through
+// the same LDS buffer in that many rounds: fewer, larger pieces per bucket.
+constexpr int PT2_ROUNDS = 2;
+template <typename K>
+constexpr uint64_t pt2_tile() {
+    return pt_tile<K>() * PT2_ROUNDS;
+}
+static_assert(PT_CH % PT2_ROUNDS == 0, "a pass-2 chunk holds whole tiles");
 
 
 // Largest i in [0, n) with at(i) <= v, for a non-decreasing at(); 0 if none.
@@ -135,7 +143,7 @@ __device__ __forceinline__ bool chunk_of(const PassArgs &a, Chunk &ch) {
     ch.shift = 2 * a.libs[j].k - a.libs[j].D;
     ch.bits = a.libs[j].D2;
     ch.k = a.libs[j].k;
-    ch.tile = a.tt[s] + i * PT_CH;
+    ch.tile = a.tt[s] + i * (PT_CH / PT2_ROUNDS);
     return true;
 }
 
@@ -409,20 +417,23 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint3
     }
 }
 
-// Pass 2: every tile of a segment (up to PT_CH per workgroup) ordered by its
-// library's next D2 bits in place; pt[t * pw + d] receives the first
-// position of digit d in tile t, entries past the last digit the tile's
-// size.  A tile holds at most 2^14 keys, so the entries fit 16 bits.
+// Pass 2: every tile of a segment (up to PT_CH / PT2_ROUNDS per workgroup)
+// ordered by its library's next D2 bits in place; pt[t * pw + d] receives
+// the first position of digit d in tile t, entries past the last digit the
+// tile's size.  A tile holds at most 2^15 keys, so the entries fit 16 bits.
+// The keys stay in registers while the tile's digit order is staged in LDS
+// and written out, PtItems keys per thread and round.
 template <typename K>
 __global__ __launch_bounds__(PT_THREADS) void pt_tiles(PassArgs a, uint16_t *__restrict__ pt, uint32_t pw,
                                                        K *__restrict__ out) {
-    constexpr int ITEMS = PtItems<K>::value;
+    constexpr int STAGE = PT_THREADS * PtItems<K>::value;  // keys staged per round
+    constexpr int ITEMS = PtItems<K>::value * PT2_ROUNDS;
     constexpr int TILE = PT_THREADS * ITEMS;
     static_assert(TILE <= 65535, "prefix entries are 16 bits");
     static_assert(TILE < (1 << (32 - PT_MAX_BITS)), "(rank, digit) fits a word");
     __shared__ uint32_t s_cnt[PT_MAX_BINS];  // digit counts of the tile, then their starts
     __shared__ uint32_t s_wt[PT_WAVES];
-    __shared__ K s_stage[TILE];
+    __shared__ K s_stage[STAGE];
     const int tid = threadIdx.x;
     const int wave = tid / WAVE;
     const uint32_t lane = lane_id();
@@ -449,7 +460,7 @@ __global__ __launch_bounds__(PT_THREADS) void pt_tiles(PassArgs a, uint16_t *__r
             if (e < n_tile)
                 key[i] = in[t0 + e];
         }
-        uint32_t rd[ITEMS];  // (rank << 10) | digit; ~0 for no key
+        uint32_t rd[ITEMS];  // (rank << 10) | digit, then the slot; ~0 for no key
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             rd[i] = ~0u;
@@ -490,11 +501,24 @@ __global__ __launch_bounds__(PT_THREADS) void pt_tiles(PassArgs a, uint16_t *__r
 #pragma unroll
         for (int i = 0; i < ITEMS; i++)
             if (rd[i] != ~0u)
-                s_stage[s_cnt[rd[i] & (PT_MAX_BINS - 1)] + (rd[i] >> PT_MAX_BITS)] = key[i];
-        __syncthreads();
-        // the tile back to its own positions, now in digit order
-        for (uint32_t j = tid; j < n_tile; j += PT_THREADS)
-            out[t0 + j] = s_stage[j];
+                rd[i] = s_cnt[rd[i] & (PT_MAX_BINS - 1)] + (rd[i] >> PT_MAX_BITS);
+        // the tile back to its own positions in digit order, one stage of
+        // slots per round
+#pragma unroll
+        for (int r = 0; r < PT2_ROUNDS; r++) {
+            const uint32_t lo = (uint32_t)r * STAGE;
+            if (lo >= n_tile)
+                break;  // uniform
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++)
+                if (rd[i] - lo < (uint32_t)STAGE)  // false for ~0 (no key): lo + STAGE <= 2^16
+                    s_stage[rd[i] - lo] = key[i];
+            __syncthreads();
+            const uint32_t n = min((uint32_t)STAGE, n_tile - lo);
+            for (uint32_t j = tid; j < n; j += PT_THREADS)
+                out[t0 + lo + j] = s_stage[j];
+            __syncthreads();
+        }
 #pragma unroll
         for (int j = 0; j < PT_BPT; j++)
             s_cnt[d0 + j] = 0;
@@ -593,7 +617,7 @@ __global__ __launch_bounds__(SEG_THREADS) void pt_segments(PassArgs a, const uin
         if (s < a.nseg) {
             const uint32_t end = segment_start(a, scan1, n_hist1, total1, s + 1);
             chs[s] = (uint32_t)(((uint64_t)(end - start) + pt_chunk<K>() - 1) / pt_chunk<K>());
-            tiles[s] = (uint32_t)(((uint64_t)(end - start) + pt_tile<K>() - 1) / pt_tile<K>());
+            tiles[s] = (uint32_t)(((uint64_t)(end - start) + pt2_tile<K>() - 1) / pt2_tile<K>());
         }
     }
     // first key of every library: the start of its first segment
@@ -711,7 +735,7 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
                          uint32_t *lib_keys, uint32_t *bucket_starts, KeyLayout *layout, hipStream_t stream) {
     if (p.D2max < 0 || p.D2max > PT_MAX_BITS)
         return hipErrorInvalidValue;
-    const ScratchMap m = scratch_map(p, pt_tile<K>());
+    const ScratchMap m = scratch_map(p, pt2_tile<K>());
     const bool shard = p.shard_count > 1;
     if (m.words > scratch_words || (shard && (p.n_libs != 1 || p.nseg > SH_THREADS)))
         return hipErrorInvalidValue;
@@ -800,7 +824,7 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
     layout->tt = tt;
     layout->px = px;
     layout->pw = m.pw;
-    layout->tile_keys = (uint32_t)pt_tile<K>();
+    layout->tile_keys = (uint32_t)pt2_tile<K>();
     return hipSuccess;
 }
 
@@ -809,7 +833,7 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
 uint64_t partition_chunk(int key_words) { return key_words == 2 ? pt_chunk<Key2>() : pt_chunk<uint64_t>(); }
 
 size_t partition_scratch_words(const PartPlan &p, int key_words) {
-    return key_words == 2 ? scratch_map(p, pt_tile<Key2>()).words : scratch_map(p, pt_tile<uint64_t>()).words;
+    return key_words == 2 ? scratch_map(p, pt2_tile<Key2>()).words : scratch_map(p, pt2_tile<uint64_t>()).words;
 }
 
 hipError_t partition_keys(const PartPlan &p, int key_words, void *tmp, void *out, uint32_t *scratch,

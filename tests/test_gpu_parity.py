@@ -407,7 +407,7 @@ def test_segment_with_more_tiles_than_a_group_spans(tk, oracle_lib, k):
     segment go through the fallback as well (gathered from the tiles), the
     giant one too, and every count stays exact."""
     rng = np.random.default_rng(404 + k)
-    n_same = 50_000 if k <= 31 else 40_000  # > 256 tiles of 16384 (8192) keys
+    n_same = 50_000 if k <= 31 else 40_000  # > 128 tiles of 32768 (16384) keys
     reads = ["A" * 120] * n_same
     # random reads: k-mers in the same segment (a leading run of A) and elsewhere
     reads += ["A" * 6 + "".join("ACGT"[x] for x in rng.integers(0, 4, 114)) for _ in range(4000)]
