@@ -158,7 +158,8 @@ typedef struct {
  * of every k-mer to the one consumer that owns its filter (§2.1,
  * parallelization), with key ranges as owners.  Every window is extracted,
  * and the first partition pass counts the library's top-digit histogram
- * (top D1 = min(D, 10) bits of the canonical key).  Digit d goes to shard
+ * (the top D1 bits of the canonical key: D1 = D for D <= 10, else D - 10,
+ * the second pass taking the other 10).  Digit d goes to shard
  * min(G - 1, floor(G * (below(d) + n(d) / 2) / M)), where n(d) is its
  * window count, below(d) that of the digits before it, and M the library's
  * window count.  The owners are contiguous and the shares even to within one

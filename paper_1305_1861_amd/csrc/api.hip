@@ -285,7 +285,11 @@ tk_status make_plan(const LibSpec *ls, uint64_t n_libs, uint64_t n_bases, uint64
             L.c = ls[j].c;
             L.k = ls[j].k;
             L.D = part_bits_for(L.pos1 - L.pos0, ls[j].n_reads, L.k, p->opts);
-            L.D1 = std::min(L.D, 10);
+            // the second pass orders its tiles in place, so its digit count
+            // does not shape its writes: it takes 10 bits, and the first
+            // pass (whose digit runs are shorter the more digits it has)
+            // only the rest
+            L.D1 = L.D > 10 ? L.D - 10 : L.D;
             L.D2 = L.D - L.D1;
             L.nch1 = L.pos1 > L.pos0 ? (uint32_t)ceil_div(L.pos1 - (L.pos0 & ~31ull), chunk) : 0u;
             L.cb1 = (uint32_t)n_ch;
@@ -311,7 +315,12 @@ tk_status make_plan(const LibSpec *ls, uint64_t n_libs, uint64_t n_bases, uint64
         p->part.cap = p->cap;
         p->part.shard_count = p->opts.shard_count;
         p->part.shard_index = p->opts.shard_index;
+        // fallback list: buckets larger than a group, and every bucket of a
+        // segment with more second-pass tiles than a group may span (more
+        // than BK_TILES_MAX tiles of keys each)
         p->fb_cap = p->cap / ((uint64_t)bucket_capacity(p->key_words, p->opts.tile) + 1) + 1;
+        if (d2max)
+            p->fb_cap += (p->cap / (BK_TILES_MAX * partition_tile2(p->key_words)) + 1) << d2max;
         p->fb_nb_max = p->screen ? ceil_div((uint64_t)p->opts.beta * std::max<uint64_t>(p->cap, 1), 256) + p->fb_cap : 0;
         p->part.n_buckets = (uint32_t)n_bk;
         p->part_words = partition_scratch_words(p->part, p->key_words);

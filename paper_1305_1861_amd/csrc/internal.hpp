@@ -80,6 +80,7 @@ hipError_t launch_pack(const uint8_t *bases, const uint64_t *offsets, uint64_t n
 // library: chunk i of library j covers window positions
 // [floor32(pos0) + i * chunk, ...) inside [pos0, pos1).
 uint64_t partition_chunk(int key_words);  // window positions (pass 1) or keys (pass 2) per chunk
+uint64_t partition_tile2(int key_words);  // keys per second-pass tile
 struct PartPlan {
     const uint64_t *packed;
     const uint32_t *valid;

@@ -650,48 +650,51 @@ __global__ __launch_bounds__(256) void pt_bucket_starts(PassArgs a, const uint32
 // for the segment's T tiles, so that one digit's entries over all tiles are
 // contiguous), and the size of every bucket (into sizes[b], b = bucket0 of
 // its library + its top D bits): digit d2 of its segment summed over the
-// segment's tiles, the difference of two row sums.  One workgroup per
-// segment, blocks of 64 tiles x 64 digits through LDS.
+// segment's tiles.  One workgroup per segment and block of 64 digits (the
+// block's sums need the entries of the digit after it too), 64 tiles at a
+// time through LDS.
 constexpr int TR_THREADS = 256;
 constexpr int TR_B = 64;
 __global__ __launch_bounds__(TR_THREADS) void pt_transpose(PassArgs a, const uint16_t *__restrict__ pt, uint32_t pw,
                                                            uint16_t *__restrict__ px, uint32_t *__restrict__ sizes) {
-    __shared__ uint16_t s_b[TR_B][TR_B + 2];
-    __shared__ uint32_t s_rs[PT_MAX_BINS + 1];
-    const uint32_t s = blockIdx.x;
+    __shared__ uint16_t s_b[TR_B][TR_B + 2];  // 64 tiles x 65 digits
+    __shared__ uint32_t s_rs[TR_B + 1];
+    const uint32_t s = blockIdx.x, dd = blockIdx.y * TR_B;
     if (s >= a.nseg)
         return;
     const int tid = threadIdx.x;
     const uint32_t j = last_le(a.n_libs, s, [&](uint32_t i) { return (uint64_t)a.libs[i].seg0; });
     const LibDesc &L = a.libs[j];
-    const uint32_t bins = 1u << L.D2, nd = bins + 1;
+    const uint32_t bins = 1u << L.D2, nd = bins + 1;  // prefix entries of a tile: digits 0 .. bins
+    if (dd >= bins)
+        return;  // uniform
     const uint32_t t0 = a.tt[s], T = a.tt[s + 1] - t0;
     uint16_t *const out = px + (uint64_t)t0 * pw;
-    for (uint32_t dd = 0; dd < nd; dd += TR_B) {
-        uint32_t acc = 0;  // row sum of digit dd + tid (tid < TR_B)
-        for (uint32_t tb = 0; tb < T; tb += TR_B) {
-            for (int x = tid; x < TR_B * TR_B; x += TR_THREADS) {
-                const uint32_t ti = (uint32_t)x / TR_B, di = (uint32_t)x % TR_B;
-                s_b[ti][di] = (tb + ti < T && dd + di < nd) ? pt[(uint64_t)(t0 + tb + ti) * pw + dd + di] : 0;
-            }
-            __syncthreads();
-            for (int x = tid; x < TR_B * TR_B; x += TR_THREADS) {
-                const uint32_t di = (uint32_t)x / TR_B, ti = (uint32_t)x % TR_B;
-                if (tb + ti < T && dd + di < nd)
-                    out[(uint64_t)(dd + di) * T + tb + ti] = s_b[ti][di];
-            }
-            if (tid < TR_B)
-                for (int ti = 0; ti < TR_B; ti++)
-                    acc += s_b[ti][tid];
-            __syncthreads();
+    uint32_t acc = 0;  // sum over the segment's tiles of digit dd + tid's entry (tid <= TR_B)
+    for (uint32_t tb = 0; tb < T; tb += TR_B) {
+        for (int x = tid; x < TR_B * (TR_B + 1); x += TR_THREADS) {
+            const uint32_t ti = (uint32_t)x / (TR_B + 1), di = (uint32_t)x % (TR_B + 1);
+            s_b[ti][di] = (tb + ti < T && dd + di < nd) ? pt[(uint64_t)(t0 + tb + ti) * pw + dd + di] : 0;
         }
-        if (tid < TR_B && dd + tid < nd)
-            s_rs[dd + tid] = acc;
+        __syncthreads();
+        // rows dd .. dd + 63, and the last block also row `bins` (the
+        // tiles' sizes)
+        for (int x = tid; x < TR_B * (TR_B + 1); x += TR_THREADS) {
+            const uint32_t di = (uint32_t)x / TR_B, ti = (uint32_t)x % TR_B;
+            if (tb + ti < T && dd + di < nd && (di < TR_B || dd + di == bins))
+                out[(uint64_t)(dd + di) * T + tb + ti] = s_b[ti][di];
+        }
+        if (tid <= TR_B)
+            for (int ti = 0; ti < TR_B; ti++)
+                acc += s_b[ti][tid];
+        __syncthreads();
     }
+    if (tid <= TR_B)
+        s_rs[tid] = acc;
     __syncthreads();
     const uint32_t b0 = L.bucket0 + ((s - L.seg0) << L.D2);
-    for (uint32_t d = tid; d < bins; d += TR_THREADS)
-        sizes[b0 + d] = s_rs[d + 1] - s_rs[d];
+    if (tid < TR_B && dd + tid < bins)
+        sizes[b0 + dd + tid] = s_rs[tid + 1] - s_rs[tid];
 }
 
 // Scratch words of the partition, in order: pass-1 counts and their scan
@@ -812,7 +815,8 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
     // in entry n_buckets, the number of keys
     uint16_t *px = reinterpret_cast<uint16_t *>(scratch + m.px);
     if (p.nseg) {
-        pt_transpose<<<dim3(p.nseg), dim3(TR_THREADS), 0, stream>>>(a, pt, m.pw, px, bucket_starts);
+        const unsigned dblocks = (unsigned)ceil_div(1ull << p.D2max, TR_B);
+        pt_transpose<<<dim3(p.nseg, dblocks), dim3(TR_THREADS), 0, stream>>>(a, pt, m.pw, px, bucket_starts);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
@@ -831,6 +835,7 @@ hipError_t run_partition(const PartPlan &p, void *tmp, void *out, uint32_t *scra
 }  // namespace
 
 uint64_t partition_chunk(int key_words) { return key_words == 2 ? pt_chunk<Key2>() : pt_chunk<uint64_t>(); }
+uint64_t partition_tile2(int key_words) { return key_words == 2 ? pt2_tile<Key2>() : pt2_tile<uint64_t>(); }
 
 size_t partition_scratch_words(const PartPlan &p, int key_words) {
     return key_words == 2 ? scratch_map(p, pt2_tile<Key2>()).words : scratch_map(p, pt2_tile<uint64_t>()).words;

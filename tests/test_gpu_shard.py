@@ -39,11 +39,17 @@ def run(tk, bases, offsets, k, c, opts):
     return keys, counts, r
 
 
+def first_pass_bits(D):
+    """Bits of the first partition pass: all D up to 10, else D - 10 (the
+    second pass takes 10)."""
+    return D - 10 if D > 10 else D
+
+
 def expected_owners(oracle_lib, bases, offsets, k, D, G):
-    """Pass-1 digit (top min(D, 10) bits of the canonical key) of every
-    window, from the oracle's counts at c = 1, and the owner of each digit:
-    min(G - 1, floor(G * (below + n / 2) / M))."""
-    D1 = min(D, 10)
+    """Pass-1 digit (top first_pass_bits(D) bits of the canonical key) of
+    every window, from the oracle's counts at c = 1, and the owner of each
+    digit: min(G - 1, floor(G * (below + n / 2) / M))."""
+    D1 = first_pass_bits(D)
     allk = oracle_lib.kmer_count(bases, offsets, k, 1)
     if k <= 31:
         dig = (allk.lo >> np.uint64(2 * k - D1)) if D1 else np.zeros(allk.lo.size, np.uint64)
@@ -81,7 +87,7 @@ def check_shards(tk, oracle_lib, bases, offsets, k, c, G, part_bits=-1):
     # every shard holds exactly its digits' keys and windows
     D = full.part_bits
     _, owner, n = expected_owners(oracle_lib, bases, offsets, k, D, G)
-    D1 = min(D, 10)
+    D1 = first_pass_bits(D)
     for g, (pk, _, pr) in enumerate(parts):
         assert pr.n_windows == int(n[owner == g].sum()), (g, pr.n_windows)
         if pk.shape[0] and D1:
