@@ -22,10 +22,12 @@
 // Pass-1 work unit: a chunk of up to PT_CH tiles, one workgroup each; chunks
 // never straddle a library.  hist counts the chunk's digits; the counts are
 // laid out (library, digit, chunk) so that one exclusive scan gives every
-// (chunk, digit) its write position.  scatter, per tile: rank every key
-// within its digit (LDS atomics), stage the tile in LDS in digit order, write
-// each digit's run contiguously at its cursor.  Pass 2 takes chunks of up to
-// PT_CH tiles of one segment and writes every tile back in digit order.
+// (chunk, digit) its write position.  scatter, per tile: rank every window
+// within its digit (LDS atomics), stage the tile's window positions in LDS in
+// digit order, rebuild each key from the tile's packed words as its digit's
+// run is written contiguously at its cursor.  Pass 2 takes chunks of up to
+// PT_CH / PT2_ROUNDS tiles of one segment and writes every tile back in digit
+// order.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -319,15 +321,29 @@ __global__ __launch_bounds__(PT_THREADS) void pt_hist(PassArgs a, uint32_t *__re
 }
 
 // Pass 1: keys of every chunk to their (library, digit, chunk) places.
+// Per tile: every window's digit from its first and last five bases (as in
+// pt_hist; k < 5: from the whole key), ranked within its digit by LDS
+// atomics; the tile's window positions (2 bytes each, not the 8- or 16-byte
+// keys) staged in digit order; then each staged window's key rebuilt from
+// the tile's packed words, kept in LDS, and written to its digit's run.
+// Staging positions instead of keys keeps the workgroup small enough for
+// two to share a CU, so one's loads and barriers overlap the other's work.
 template <typename K>
-__global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint32_t *__restrict__ offs,
-                                                         K *__restrict__ out) {
+__global__ __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void pt_scatter(PassArgs a, const uint32_t *__restrict__ offs,
+                                                            K *__restrict__ out) {
     constexpr int ITEMS = PtItems<K>::value;
-    constexpr int TILE = PT_THREADS * ITEMS;
-    __shared__ uint32_t s_cnt[PT_MAX_BINS];  // digit counts of the tile, then their starts
-    __shared__ uint32_t s_cur[PT_MAX_BINS];  // write position of each digit
+    constexpr int TILE = PT_THREADS * ITEMS;  // window positions per tile
+    constexpr int PER_WORD = 32 / ITEMS;      // threads per packed word
+    constexpr int WORDS = TILE / 32;
+    constexpr int BACK = std::is_same<K, Key2>::value ? 2 : 1;  // words before the tile a key may reach into
+    constexpr uint32_t SPARE = PT_MAX_BINS;   // counter of the windows that are not kept
+    static_assert(TILE <= 65536, "positions are 16 bits");
+    __shared__ uint32_t s_cnt[PT_MAX_BINS + 1];   // digit counts of the tile
+    __shared__ uint32_t s_start[PT_MAX_BINS];     // first slot of every digit
+    __shared__ uint32_t s_base[PT_MAX_BINS];      // output position minus slot, per digit
     __shared__ uint32_t s_wt[PT_WAVES];
-    __shared__ K s_stage[TILE];
+    __shared__ uint64_t s_words[2][BACK + WORDS];  // the tile's packed words (two tiles in turn)
+    __shared__ uint16_t s_idx[TILE];               // window positions in digit order
     const int tid = threadIdx.x;
     const int wave = tid / WAVE;
     const uint32_t lane = lane_id();
@@ -335,48 +351,80 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint3
     if (!chunk_of<K, true>(a, ch))
         return;  // uniform over the block
     const uint32_t bins = 1u << ch.bits, mask = bins - 1;
+    static_assert(PT_BPT == 1, "one digit per thread");
     // a shard keeps the keys of its digits only (one library)
     uint32_t own_lo = 0, own_hi = bins;
     if (a.own) {
         own_lo = a.own[0];
         own_hi = a.own[1];
     }
-    // thread t owns digits t * PT_BPT .. t * PT_BPT + PT_BPT - 1
-    const uint32_t d0 = (uint32_t)tid * PT_BPT;
-#pragma unroll
-    for (int j = 0; j < PT_BPT; j++) {
-        if (d0 + j < bins)
-            s_cur[d0 + j] = offs[ch.hidx + (uint64_t)(d0 + j) * ch.hstride];
-        s_cnt[d0 + j] = 0;
-    }
+    // thread t owns digit t: its write position stays in a register
+    uint32_t cur = (uint32_t)tid < bins ? offs[ch.hidx + (uint64_t)tid * ch.hstride] : 0u;
+    s_cnt[tid] = 0;
+    if (tid == 0)
+        s_cnt[SPARE] = 0;
     __syncthreads();
-    for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += TILE) {
-        K key[ITEMS];
-        uint32_t vm = load_tile<K, true>(a, t0, min(t0 + (uint64_t)TILE, ch.c1), ch.lo, ch.k, key);
-        uint32_t rd[ITEMS];  // (rank << 10) | digit
+    uint32_t par = 0;
+    for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += pt_tile<K>(), par ^= 1u) {
+        // (the thread index passes through an empty asm each tile, so that
+        // the compiler recomputes the per-lane shifts rather than keeping
+        // them across the loop, where they would not fit the registers)
+        int tix = tid;
+        asm volatile("" : "+v"(tix));
+        const int first = (tix % PER_WORD) * ITEMS;  // this thread's first window in its word
+        const RawWin r = fetch_win<K>(a, t0, min(t0 + pt_tile<K>(), ch.c1), ch.lo);
+        uint64_t *const words = s_words[par];
+        // every thread that loaded its word stores it (a window's bases lie in
+        // words that hold some window of [lo, t1)); thread 0 also the words
+        // before the tile
+        if (r.okmask) {
+            words[BACK + tix / PER_WORD] = r.w0;
+            if (tix == 0) {
+                words[BACK - 1] = r.w1;
+                if (BACK == 2)
+                    words[0] = r.w2;
+            }
+        }
+        // digits, ranked; windows not kept count in the spare bin so that
+        // the atomics issue without a branch per item
+        const uint32_t ok = r.okmask ? (r.vword >> first) & r.okmask : 0u;
+        uint32_t rd[ITEMS];  // (rank << 11) | digit (SPARE: not kept)
+        auto rank = [&](int i, uint32_t dg) __attribute__((always_inline)) {
+            const bool keep = ((ok >> i) & 1u) && dg >= own_lo && dg < own_hi;
+            const uint32_t d = keep ? dg : SPARE;
+            rd[i] = (atomicAdd(&s_cnt[d], 1u) << (PT_MAX_BITS + 1)) | d;
+        };
+        if (ch.k >= 5) {
+            // the canonical key's top 10 bits are the smaller of the forward
+            // code's first five bases and the reverse complement's
+            const uint64_t last5 = ~group_reverse(codes_ending_at(r, first + ITEMS - 1));
+            const uint64_t first5 = codes_ending_at(r, first + ITEMS + 4 - ch.k);
+            const int drop = 10 - ch.bits;
 #pragma unroll
-        for (int i = 0; i < ITEMS; i++) {
-            rd[i] = 0;
-            if ((vm >> i) & 1u) {
-                const uint32_t d = digit_of(key[i], ch.shift, mask);
-                if (d >= own_lo && d < own_hi)
-                    rd[i] = (atomicAdd(&s_cnt[d], 1u) << PT_MAX_BITS) | d;
-                else
-                    vm &= ~(1u << i);
+            for (int i = 0; i < ITEMS; i++) {
+                const uint32_t f = (uint32_t)(first5 >> (2 * (ITEMS - 1 - i))) & 0x3FFu;
+                const uint32_t b = (uint32_t)(last5 >> (56 - 2 * ITEMS + 2 * i)) & 0x3FFu;
+                rank(i, min(f, b) >> drop);
+            }
+        } else {
+            typename KeyOf<std::is_same<K, Key2>::value>::Roll rl;
+            rl.init(r.w0, r.w1, r.w2, (uint32_t)first, ch.k);
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                if (i)
+                    rl.step((uint32_t)(r.w0 >> (62 - 2 * (first + i))) & 3u);
+                rank(i, digit_of(rl.key(), ch.shift, mask));
             }
         }
         __syncthreads();
         // starts of the digits in the tile
-        uint32_t c[PT_BPT];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int j = 0; j < PT_BPT; j++) {
-            c[j] = s_cnt[d0 + j];
-            sum += c[j];
-        }
-        const uint32_t inc = wave_inclusive_sum(sum);
+        const uint32_t c = s_cnt[tid];
+        const uint32_t inc = wave_inclusive_sum(c);
         if (lane == WAVE - 1)
             s_wt[wave] = inc;
+        s_cnt[tid] = 0;  // read by its owner only until the next tile's atomics
+        if (tid == 0)
+            s_cnt[SPARE] = 0;
         __syncthreads();
         uint32_t before = 0, n_tile = 0;
 #pragma unroll
@@ -385,35 +433,33 @@ __global__ __launch_bounds__(PT_THREADS) void pt_scatter(PassArgs a, const uint3
             before += w < wave ? t : 0u;
             n_tile += t;
         }
-        uint32_t run = before + inc - sum;
-#pragma unroll
-        for (int j = 0; j < PT_BPT; j++) {
-            s_cnt[d0 + j] = run;
-            run += c[j];
-        }
+        const uint32_t start = before + inc - c;
+        s_start[tid] = start;
+        s_base[tid] = cur - start;
+        cur += c;
         __syncthreads();
+        const uint32_t pos0 = (uint32_t)(tix / PER_WORD) * 32 + (uint32_t)first;
 #pragma unroll
-        for (int i = 0; i < ITEMS; i++)
-            if ((vm >> i) & 1u)
-                s_stage[s_cnt[rd[i] & (PT_MAX_BINS - 1)] + (rd[i] >> PT_MAX_BITS)] = key[i];
+        for (int i = 0; i < ITEMS; i++) {
+            const uint32_t d = rd[i] & (2 * PT_MAX_BINS - 1);
+            if (d != SPARE)
+                s_idx[s_start[d] + (rd[i] >> (PT_MAX_BITS + 1))] = (uint16_t)(pos0 + i);
+        }
         __syncthreads();
         // each digit's run goes to its cursor; consecutive threads write
         // consecutive positions of a run
         for (uint32_t j = tid; j < n_tile; j += PT_THREADS) {
-            const K x = s_stage[j];
-            const uint32_t d = digit_of(x, ch.shift, mask);
-            const uint64_t o = (uint64_t)s_cur[d] + (j - s_cnt[d]);
+            const uint32_t p = s_idx[j];
+            const uint32_t w = BACK + p / 32, u = p % 32;
+            K x;
+            if constexpr (std::is_same<K, Key2>::value)
+                x = window_key2(words[w], words[w - 1], words[w - 2], u, ch.k);
+            else
+                x = window_key1(words[w], words[w - 1], u, ch.k);
+            const uint64_t o = (uint32_t)(s_base[digit_of(x, ch.shift, mask)] + j);
             if (o < a.cap)  // holds whenever the counts match the keys
                 out[o] = x;
         }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < PT_BPT; j++) {
-            if (d0 + j < bins)
-                s_cur[d0 + j] += c[j];
-            s_cnt[d0 + j] = 0;
-        }
-        __syncthreads();
     }
 }
 
