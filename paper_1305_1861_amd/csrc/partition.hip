@@ -6,8 +6,8 @@
 // sort-and-compact results concatenate into each library's sorted answer.
 //
 // Pass 1 extracts the canonical keys straight from the packed reads (§2.1,
-// k-mer extraction) and orders them by (library, top D1 = min(D, 10) bits):
-// the "segments", each one contiguous range.  Pass 2 (run when some library
+// k-mer extraction) and orders them by (library, top D1 bits), D1 = D - 10
+// for D > 10 and D otherwise: the "segments", each one contiguous range.  Pass 2 (run when some library
 // has D2 = D - D1 > 0) cuts every segment into tiles of PtItems * PT_THREADS
 // keys and orders each tile by the next D2 bits in place, recording for
 // every tile the first position of every digit (a prefix table of 16-bit
@@ -149,14 +149,11 @@ __device__ __forceinline__ bool chunk_of(const PassArgs &a, Chunk &ch) {
     return true;
 }
 
-// Keys of one tile into registers.  Pass 1: the tile is PT_TILE window
-// positions starting at a word boundary; thread t takes ITEMS consecutive
-// windows of one packed word; positions outside [lo, t1) are skipped.
-// Pass 2: keys [t0, t1) of the pass-1 output, item-major.  Bit i of the
-// result: item i holds a key.
-// Pass 1 in two steps, so that the loads of the next tile can be in flight
-// while this one is processed: fetch_win issues the loads of one thread's
-// packed words and validity bits, extract_win rolls the keys out of them.
+// Pass-1 tiles: pt_tile window positions starting at a word boundary;
+// thread t takes ITEMS consecutive windows of one packed word, and positions
+// outside [lo, t1) are skipped.  fetch_win issues the loads of one thread's
+// packed words and validity bits, so that the next tile's loads can be in
+// flight while the current tile is processed.
 struct RawWin {
     uint64_t w0, w1, w2;  // packed words w, w - 1, w - 2 (0 before the first)
     uint32_t vword;       // valid[w]
@@ -187,34 +184,6 @@ __device__ __forceinline__ RawWin fetch_win(const PassArgs &a, uint64_t t0, uint
     return r;
 }
 
-template <typename K>
-__device__ __forceinline__ uint32_t extract_win(const RawWin &r, int k, K (&key)[PtItems<K>::value]) {
-    constexpr int ITEMS = PtItems<K>::value;
-    constexpr int PER_WORD = 32 / ITEMS;
-    const uint32_t first = (uint32_t)(threadIdx.x % PER_WORD) * ITEMS;
-    uint32_t vm = 0;
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++)
-        key[i] = K{};
-    if (r.okmask) {
-        const uint32_t ok = (r.vword >> first) & r.okmask;
-        // consecutive windows: the first extracted whole, the others
-        // rolled on by one base each
-        typename KeyOf<std::is_same<K, Key2>::value>::Roll rl;
-        rl.init(r.w0, r.w1, r.w2, first, k);
-#pragma unroll
-        for (int i = 0; i < ITEMS; i++) {
-            if (i)
-                rl.step((uint32_t)(r.w0 >> (62 - 2 * (first + i))) & 3u);
-            if ((ok >> i) & 1u) {
-                key[i] = rl.key();
-                vm |= 1u << i;
-            }
-        }
-    }
-    return vm;
-}
-
 // Two-bit codes of the 32 bases ending at base 32w + u (that base in bits
 // 1..0), -64 <= u <= 31, from the packed words w, w - 1 and w - 2 held in
 // r; bases before word w - 2 read as 0.
@@ -232,27 +201,6 @@ __device__ __forceinline__ uint64_t codes_ending_at(const RawWin &r, int u) {
     }
     const uint32_t s = 62 - 2 * u;
     return s ? (a >> s) | (b << (64 - s)) : a;
-}
-
-template <typename K, bool FROM_WIN>
-__device__ __forceinline__ uint32_t load_tile(const PassArgs &a, uint64_t t0, uint64_t t1, uint64_t lo, int k,
-                                              K (&key)[PtItems<K>::value]) {
-    constexpr int ITEMS = PtItems<K>::value;
-    if (FROM_WIN)
-        return extract_win<K>(fetch_win<K>(a, t0, t1, lo), k, key);
-    const int tid = threadIdx.x;
-    uint32_t vm = 0;
-    const K *__restrict__ in = static_cast<const K *>(a.keys_in);
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-        key[i] = K{};
-        const uint64_t e = t0 + (uint64_t)i * PT_THREADS + tid;
-        if (e < t1) {
-            key[i] = in[e];
-            vm |= 1u << i;
-        }
-    }
-    return vm;
 }
 
 // Pass 1: digit counts of every chunk.
