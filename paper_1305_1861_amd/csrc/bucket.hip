@@ -184,15 +184,16 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     // pieces of the next group of a tiled library (one per tile of its
     // segment): s_pc[p] piece p's size, then the group index of its first
     // key; s_lo[p] its first key's offset in its tile.  Row r (group indices
-    // 64 r .. 64 r + 63, one wave's load): s_rc[r] = pieces starting inside
-    // the row | (piece of index 64 r << 16); s_rd0[r] = that piece's key
-    // offset (key position of group index e: segment start + offset + e);
-    // s_rd1[r] = for a piece starting inside the row, its offset + PBIAS
-    // (24 bits) | (its first lane << 24).
+    // 64 r .. 64 r + 63, the keys of item r / BK_WAVES of wave r % BK_WAVES)
+    // has one record, read by the wave at one address: x = key offset of the
+    // piece holding index 64 r (key position of group index e: segment start
+    // + offset + e), y = that of a piece starting inside the row, z = that
+    // piece's first lane (WAVE if none), w = pieces starting inside the row
+    // | (piece of index 64 r << 16).
     constexpr int ROWS = (CAP + WAVE - 1) / WAVE;
-    constexpr uint32_t PBIAS = 1u << 14;  // > any group index: biased offsets are positive
+    static_assert(ROWS == ITEMS * BK_WAVES, "one row per item and wave");
     __shared__ uint16_t s_pc[BK_TILES_MAX], s_lo[BK_TILES_MAX];
-    __shared__ uint32_t s_rc[ROWS], s_rd0[ROWS], s_rd1[ROWS];
+    __shared__ uint4 s_row[ROWS];
     static_assert(BK_TILES_MAX <= 2 * WAVE, "two pieces per lane of wave 0");
 
     K *const s_ex = s_exs + 1;
@@ -278,8 +279,10 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             o[q] = p < np ? (uint32_t)s_lo[p] : 0u;
         }
         uint32_t run = wave_inclusive_sum(v[0] + v[1]) - v[0] - v[1];
-        for (uint32_t r = ln; r < (uint32_t)ROWS; r += WAVE)
-            s_rc[r] = 0;
+        for (uint32_t r = ln; r < (uint32_t)ROWS; r += WAVE) {
+            s_row[r].z = WAVE;
+            s_row[r].w = 0;
+        }
 #pragma unroll
         for (int q = 0; q < 2; q++) {
             const uint32_t p = 2 * ln + (uint32_t)q;
@@ -288,12 +291,14 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                 if (v[q]) {
                     const uint32_t dl = p * tile_keys + o[q] - run;
                     if (run & (WAVE - 1)) {
-                        atomicAdd(&s_rc[run / WAVE], 1u);
-                        s_rd1[run / WAVE] = ((dl + PBIAS) & 0xFFFFFFu) | ((run & (WAVE - 1)) << 24);
+                        const uint32_t r = run / WAVE;
+                        atomicAdd(&s_row[r].w, 1u);
+                        s_row[r].y = dl;
+                        s_row[r].z = run & (WAVE - 1);
                     }
                     for (uint32_t r = (run + WAVE - 1) / WAVE; r * WAVE < run + v[q]; r++) {
-                        s_rd0[r] = dl;
-                        atomicOr(&s_rc[r], p << 16);
+                        s_row[r].x = dl;
+                        atomicOr(&s_row[r].w, p << 16);
                     }
                 }
             }
@@ -304,21 +309,20 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         const uint32_t np = gp.y, ln = (uint32_t)t % WAVE;
         uint32_t dl[ITEMS];
         uint32_t many = 0;  // bit i: two or more pieces start inside item i's row
+        const uint32_t wv = (uint32_t)t / WAVE;
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             const uint32_t e = (uint32_t)i * BK_THREADS + (uint32_t)t;
-            const uint32_t r = min(e, n - 1) / WAVE;
-            const uint32_t rc = s_rc[r], d0 = s_rd0[r], d1 = s_rd1[r];
-            const uint32_t cnt = rc & 0xFFFFu;
-            dl[i] = (cnt == 1 && ln >= (d1 >> 24)) ? (d1 & 0xFFFFFFu) - PBIAS : d0;
-            many |= (uint32_t)(e < n && cnt > 1) << i;
+            const uint4 rec = s_row[(uint32_t)i * BK_WAVES + wv];  // the row of e
+            dl[i] = ln >= rec.z ? rec.y : rec.x;
+            many |= (uint32_t)(e < n && (rec.w & 0xFFFFu) > 1) << i;
         }
         if (many) {
 #pragma unroll
             for (int i = 0; i < ITEMS; i++) {
                 if ((many >> i) & 1u) {
                     const uint32_t e = (uint32_t)i * BK_THREADS + (uint32_t)t;
-                    uint32_t p = s_rc[e / WAVE] >> 16;
+                    uint32_t p = s_row[e / WAVE].w >> 16;
                     while (p + 1 < np && (uint32_t)s_pc[p + 1] <= e)
                         p++;
                     dl[i] = p * tile_keys + s_lo[p] - s_pc[p];
@@ -539,14 +543,28 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             s_mix[tid] = 0;
         __syncthreads();
         uint32_t rd[ITEMS];  // MSD pass: (rank << 12) | bin; LSD passes: (rank << 9) | digit
+        // four items at a time: their counter updates are issued before any
+        // of their results is used
 #pragma unroll
-        for (int i = 0; i < ITEMS; i++) {
-            rd[i] = 0;
-            if (i < n_items && ((sv >> i) & 1u)) {
-                const uint32_t d = vdigit(key[i], mshift, MB, vbase);
-                const uint32_t sh = (d & 1u) * 16u;
-                const uint32_t old = atomicAdd(&s_c32[d >> 1], 1u << sh);
-                rd[i] = (((old >> sh) & 0xFFFFu) << BK_MSD_BITS) | d;
+        for (int i0 = 0; i0 < ITEMS; i0 += 4) {
+            uint32_t old[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int i = i0 + j;
+                if (i < ITEMS) {
+                    rd[i] = 0;
+                    old[j] = 0;
+                    if (i < n_items && ((sv >> i) & 1u)) {
+                        rd[i] = vdigit(key[i], mshift, MB, vbase);
+                        old[j] = atomicAdd(&s_c32[rd[i] >> 1], 1u << ((rd[i] & 1u) * 16u));
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int i = i0 + j;
+                if (i < ITEMS)
+                    rd[i] |= ((old[j] >> ((rd[i] & 1u) * 16u)) & 0xFFFFu) << BK_MSD_BITS;
             }
         }
         __syncthreads();
@@ -563,12 +581,24 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             reinterpret_cast<uint4 *>(s_c32)[tid] = w;
         }
         __syncthreads();
+        // four items at a time: their bin starts are read before any key is
+        // written (rd is 0 for items that hold no survivor: bin 0, in bounds)
 #pragma unroll
-        for (int i = 0; i < ITEMS; i++) {
-            if (i < n_items && ((sv >> i) & 1u)) {
-                const uint32_t d = rd[i] & (BK_MSD_BINS - 1);
-                const uint32_t st = (s_c32[d >> 1] >> ((d & 1u) * 16u)) & 0xFFFFu;
-                s_ex[st + (rd[i] >> BK_MSD_BITS)] = key[i];
+        for (int i0 = 0; i0 < ITEMS; i0 += 4) {
+            if (i0 < n_items) {
+                uint32_t w[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    if (i0 + j < ITEMS)
+                        w[j] = s_c32[(rd[i0 + j] & (BK_MSD_BINS - 1)) >> 1];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int i = i0 + j;
+                    if (i < ITEMS && ((sv >> i) & 1u)) {
+                        const uint32_t st = (w[j] >> ((rd[i] & 1u) * 16u)) & 0xFFFFu;
+                        s_ex[st + (rd[i] >> BK_MSD_BITS)] = key[i];
+                    }
+                }
             }
         }
         __syncthreads();
@@ -893,7 +923,10 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         // the head of a tail is the last head at or before it, found from the
         // head ballots of this wave (and, for the first run of a wave, the
         // last head of the waves before).
-        const int n_it = (int)((n_surv + BK_THREADS - 1) / BK_THREADS);
+        // (n_it equals n_ch; passed through an empty asm so that the compiler
+        // does not keep the detection loop's per-item masks alive until here)
+        int n_it = (int)((n_surv + BK_THREADS - 1) / BK_THREADS);
+        asm volatile("" : "+s"(n_it));
         if (tid == 0) {
             s_ex[-1] = sentinel<K>();
             s_ex[n_surv] = sentinel<K>();
@@ -902,23 +935,36 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         uint32_t rh = 0, rt = 0;  // bit i: item i is a run head / a run tail
         uint32_t last = 0;        // 1 + position of this wave's last head (0: none)
         uint32_t nh = 0;          // heads (runs) in this wave, wave-uniform
+        // items in pairs, each pair's reads issued together; positions past
+        // n_surv read in-bounds slots (below CAP + 1) and count as nothing
 #pragma unroll
-        for (int i = 0; i < ITEMS; i++) {
-            if (i < n_it) {
-                const uint32_t base = (uint32_t)(wave * n_it + i) * WAVE;
-                const uint32_t e = base + lane;
-                bool h = false, t = false;
-                if (e < n_surv) {
-                    const K x = s_ex[e];
-                    h = s_ex[(int)e - 1] != x;
-                    t = s_ex[e + 1] != x;
+        for (int i0 = 0; i0 < ITEMS; i0 += 2) {
+            if (i0 < n_it) {
+                K x[2], y[2], z[2];
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    const uint32_t e = (uint32_t)(wave * n_it + i0 + j) * WAVE + lane;
+                    if (i0 + j < ITEMS) {
+                        x[j] = s_ex[e];
+                        y[j] = s_ex[(int)e - 1];
+                        z[j] = s_ex[e + 1];
+                    }
                 }
-                rh |= (uint32_t)h << i;
-                rt |= (uint32_t)t << i;
-                const uint64_t hb = __ballot(h);
-                nh += wave_count(hb);
-                if (hb)
-                    last = base + 64u - (uint32_t)__clzll(hb);
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    const int i = i0 + j;
+                    if (i < ITEMS) {
+                        const uint32_t base = (uint32_t)(wave * n_it + i) * WAVE;
+                        const bool in = i < n_it && base + lane < n_surv;
+                        const bool h = in && y[j] != x[j], t = in && z[j] != x[j];
+                        rh |= (uint32_t)h << i;
+                        rt |= (uint32_t)t << i;
+                        const uint64_t hb = __ballot(h);
+                        nh += wave_count(hb);
+                        if (hb)
+                            last = base + 64u - (uint32_t)__clzll(hb);
+                    }
+                }
             }
         }
         if (lane == 0)
