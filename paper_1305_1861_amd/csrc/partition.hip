@@ -284,9 +284,9 @@ __global__ __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
     constexpr int PER_WORD = 32 / ITEMS;      // threads per packed word
     constexpr int WORDS = TILE / 32;
     constexpr int BACK = std::is_same<K, Key2>::value ? 2 : 1;  // words before the tile a key may reach into
-    constexpr uint32_t SPARE = PT_MAX_BINS;   // counter of the windows that are not kept
+    constexpr uint32_t SPARE = PT_MAX_BINS;   // rank record of a window that is not kept
     static_assert(TILE <= 65536, "positions are 16 bits");
-    __shared__ uint32_t s_cnt[PT_MAX_BINS + 1];   // digit counts of the tile
+    __shared__ uint32_t s_cnt[PT_MAX_BINS];       // digit counts of the tile
     __shared__ uint32_t s_start[PT_MAX_BINS];     // first slot of every digit
     __shared__ uint32_t s_base[PT_MAX_BINS];      // output position minus slot, per digit
     __shared__ uint32_t s_wt[PT_WAVES];
@@ -309,8 +309,6 @@ __global__ __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
     // thread t owns digit t: its write position stays in a register
     uint32_t cur = (uint32_t)tid < bins ? offs[ch.hidx + (uint64_t)tid * ch.hstride] : 0u;
     s_cnt[tid] = 0;
-    if (tid == 0)
-        s_cnt[SPARE] = 0;
     __syncthreads();
     uint32_t par = 0;
     for (uint64_t t0 = ch.c0; t0 < ch.c1; t0 += pt_tile<K>(), par ^= 1u) {
@@ -333,14 +331,16 @@ __global__ __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
                     words[0] = r.w2;
             }
         }
-        // digits, ranked; windows not kept count in the spare bin so that
-        // the atomics issue without a branch per item
+        // digits, ranked; a window that is not kept (not valid, or outside
+        // a shard's digits) takes no counter: one shared spare counter
+        // would serialise the atomics of every such window of a wave
         const uint32_t ok = r.okmask ? (r.vword >> first) & r.okmask : 0u;
         uint32_t rd[ITEMS];  // (rank << 11) | digit (SPARE: not kept)
         auto rank = [&](int i, uint32_t dg) __attribute__((always_inline)) {
             const bool keep = ((ok >> i) & 1u) && dg >= own_lo && dg < own_hi;
-            const uint32_t d = keep ? dg : SPARE;
-            rd[i] = (atomicAdd(&s_cnt[d], 1u) << (PT_MAX_BITS + 1)) | d;
+            rd[i] = SPARE;
+            if (keep)
+                rd[i] = (atomicAdd(&s_cnt[dg], 1u) << (PT_MAX_BITS + 1)) | dg;
         };
         if (ch.k >= 5) {
             // the canonical key's top 10 bits are the smaller of the forward
@@ -371,8 +371,6 @@ __global__ __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
         if (lane == WAVE - 1)
             s_wt[wave] = inc;
         s_cnt[tid] = 0;  // read by its owner only until the next tile's atomics
-        if (tid == 0)
-            s_cnt[SPARE] = 0;
         __syncthreads();
         uint32_t before = 0, n_tile = 0;
 #pragma unroll
