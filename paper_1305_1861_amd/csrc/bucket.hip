@@ -194,7 +194,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     static_assert(ROWS == ITEMS * BK_WAVES, "one row per item and wave");
     __shared__ uint16_t s_pc[BK_TILES_MAX], s_lo[BK_TILES_MAX];
     __shared__ uint4 s_row[ROWS];
-    static_assert(BK_TILES_MAX <= 2 * WAVE, "two pieces per lane of wave 0");
+    constexpr int PPL = BK_TILES_MAX / WAVE;  // pieces per lane of wave 0
+    static_assert(PPL * WAVE == BK_TILES_MAX, "pieces spread evenly over wave 0");
 
     K *const s_ex = s_exs + 1;
     uint64_t *s_filter = reinterpret_cast<uint64_t *>(s_exs);
@@ -270,22 +271,23 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         }
     };
     auto piece_index = [&](const uint4 &gp, uint32_t ln) __attribute__((always_inline)) {  // wave 0
-        const uint32_t np = gp.y;  // <= BK_TILES_MAX = 2 * WAVE
-        uint32_t v[2], o[2];
+        const uint32_t np = gp.y;  // <= BK_TILES_MAX = PPL * WAVE
+        uint32_t v[PPL], o[PPL], vs = 0;
 #pragma unroll
-        for (int q = 0; q < 2; q++) {
-            const uint32_t p = 2 * ln + (uint32_t)q;
+        for (int q = 0; q < PPL; q++) {
+            const uint32_t p = PPL * ln + (uint32_t)q;
             v[q] = p < np ? (uint32_t)s_pc[p] : 0u;
             o[q] = p < np ? (uint32_t)s_lo[p] : 0u;
+            vs += v[q];
         }
-        uint32_t run = wave_inclusive_sum(v[0] + v[1]) - v[0] - v[1];
+        uint32_t run = wave_inclusive_sum(vs) - vs;
         for (uint32_t r = ln; r < (uint32_t)ROWS; r += WAVE) {
             s_row[r].z = WAVE;
             s_row[r].w = 0;
         }
 #pragma unroll
-        for (int q = 0; q < 2; q++) {
-            const uint32_t p = 2 * ln + (uint32_t)q;
+        for (int q = 0; q < PPL; q++) {
+            const uint32_t p = PPL * ln + (uint32_t)q;
             if (p < np) {
                 s_pc[p] = (uint16_t)run;
                 if (v[q]) {

@@ -156,7 +156,7 @@ struct BucketArgs {
 };
 int bucket_grid();
 constexpr uint32_t BK_CHUNK_MAX = 32;  // bucket ids per chunk of the bucket kernel's schedule
-constexpr uint32_t BK_TILES_MAX = 128;  // tiles a group of a tiled library may span
+constexpr uint32_t BK_TILES_MAX = 256;  // tiles a group of a tiled library may span
 int bucket_capacity(int key_words, int tile);
 hipError_t launch_bucket(const BucketArgs &a, int key_words, int grid, hipStream_t stream);
 // Oversized buckets (more keys than a workgroup holds) of one library, in
