@@ -194,8 +194,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     static_assert(ROWS == ITEMS * BK_WAVES, "one row per item and wave");
     __shared__ uint16_t s_pc[BK_TILES_MAX], s_lo[BK_TILES_MAX];
     __shared__ uint4 s_row[ROWS];
-    constexpr int PPL = BK_TILES_MAX / WAVE;  // pieces per lane of wave 0
-    static_assert(PPL * WAVE == BK_TILES_MAX, "pieces spread evenly over wave 0");
+    constexpr int PPL = BK_TILES_MAX / WAVE;  // rounds of pieces of wave 0
+    static_assert(PPL * WAVE == BK_TILES_MAX, "whole rounds of pieces");
 
     K *const s_ex = s_exs + 1;
     uint64_t *s_filter = reinterpret_cast<uint64_t *>(s_exs);
@@ -272,39 +272,39 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     };
     auto piece_index = [&](const uint4 &gp, uint32_t ln) __attribute__((always_inline)) {  // wave 0
         const uint32_t np = gp.y;  // <= BK_TILES_MAX = PPL * WAVE
-        uint32_t v[PPL], o[PPL], vs = 0;
-#pragma unroll
-        for (int q = 0; q < PPL; q++) {
-            const uint32_t p = PPL * ln + (uint32_t)q;
-            v[q] = p < np ? (uint32_t)s_pc[p] : 0u;
-            o[q] = p < np ? (uint32_t)s_lo[p] : 0u;
-            vs += v[q];
-        }
-        uint32_t run = wave_inclusive_sum(vs) - vs;
         for (uint32_t r = ln; r < (uint32_t)ROWS; r += WAVE) {
             s_row[r].z = WAVE;
             s_row[r].w = 0;
         }
+        // piece p on lane p % WAVE, in rounds of WAVE pieces (one round for
+        // most groups); run: the group index of the piece's first key
+        uint32_t base = 0;
 #pragma unroll
         for (int q = 0; q < PPL; q++) {
-            const uint32_t p = PPL * ln + (uint32_t)q;
-            if (p < np) {
-                s_pc[p] = (uint16_t)run;
-                if (v[q]) {
-                    const uint32_t dl = p * tile_keys + o[q] - run;
-                    if (run & (WAVE - 1)) {
-                        const uint32_t r = run / WAVE;
-                        atomicAdd(&s_row[r].w, 1u);
-                        s_row[r].y = dl;
-                        s_row[r].z = run & (WAVE - 1);
-                    }
-                    for (uint32_t r = (run + WAVE - 1) / WAVE; r * WAVE < run + v[q]; r++) {
-                        s_row[r].x = dl;
-                        atomicOr(&s_row[r].w, p << 16);
+            if ((uint32_t)q * WAVE < np) {
+                const uint32_t p = (uint32_t)q * WAVE + ln;
+                const uint32_t v = p < np ? (uint32_t)s_pc[p] : 0u;
+                const uint32_t o = p < np ? (uint32_t)s_lo[p] : 0u;
+                const uint32_t inc = wave_inclusive_sum(v);
+                const uint32_t run = base + inc - v;
+                base += (uint32_t)__shfl(inc, WAVE - 1);
+                if (p < np) {
+                    s_pc[p] = (uint16_t)run;
+                    if (v) {
+                        const uint32_t dl = p * tile_keys + o - run;
+                        if (run & (WAVE - 1)) {
+                            const uint32_t r = run / WAVE;
+                            atomicAdd(&s_row[r].w, 1u);
+                            s_row[r].y = dl;
+                            s_row[r].z = run & (WAVE - 1);
+                        }
+                        for (uint32_t r = (run + WAVE - 1) / WAVE; r * WAVE < run + v; r++) {
+                            s_row[r].x = dl;
+                            atomicOr(&s_row[r].w, p << 16);
+                        }
                     }
                 }
             }
-            run += v[q];
         }
     };
     auto piece_load = [&](const uint4 &gp, uint32_t n, int t) __attribute__((always_inline)) {
