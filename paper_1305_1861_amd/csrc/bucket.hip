@@ -665,90 +665,155 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             if (tid == 0)
                 s_u[2] = 0;
             __syncthreads();
+            // A wave takes two list entries at a time.  Those of at most a
+            // wave's keys are ranked side by side, one key per lane each:
+            // their ranking steps are independent and issued together, so
+            // that one bin's waits overlap the other's work (more bins in
+            // flight measured slower).  A larger bin goes through the
+            // general ranking below.
+            constexpr int NB = 2;
             for (;;) {
                 uint32_t idx = 0;
                 if (lane == 0)
-                    idx = atomicAdd(&s_u[2], 1u);
+                    idx = atomicAdd(&s_u[2], (uint32_t)NB);
                 idx = __builtin_amdgcn_readfirstlane(idx);
                 if (idx >= n_mb)
                     break;
-                const uint32_t ent = s_list[idx];
-                const uint32_t st = ent & 0xFFFFu, m = ent >> 16;
-                constexpr int Q = BK_RANK_MAX / WAVE;
-                const int nq = (int)((m + WAVE - 1) / WAVE);
-                K x[Q];
-                uint32_t rk[Q];
-                uint32_t pend = 0;  // bit q: key q of this lane has no place yet
+                uint32_t es[NB], sm = 0;  // entries (0: none); bit b: entry b is small
 #pragma unroll
-                for (int q = 0; q < Q; q++) {
-                    rk[q] = 0;
-                    x[q] = sentinel<K>();
-                    if ((uint32_t)(q * WAVE) + lane < m) {
-                        x[q] = s_ex[st + q * WAVE + lane];
-                        pend |= 1u << q;
+                for (int b = 0; b < NB; b++) {
+                    es[b] = idx + b < n_mb ? __builtin_amdgcn_readfirstlane(s_list[idx + b]) : 0u;
+                    sm |= (uint32_t)(es[b] != 0 && (es[b] >> 16) <= WAVE) << b;
+                }
+                if (sm) {
+                    K xs[NB];
+                    bool ps[NB];  // the lane's key has no place yet
+                    uint32_t rs[NB], sts[NB], ms[NB], caps[NB];
+#pragma unroll
+                    for (int b = 0; b < NB; b++) {
+                        sts[b] = es[b] & 0xFFFFu;
+                        ms[b] = ((sm >> b) & 1u) ? es[b] >> 16 : 0u;
+                        caps[b] = 8u + ms[b] / 16u;
+                        xs[b] = lane < ms[b] ? s_ex[sts[b] + lane] : sentinel<K>();
+                        ps[b] = lane < ms[b];
+                        rs[b] = 0;
+                    }
+                    // one distinct value of each bin per step (a bin with
+                    // no pending key, or past its cap, takes part idly)
+                    for (uint32_t it = 0;; it++) {
+                        uint64_t bs[NB], any = 0;
+#pragma unroll
+                        for (int b = 0; b < NB; b++) {
+                            bs[b] = __ballot(ps[b] && it < caps[b]);
+                            any |= bs[b];
+                        }
+                        if (!any)
+                            break;
+#pragma unroll
+                        for (int b = 0; b < NB; b++) {
+                            const K v = read_lane(xs[b], bs[b] ? (int)__builtin_ctzll(bs[b]) : 0);
+                            const uint32_t less = (uint32_t)__popcll(__ballot(xs[b] < v));
+                            const bool eq = ps[b] && bs[b] && xs[b] == v;
+                            const uint64_t qb = __ballot(eq);
+                            rs[b] = eq ? less + (uint32_t)__popcll(qb & lt) : rs[b];
+                            ps[b] = ps[b] && !eq;
+                        }
+                    }
+#pragma unroll
+                    for (int b = 0; b < NB; b++) {
+                        // past its cap, a bin's remaining keys scan the bin
+                        if (__ballot(ps[b])) {
+                            for (uint32_t j = 0; j < ms[b]; j++) {
+                                const K y = s_ex[sts[b] + j];
+                                if (ps[b])
+                                    rs[b] += (y < xs[b] || (y == xs[b] && j < lane)) ? 1u : 0u;
+                            }
+                        }
+                        if (lane < ms[b])
+                            s_ex[sts[b] + rs[b]] = xs[b];
                     }
                 }
-                const uint32_t cap = 8u + m / 16u;  // distinct values taken before switching
-                for (uint32_t it = 0;; it++) {
-                    int q0 = -1;
-                    uint64_t b0 = 0;
+                for (int b = 0; b < NB; b++) {
+                    const uint32_t ent = es[b];
+                    if (ent == 0 || ((sm >> b) & 1u))
+                        continue;
+                    const uint32_t st = ent & 0xFFFFu, m = ent >> 16;
+                    constexpr int Q = BK_RANK_MAX / WAVE;
+                    const int nq = (int)((m + WAVE - 1) / WAVE);
+                    K x[Q];
+                    uint32_t rk[Q];
+                    uint32_t pend = 0;  // bit q: key q of this lane has no place yet
 #pragma unroll
                     for (int q = 0; q < Q; q++) {
-                        if (q < nq) {
-                            const uint64_t b = __ballot((pend >> q) & 1u);
-                            if (q0 < 0 && b) {
-                                q0 = q;
-                                b0 = b;
+                        rk[q] = 0;
+                        x[q] = sentinel<K>();
+                        if ((uint32_t)(q * WAVE) + lane < m) {
+                            x[q] = s_ex[st + q * WAVE + lane];
+                            pend |= 1u << q;
+                        }
+                    }
+                    const uint32_t cap = 8u + m / 16u;  // distinct values taken before switching
+                    for (uint32_t it = 0;; it++) {
+                        int q0 = -1;
+                        uint64_t b0 = 0;
+#pragma unroll
+                        for (int q = 0; q < Q; q++) {
+                            if (q < nq) {
+                                const uint64_t b = __ballot((pend >> q) & 1u);
+                                if (q0 < 0 && b) {
+                                    q0 = q;
+                                    b0 = b;
+                                }
+                            }
+                        }
+                        if (q0 < 0 || it == cap)
+                            break;
+                        const int l0 = (int)__builtin_ctzll(b0);
+                        K v = sentinel<K>();
+#pragma unroll
+                        for (int q = 0; q < Q; q++)
+                            if (q == q0)
+                                v = read_lane(x[q], l0);
+                        uint32_t less = 0;
+#pragma unroll
+                        for (int q = 0; q < Q; q++)
+                            if (q < nq)
+                                less += (uint32_t)__popcll(__ballot(x[q] < v));  // invalid slots hold the sentinel
+#pragma unroll
+                        for (int q = 0; q < Q; q++) {
+                            if (q < nq) {
+                                const bool eq = ((pend >> q) & 1u) && x[q] == v;
+                                const uint64_t b = __ballot(eq);
+                                if (eq) {
+                                    rk[q] = less + (uint32_t)__popcll(b & lt);
+                                    pend &= ~(1u << q);
+                                }
+                                less += (uint32_t)__popcll(b);
                             }
                         }
                     }
-                    if (q0 < 0 || it == cap)
-                        break;
-                    const int l0 = (int)__builtin_ctzll(b0);
-                    K v = sentinel<K>();
+                    if (__ballot(pend != 0)) {
+                        // remaining keys: scan the whole bin (four keys per step)
+                        for (uint32_t j0 = 0; j0 < m; j0 += 4) {
+                            K y[4];
 #pragma unroll
-                    for (int q = 0; q < Q; q++)
-                        if (q == q0)
-                            v = read_lane(x[q], l0);
-                    uint32_t less = 0;
+                            for (int u = 0; u < 4; u++)
+                                y[u] = j0 + u < m ? s_ex[st + j0 + u] : sentinel<K>();
 #pragma unroll
-                    for (int q = 0; q < Q; q++)
-                        if (q < nq)
-                            less += (uint32_t)__popcll(__ballot(x[q] < v));  // invalid slots hold the sentinel
+                            for (int u = 0; u < 4; u++) {
+                                const uint32_t j = j0 + u;
 #pragma unroll
-                    for (int q = 0; q < Q; q++) {
-                        if (q < nq) {
-                            const bool eq = ((pend >> q) & 1u) && x[q] == v;
-                            const uint64_t b = __ballot(eq);
-                            if (eq) {
-                                rk[q] = less + (uint32_t)__popcll(b & lt);
-                                pend &= ~(1u << q);
+                                for (int q = 0; q < Q; q++)
+                                    if (q < nq && ((pend >> q) & 1u))
+                                        rk[q] += (y[u] < x[q] || (y[u] == x[q] && j < (uint32_t)(q * WAVE) + lane)) ? 1u : 0u;
                             }
-                            less += (uint32_t)__popcll(b);
                         }
                     }
+#pragma unroll
+                    for (int q = 0; q < Q; q++)
+                        if ((uint32_t)(q * WAVE) + lane < m)
+                            s_ex[st + rk[q]] = x[q];
                 }
-                if (__ballot(pend != 0)) {
-                    // remaining keys: scan the whole bin (four keys per step)
-                    for (uint32_t j0 = 0; j0 < m; j0 += 4) {
-                        K y[4];
-#pragma unroll
-                        for (int u = 0; u < 4; u++)
-                            y[u] = j0 + u < m ? s_ex[st + j0 + u] : sentinel<K>();
-#pragma unroll
-                        for (int u = 0; u < 4; u++) {
-                            const uint32_t j = j0 + u;
-#pragma unroll
-                            for (int q = 0; q < Q; q++)
-                                if (q < nq && ((pend >> q) & 1u))
-                                    rk[q] += (y[u] < x[q] || (y[u] == x[q] && j < (uint32_t)(q * WAVE) + lane)) ? 1u : 0u;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < Q; q++)
-                    if ((uint32_t)(q * WAVE) + lane < m)
-                        s_ex[st + rk[q]] = x[q];
             }
             __syncthreads();
             n_sort = 0;

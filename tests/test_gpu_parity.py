@@ -423,6 +423,44 @@ def test_segment_with_more_tiles_than_a_group_spans(tk, oracle_lib, k, over):
     assert r.n_fallback >= 2 if over else r.n_fallback == 1, r.n_fallback
 
 
+def _bin_reads(rng, k, prefix, n_distinct, copies):
+    """Reads of exactly k bases (one window each): n_distinct k-mers that
+    start with ``prefix`` and end in A (so the forward strand is the
+    canonical one and the key keeps the prefix), each repeated ``copies``
+    times."""
+    out = []
+    for _ in range(n_distinct):
+        mid = "".join("ACGT"[x] for x in rng.integers(0, 4, k - len(prefix) - 1))
+        out += [prefix + mid + "A"] * copies
+    return out
+
+
+@pytest.mark.parametrize("k", [31, 63])
+def test_mixed_bins_past_the_rank_cap(tk, oracle_lib, k):
+    """Mixed bins of every ordering path.  With one bucket (part_bits 0) the
+    sort's first pass bins keys by their first six bases, so each prefix
+    below is one bin.  The bins are taken two at a time in key order:
+    (small, large) then (small, small).  The small bins, ranked side by
+    side, and the large one, ranked alone, all hold more distinct values
+    than the value-at-a-time ranking takes before it scans the bin (8 +
+    keys / 16), except the last.  A separate library has one bin of more
+    than 256 keys, which sends its group through the radix passes."""
+    rng = np.random.default_rng(1303 + k)
+    reads = (_bin_reads(rng, k, "AAAAAC", 20, 2)     # 40 keys, 20 values: small, past the cap
+             + _bin_reads(rng, k, "AAAAAG", 40, 3)   # 120 keys, 40 values: large, past the cap
+             + _bin_reads(rng, k, "AAAACA", 12, 3)   # 36 keys, 12 values: small, past the cap
+             + _bin_reads(rng, k, "AAAACC", 5, 8))   # 40 keys, 5 values: small, within the cap
+    rng.shuffle(reads)
+    bases, offsets = readsim.from_strings(reads)
+    case(f"mixed bins k={k} windows={len(reads)}")
+    check_against_oracle(tk, oracle_lib, bases, offsets, k, 2, opts=dict(part_bits=0))
+    reads = _bin_reads(rng, k, "AAAAGA", 150, 2) + _bin_reads(rng, k, "AAAAGC", 10, 4)
+    rng.shuffle(reads)
+    bases, offsets = readsim.from_strings(reads)
+    case(f"mixed bin over 256 keys k={k} windows={len(reads)}")
+    check_against_oracle(tk, oracle_lib, bases, offsets, k, 2, opts=dict(part_bits=0))
+
+
 def test_bucket_capacity_edges(tk, oracle_lib):
     """One bucket (part_bits 0) of exactly the register capacity, one less
     and one more: 512 threads x 14 one-word keys = 7168, x 7 two-word keys =
