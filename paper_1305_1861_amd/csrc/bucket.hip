@@ -150,6 +150,59 @@ __device__ __forceinline__ Key2 shift_up_lane(const Key2 &x) { return Key2{shift
 // Number of lanes whose flag is set in a ballot.
 __device__ __forceinline__ uint32_t wave_count(uint64_t ball) { return (uint32_t)__popcll(ball); }
 
+// Orders NB bins of at most WAVE keys each side by side, run by one wave,
+// one key per lane and bin: bin b's keys s_ex[st[b], st[b] + m[b]) (m[b] =
+// 0: no bin).  A key's place in its bin is the number of smaller keys plus
+// the number of equal keys before it.  Each step takes one pending distinct
+// value of every bin; the bins' steps are independent, so one bin's waits
+// overlap the others' work.  Past 8 + m / 16 values, a bin's remaining keys
+// scan the bin instead.
+template <typename K, int NB>
+__device__ __forceinline__ void rank_bins(K *s_ex, const uint32_t (&st)[NB], const uint32_t (&m)[NB], uint32_t lane,
+                                          uint64_t lt) {
+    K x[NB];
+    uint32_t rk[NB], cap[NB];
+    bool pend[NB];  // the lane's key has no place yet
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        cap[b] = 8u + m[b] / 16u;
+        rk[b] = 0;
+        pend[b] = lane < m[b];
+        x[b] = pend[b] ? s_ex[st[b] + lane] : sentinel<K>();
+    }
+    for (uint32_t it = 0;; it++) {
+        uint64_t first[NB], any = 0;  // lanes with a pending key
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            first[b] = __ballot(it < cap[b] && pend[b]);
+            any |= first[b];
+        }
+        if (!any)
+            break;
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            const K v = read_lane(x[b], first[b] ? (int)__builtin_ctzll(first[b]) : 0);
+            const uint32_t less = (uint32_t)__popcll(__ballot(x[b] < v));  // empty lanes hold the sentinel
+            const bool eq = first[b] && pend[b] && x[b] == v;
+            const uint64_t qb = __ballot(eq);
+            rk[b] = eq ? less + (uint32_t)__popcll(qb & lt) : rk[b];
+            pend[b] = pend[b] && !eq;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        if (__ballot(pend[b])) {
+            for (uint32_t j = 0; j < m[b]; j++) {
+                const K y = s_ex[st[b] + j];
+                if (pend[b])
+                    rk[b] += (y < x[b] || (y == x[b] && j < lane)) ? 1u : 0u;
+            }
+        }
+        if (lane < m[b])
+            s_ex[st[b] + rk[b]] = x[b];
+    }
+}
+
 // TBITS: log2 of the pattern table entries when fixed at compile time (the
 // default table: the pattern fields of the hash become constant shifts), or
 // 0 to take it from the arguments.
@@ -686,52 +739,13 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                     sm |= (uint32_t)(es[b] != 0 && (es[b] >> 16) <= WAVE) << b;
                 }
                 if (sm) {
-                    K xs[NB];
-                    bool ps[NB];  // the lane's key has no place yet
-                    uint32_t rs[NB], sts[NB], ms[NB], caps[NB];
+                    uint32_t sts[NB], ms[NB];
 #pragma unroll
                     for (int b = 0; b < NB; b++) {
                         sts[b] = es[b] & 0xFFFFu;
                         ms[b] = ((sm >> b) & 1u) ? es[b] >> 16 : 0u;
-                        caps[b] = 8u + ms[b] / 16u;
-                        xs[b] = lane < ms[b] ? s_ex[sts[b] + lane] : sentinel<K>();
-                        ps[b] = lane < ms[b];
-                        rs[b] = 0;
                     }
-                    // one distinct value of each bin per step (a bin with
-                    // no pending key, or past its cap, takes part idly)
-                    for (uint32_t it = 0;; it++) {
-                        uint64_t bs[NB], any = 0;
-#pragma unroll
-                        for (int b = 0; b < NB; b++) {
-                            bs[b] = __ballot(ps[b] && it < caps[b]);
-                            any |= bs[b];
-                        }
-                        if (!any)
-                            break;
-#pragma unroll
-                        for (int b = 0; b < NB; b++) {
-                            const K v = read_lane(xs[b], bs[b] ? (int)__builtin_ctzll(bs[b]) : 0);
-                            const uint32_t less = (uint32_t)__popcll(__ballot(xs[b] < v));
-                            const bool eq = ps[b] && bs[b] && xs[b] == v;
-                            const uint64_t qb = __ballot(eq);
-                            rs[b] = eq ? less + (uint32_t)__popcll(qb & lt) : rs[b];
-                            ps[b] = ps[b] && !eq;
-                        }
-                    }
-#pragma unroll
-                    for (int b = 0; b < NB; b++) {
-                        // past its cap, a bin's remaining keys scan the bin
-                        if (__ballot(ps[b])) {
-                            for (uint32_t j = 0; j < ms[b]; j++) {
-                                const K y = s_ex[sts[b] + j];
-                                if (ps[b])
-                                    rs[b] += (y < xs[b] || (y == xs[b] && j < lane)) ? 1u : 0u;
-                            }
-                        }
-                        if (lane < ms[b])
-                            s_ex[sts[b] + rs[b]] = xs[b];
-                    }
+                    rank_bins<K, NB>(s_ex, sts, ms, lane, lt);
                 }
                 for (int b = 0; b < NB; b++) {
                     const uint32_t ent = es[b];
