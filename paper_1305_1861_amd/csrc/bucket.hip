@@ -16,8 +16,9 @@
 //            in the screen for the windows that found them all set);
 //   sort   : one MSD pass on the top bits of (bucket - first bucket, key
 //            bits below the bucket digit) into 4096 bins, then the bins that
-//            hold different keys ordered one wave per bin (LSD passes only
-//            for groups whose bins are too large for that);
+//            hold different keys ranked by waves, two bins of at most 64
+//            keys side by side or a larger bin alone (LSD passes only for
+//            groups whose bins are too large for that);
 //   compact: run-length compaction, threshold c, (key, count) records written
 //            at the group's first window index (gathered into place after).
 //
@@ -583,11 +584,13 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         // (1) one MSD pass on the top MB <= 12 bits of V into 4096 bins
         //     (unordered within a bin: LDS atomics on packed 16-bit counters);
         // (2) a bin whose keys are not all equal is "mixed";
-        // (3) the keys of mixed bins -- a few percent of them, since every
-        //     distinct key recurs about coverage times -- are sorted by an
-        //     LSD radix sort (9-bit digits, stable wave-match ranking) over
-        //     just their positions; if there are too many of them to map,
-        //     the LSD sort runs over the whole group instead.
+        // (3) the keys of mixed bins (a quarter of the survivors on deep
+        //     libraries with repeats: copies and error k-mers share
+        //     prefixes) are ranked within their bins by waves; groups with a
+        //     bin of more than BK_RANK_MAX keys, or too many mixed bins, take
+        //     an LSD radix sort (9-bit digits, stable wave-match ranking)
+        //     over just the mixed bins' positions, or over the whole group
+        //     when there are too many of them to map.
         const int TB = SB + RB;
         const int MB = min(BK_MSD_BITS, TB);
         const int mshift = TB - MB;
