@@ -1062,7 +1062,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                 carry = l - 1;
         }
         uint32_t cnt[ITEMS];
-        uint32_t nk = 0, single = 0, below = 0;  // wave-uniform
+        uint32_t below = 0;  // runs of 2 .. c - 1 keys ending in this wave, wave-uniform
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             cnt[i] = 0;
@@ -1075,11 +1075,16 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                     cnt[i] = base + lane - hp + 1;
                 if (hb)
                     carry = base + 63u - (uint32_t)__clzll(hb);
-                single += wave_count(__ballot(cnt[i] == 1));
-                below += wave_count(__ballot(cnt[i] >= 2 && cnt[i] < c));
-                nk += wave_count(__ballot(cnt[i] >= c));
+                if (c > 2)
+                    below += wave_count(__ballot(cnt[i] >= 2 && cnt[i] < c));
             }
         }
+        // the runs ending in this wave (one per tail), those of one key (a
+        // head and a tail at once) and the kept ones
+        const uint32_t tw = wave_inclusive_sum((uint32_t)__popc(rt) | ((uint32_t)__popc(rh & rt) << 16));
+        const uint32_t tt = (uint32_t)__builtin_amdgcn_readlane((int)tw, WAVE - 1);
+        const uint32_t single = tt >> 16;
+        const uint32_t nk = (tt & 0xFFFFu) - below - (c >= 2 ? single : 0u);
         if (lane == 0)
             s_w[0][wave] = nk;
         __syncthreads();
