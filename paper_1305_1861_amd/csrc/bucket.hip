@@ -492,7 +492,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         }
         __syncthreads();
         const uint32_t blocks_cut = s_fo[R];
-        uint32_t rb[ITEMS];  // bucket of each key, relative to b0
+        uint32_t rb[ITEMS];  // bucket of each key, relative to b0; after the screen its filter block
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {
             rb[i] = 0;
@@ -524,7 +524,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
                 if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb) {
                     const uint32_t f0 = s_fo[rb[i]], nb = (uint32_t)s_fo[rb[i] + 1] - f0;
                     const uint64_t h = key_hash(key[i]);
-                    uint64_t *b = s_filter + f0 + (uint32_t)__umul64hi(h, nb);
+                    rb[i] = f0 + (uint32_t)__umul64hi(h, nb);  // from here on: the key's filter block
+                    uint64_t *b = s_filter + rb[i];
                     // the four pattern words and second-plane words are
                     // read together, then the first-plane atomics of the
                     // words that need them are issued together, so that a
@@ -558,9 +559,8 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
 #pragma unroll
             for (int i = 0; i < ITEMS; i++) {
                 if (i < n_items && (uint32_t)i * BK_THREADS + tid < n_sb && !((sv >> i) & 1u)) {
-                    const uint32_t f0 = s_fo[rb[i]], nb = (uint32_t)s_fo[rb[i] + 1] - f0;
                     const uint64_t h = key_hash(key[i]);
-                    const uint64_t *b = s_filter + f0 + (uint32_t)__umul64hi(h, nb) + 4 * blocks_cut;
+                    const uint64_t *b = s_filter + rb[i] + 4 * blocks_cut;  // the block the screen chose
                     bool all = true;
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
